@@ -1,0 +1,182 @@
+/*
+ * lrcc.h -- C ABI of the MI355X (gfx950) linear-response CCSD library.
+ *
+ * The library computes frequency-dependent dipole polarizabilities with
+ * relativistic (complex, antisymmetrized-spinor) linear-response CCSD,
+ * following Chakraborty, Manna, Crawford, Dutta, "A low-cost four-component
+ * relativistic coupled cluster linear response theory based on perturbation
+ * sensitive natural spinors" (arXiv:2503.23144):
+ *   ground state T and energy           Section II.A, Eqs. 9-10
+ *   CC Jacobian A                       Eq. 30
+ *   Lambda (left) equations             Eqs. 20, 22 (zeroth order)
+ *   right response X(w)                 Eqs. 29, 31
+ *   left response  Y(w)                 Eqs. 32-34
+ *   response function / polarizability  Eq. 35 (alpha = -<<mu_A; mu_B>>)
+ *   FNS++ truncated virtual space       Section II.C, Eqs. 41-50
+ *
+ * Conventions for every call:
+ *   - Complex numbers are interleaved {double re, double im}, row-major,
+ *     C-contiguous.  Orbital index order: the nocc occupied spinors first,
+ *     then the nvir virtual spinors (nmo = nocc + nvir).
+ *   - `where` says where a caller buffer lives: LRCC_HOST or LRCC_DEVICE
+ *     (a device pointer on the context's GPU).  Input buffers are copied
+ *     before the call returns; the caller keeps ownership of everything it
+ *     passes in and may free it afterwards.
+ *   - Amplitude vectors (T, Lambda, X, Y, sigma in/out) hold the unique
+ *     amplitudes: x1[i][a] (nocc*nvir) followed by x2[P(i,j)][P(a,b)] for
+ *     i<j, a<b, with the pair index P(p,q) = q(q-1)/2 + p.  Length
+ *     lrcc_amplitude_length().  Dot products between left and right
+ *     vectors are bilinear (no conjugation) over these unique entries.
+ *   - Return value 0 (LRCC_OK) on success, a negative LRCC_E_* code on
+ *     failure; lrcc_last_error() then holds a message.  No C++ exception
+ *     crosses this interface.  A context is used by one host thread at a
+ *     time.  All device work is ordered on the context's HIP stream; calls
+ *     that return results to host memory synchronize that stream.
+ */
+#ifndef LRCC_H
+#define LRCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRCC_OK 0
+#define LRCC_E_INVALID (-1)   /* null pointer, bad size or option, non-Hermitian input */
+#define LRCC_E_STATE (-2)     /* call out of order (e.g. response before ground state) */
+#define LRCC_E_NOMEM (-3)     /* device allocation failed */
+#define LRCC_E_HIP (-4)       /* HIP runtime error; message has hipGetErrorString */
+#define LRCC_E_NOCONV (-5)    /* iteration limit reached; results and stats still written */
+#define LRCC_E_SINGULAR (-6)  /* |D_mu -/+ omega| < 1e-8: frequency on a denominator pole */
+#define LRCC_E_INTERNAL (-7)
+
+#define LRCC_HOST 0
+#define LRCC_DEVICE 1
+
+#define LRCC_FP64 0   /* all arithmetic in complex FP64 */
+#define LRCC_MIXED 1  /* Jacobian products in complex FP32 (3M on MFMA), FP64 residuals/updates */
+
+#define LRCC_SIDE_RESIDUAL 0  /* out = Omega(in)                   (Eq. 10)        */
+#define LRCC_SIDE_RIGHT 1     /* out = A in + shift * in           (Eqs. 29-30)    */
+#define LRCC_SIDE_LEFT 2      /* out = in A + shift * in           (Eqs. 22, 32)   */
+
+#define LRCC_AMP_T 0
+#define LRCC_AMP_LAMBDA 1
+#define LRCC_AMP_X 2
+#define LRCC_AMP_Y 3
+
+typedef struct lrcc_ctx lrcc_ctx;
+
+typedef struct lrcc_config {
+  int device;            /* HIP device ordinal */
+  void *stream;          /* hipStream_t to order all work on; NULL = the null stream */
+  int precision;         /* LRCC_FP64 or LRCC_MIXED */
+  double tol_residual;   /* converged when ||R|| <= tol * ||driving term|| (default 1e-10) */
+  int maxit;             /* iteration limit per solve (default 100) */
+  int diis_size;         /* DIIS subspace per right-hand side (default 8, 0 = plain Jacobi) */
+  int rhs_chunk;         /* right-hand sides per batched Jacobian product (0 = all) */
+  int refine_every;      /* mixed mode: iterations between FP64 residual refinements (default 4) */
+  int verbose;           /* 0 silent, 1 per-solve summary, 2 per-iteration lines on stderr */
+} lrcc_config;
+
+typedef struct lrcc_stats {
+  int iterations;        /* iterations taken */
+  int converged;         /* 1 if ||R|| <= tol * ||b|| */
+  double residual;       /* final relative residual ||R|| / ||b|| */
+  double seconds;        /* wall time of the solve */
+  int64_t sigma_evals;   /* Jacobian-vector products (per right-hand side) evaluated */
+} lrcc_stats;
+
+/* Fill `cfg` with defaults. */
+void lrcc_default_config(lrcc_config *cfg);
+
+/* Create a context on cfg->device.  *ctx is NULL on failure. */
+int lrcc_create(lrcc_ctx **ctx, const lrcc_config *cfg);
+/* Release every device and host resource of the context (NULL is allowed). */
+void lrcc_destroy(lrcc_ctx *ctx);
+/* Message of the last failing call on this context ("" if none).  With
+   ctx == NULL, the message of the last failing lrcc_create on this thread. */
+const char *lrcc_last_error(const lrcc_ctx *ctx);
+
+/* Density-fitting factors B[naux][nmo][nmo] (complex, B^Q Hermitian in pq for
+   every Q).  Coulomb integrals (pr|qs) = sum_Q B^Q_pr B^Q_qs; the library
+   builds the antisymmetrized blocks <pq||rs> = (pr|qs) - (ps|qr) it needs on
+   the device (Section II.B, Eq. 39 uses <ij||ab>).  Resets all solutions. */
+int lrcc_load_df(lrcc_ctx *ctx, int nocc, int nvir, int naux, const void *B, int where);
+/* Fock matrix F[nmo][nmo], Hermitian; may be non-diagonal.  The diagonal
+   gives the Jacobi preconditioner D_mu = e_a (+ e_b) - e_i (- e_j). */
+int lrcc_load_fock(lrcc_ctx *ctx, const void *F, int where);
+/* Dipole (perturbation) matrices mu[ncomp][nmo][nmo], Hermitian, ncomp <= 3. */
+int lrcc_load_dipoles(lrcc_ctx *ctx, int ncomp, const void *mu, int where);
+
+/* FNS++ (Section II.C): builds the direction- and frequency-averaged second-
+   order vv density (Eqs. 45-50) from MP2 amplitudes, diagonalizes it (Eq.
+   41), keeps spinors with |n| > thresh (or the `keep` largest if keep > 0),
+   semicanonicalizes (Eqs. 42-44) and rotates B, F and mu of the context into
+   the truncated space.  Requires lrcc_load_df, _fock (diagonal) and
+   _dipoles.  *nvir_out receives the kept count; occ_out (host, length of the
+   original nvir, may be NULL) the occupations sorted by |n| descending. */
+int lrcc_fnspp_truncate(lrcc_ctx *ctx, const double *omegas, int nw, double thresh, int keep,
+                        int *nvir_out, double *occ_out);
+
+/* Ground state: solves Omega(t) = 0 from t = 0 (the first Jacobi step gives
+   MP2).  ecorr[2] (host) receives the complex correlation energy. */
+int lrcc_solve_ground(lrcc_ctx *ctx, double ecorr[2], lrcc_stats *stats);
+/* Lambda: solves eta0 + lambda A = 0 at the converged T. */
+int lrcc_solve_lambda(lrcc_ctx *ctx, lrcc_stats *stats);
+/* Response: for every dipole component B and frequency omegas[k] solves
+   (A - w) X = -xi^B and Y (A + w) = -(eta^B + F X^B), batched over all
+   right-hand sides, and forms alpha.  per_rhs (host, may be NULL) receives
+   2 * ncomp * nw stats: X solves first (k-major, then B), then Y solves. */
+int lrcc_solve_response(lrcc_ctx *ctx, int nw, const double *omegas, lrcc_stats *per_rhs);
+/* alpha[nw][ncomp][ncomp] complex (alpha_AB(w) = -1/2 [f_AB + conj f_BA],
+   f_AB = Y^B.xi^A + eta^A.X^B, Eq. 35) from the last lrcc_solve_response. */
+int lrcc_get_alpha(lrcc_ctx *ctx, void *alpha, int where);
+
+/* Raw Jacobian products for tests, benchmarks and the autograd wrapper.
+   in/out: nvec amplitude vectors; shifts (host, may be NULL = all zero).
+   RESIDUAL: out = Omega(in) (nvec must be 1).  RIGHT/LEFT are taken at the
+   current T (lrcc_solve_ground or lrcc_set_amplitudes(T) first).
+   precision: LRCC_FP64 or LRCC_MIXED (FP32 products). */
+int lrcc_sigma(lrcc_ctx *ctx, int side, int nvec, const double *shifts, const void *in, void *out,
+               int where, int precision);
+
+/* Length n = nocc*nvir + O*V of one amplitude vector (0 before load_df). */
+int64_t lrcc_amplitude_length(const lrcc_ctx *ctx);
+/* Checkpoint / resume of T, Lambda, X or Y (idx = k*ncomp + B for X, Y). */
+int lrcc_get_amplitudes(lrcc_ctx *ctx, int which, int idx, void *out, int where);
+int lrcc_set_amplitudes(lrcc_ctx *ctx, int which, int idx, const void *in, int where);
+
+/* ---- kernel-level entry points (used by the parity tests and the bench) ---- */
+
+/* C = alpha op(A) op(B) + beta C on device buffers, complex, row-major.
+   transa/transb: 0 = as stored, 1 = transposed (no conjugation).
+   precision LRCC_FP64: 4 real products per complex product on FP64 MFMA;
+   LRCC_MIXED: FP32 data, 3 real products (Gauss) on FP32 MFMA, FP32 accumulate.
+   alpha, beta: host complex {re, im}.  stream: hipStream_t or NULL. */
+int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k,
+              const double alpha[2], const void *A, int64_t lda, const void *B, int64_t ldb,
+              const double beta[2], void *C, int64_t ldc, void *stream);
+
+/* Text of the derived operation lists (host-only, no GPU needed):
+   which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L,
+   5 dE/dt, 6 grad L.
+   Writes at most `cap` bytes including the NUL; returns the full length. */
+int64_t lrcc_program_text(int which, char *buf, int64_t cap);
+
+/* Time spent in kernels of one class during the last solve or sigma call,
+   measured with HIP events on the context's stream (milliseconds, launches).
+   cls: 0 = ladder GEMM (packed vvvv), 1 = all GEMMs, 2 = everything. */
+int lrcc_kernel_time(lrcc_ctx *ctx, int cls, double *ms, int64_t *launches, double *flops);
+/* Enable (1) or disable (0) the per-launch event timing above. */
+int lrcc_set_timing(lrcc_ctx *ctx, int on);
+
+/* Build identification string. */
+const char *lrcc_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRCC_H */

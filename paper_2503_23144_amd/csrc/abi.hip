@@ -1,0 +1,369 @@
+// extern "C" entry points of liblrcc.so (declared in include/lrcc.h).
+// Every call catches all C++ exceptions and maps them to LRCC_E_* codes.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "context.h"
+#include "kernels.h"
+
+using lrcc::Context;
+using lrcc::Error;
+
+struct lrcc_ctx {
+  std::unique_ptr<Context> impl;
+  std::string err;
+};
+
+static thread_local std::string g_create_error;
+
+template <typename F>
+static int guard(lrcc_ctx* ctx, F&& f) {
+  if (!ctx || !ctx->impl) return LRCC_E_INVALID;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->impl->cfg.device));
+    f(*ctx->impl);
+    ctx->err.clear();
+    return LRCC_OK;
+  } catch (const Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return LRCC_E_INTERNAL;
+  } catch (...) {
+    ctx->err = "unknown error";
+    return LRCC_E_INTERNAL;
+  }
+}
+
+static void to_stats(const lrcc::SolveStats& s, lrcc_stats* o) {
+  if (!o) return;
+  o->iterations = s.iterations;
+  o->converged = s.converged;
+  o->residual = s.residual;
+  o->seconds = s.seconds;
+  o->sigma_evals = s.sigma_evals;
+}
+
+static void copy_out(void* dst, const void* src, size_t bytes, int where, hipStream_t st) {
+  LRCC_REQUIRE(dst != nullptr, LRCC_E_INVALID, "output pointer is null");
+  LRCC_REQUIRE(where == LRCC_HOST || where == LRCC_DEVICE, LRCC_E_INVALID, "where must be LRCC_HOST or LRCC_DEVICE");
+  HIP_CHECK(hipMemcpyAsync(dst, src, bytes, where == LRCC_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+extern "C" {
+
+void lrcc_default_config(lrcc_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->device = 0;
+  cfg->stream = nullptr;
+  cfg->precision = LRCC_FP64;
+  cfg->tol_residual = 1e-10;
+  cfg->maxit = 100;
+  cfg->diis_size = 8;
+  cfg->rhs_chunk = 0;
+  cfg->refine_every = 4;
+  cfg->verbose = 0;
+}
+
+int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
+  if (!out) return LRCC_E_INVALID;
+  *out = nullptr;
+  try {
+    lrcc_config c;
+    lrcc_default_config(&c);
+    if (cfg) c = *cfg;
+    LRCC_REQUIRE(c.precision == LRCC_FP64 || c.precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
+    LRCC_REQUIRE(c.tol_residual > 0 && c.maxit > 0 && c.diis_size >= 0 && c.diis_size <= 32 && c.rhs_chunk >= 0,
+                 LRCC_E_INVALID, "bad tolerance, iteration limit, DIIS size or chunk");
+    int ndev = 0;
+    HIP_CHECK(hipGetDeviceCount(&ndev));
+    LRCC_REQUIRE(c.device >= 0 && c.device < ndev, LRCC_E_INVALID, "no such HIP device");
+    std::unique_ptr<lrcc_ctx> ctx(new lrcc_ctx);
+    ctx->impl.reset(new Context(c));
+    *out = ctx.release();
+    g_create_error.clear();
+    return LRCC_OK;
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return LRCC_E_INTERNAL;
+  }
+}
+
+void lrcc_destroy(lrcc_ctx* ctx) {
+  if (!ctx) return;
+  try {
+    if (ctx->impl) (void)hipSetDevice(ctx->impl->cfg.device);
+    ctx->impl.reset();
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+const char* lrcc_last_error(const lrcc_ctx* ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+int lrcc_load_df(lrcc_ctx* ctx, int nocc, int nvir, int naux, const void* B, int where) {
+  return guard(ctx, [&](Context& c) { c.load_df(nocc, nvir, naux, B, where); });
+}
+
+int lrcc_load_fock(lrcc_ctx* ctx, const void* F, int where) {
+  return guard(ctx, [&](Context& c) { c.load_fock(F, where); });
+}
+
+int lrcc_load_dipoles(lrcc_ctx* ctx, int ncomp, const void* mu, int where) {
+  return guard(ctx, [&](Context& c) { c.load_dipoles(ncomp, mu, where); });
+}
+
+int lrcc_fnspp_truncate(lrcc_ctx* ctx, const double* omegas, int nw, double thresh, int keep, int* nvir_out,
+                        double* occ_out) {
+  return guard(ctx, [&](Context& c) { c.fnspp_truncate(omegas, nw, thresh, keep, nvir_out, occ_out); });
+}
+
+int lrcc_solve_ground(lrcc_ctx* ctx, double ecorr[2], lrcc_stats* stats) {
+  return guard(ctx, [&](Context& c) {
+    lrcc::SolveStats s;
+    c.kt.clear();
+    try {
+      c.solve_ground(ecorr, s);
+    } catch (...) {
+      to_stats(s, stats);
+      c.collect_times();
+      throw;
+    }
+    to_stats(s, stats);
+    c.collect_times();
+  });
+}
+
+int lrcc_solve_lambda(lrcc_ctx* ctx, lrcc_stats* stats) {
+  return guard(ctx, [&](Context& c) {
+    lrcc::SolveStats s;
+    c.kt.clear();
+    try {
+      c.solve_lambda(s);
+    } catch (...) {
+      to_stats(s, stats);
+      c.collect_times();
+      throw;
+    }
+    to_stats(s, stats);
+    c.collect_times();
+  });
+}
+
+int lrcc_solve_response(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats* per_rhs) {
+  return guard(ctx, [&](Context& c) {
+    std::vector<lrcc::SolveStats> per;
+    c.kt.clear();
+    auto out = [&]() {
+      if (per_rhs)
+        for (size_t k = 0; k < per.size(); ++k) to_stats(per[k], per_rhs + k);
+      c.collect_times();
+    };
+    try {
+      c.solve_response(nw, omegas, per);
+    } catch (...) {
+      out();
+      throw;
+    }
+    out();
+  });
+}
+
+int lrcc_get_alpha(lrcc_ctx* ctx, void* alpha, int where) {
+  return guard(ctx, [&](Context& c) {
+    LRCC_REQUIRE(c.have_alpha, LRCC_E_STATE, "no polarizability (call lrcc_solve_response first)");
+    LRCC_REQUIRE(alpha != nullptr, LRCC_E_INVALID, "alpha is null");
+    size_t bytes = c.alpha.size() * 16;
+    if (where == LRCC_HOST) {
+      std::memcpy(alpha, c.alpha.data(), bytes);
+    } else {
+      LRCC_REQUIRE(where == LRCC_DEVICE, LRCC_E_INVALID, "bad where");
+      HIP_CHECK(hipMemcpyAsync(alpha, c.alpha.data(), bytes, hipMemcpyHostToDevice, c.st));
+      c.sync();
+    }
+  });
+}
+
+int lrcc_sigma(lrcc_ctx* ctx, int side, int nvec, const double* shifts, const void* in, void* out, int where,
+               int precision) {
+  return guard(ctx, [&](Context& c) {
+    c.require_sizes();
+    LRCC_REQUIRE(in && out, LRCC_E_INVALID, "null vector");
+    LRCC_REQUIRE(nvec >= 1, LRCC_E_INVALID, "nvec must be >= 1");
+    LRCC_REQUIRE(where == LRCC_HOST || where == LRCC_DEVICE, LRCC_E_INVALID, "bad where");
+    LRCC_REQUIRE(precision == LRCC_FP64 || precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
+    LRCC_REQUIRE(c.have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+    const size_t vb = c.n * 16;
+    lrcc::DevBuf din, dout, s32, shd;
+    din.ensure(nvec * vb);
+    dout.ensure(nvec * vb);
+    HIP_CHECK(hipMemcpyAsync(din.p, in, nvec * vb, where == LRCC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             c.st));
+    c.kt.clear();
+    if (side == LRCC_SIDE_RESIDUAL) {
+      LRCC_REQUIRE(nvec == 1, LRCC_E_INVALID, "the residual takes one vector");
+      c.residual64(din.p, dout.p, nullptr);
+    } else {
+      LRCC_REQUIRE(side == LRCC_SIDE_RIGHT || side == LRCC_SIDE_LEFT, LRCC_E_INVALID, "bad side");
+      lrcc::Side sd = side == LRCC_SIDE_RIGHT ? lrcc::Side::Right : lrcc::Side::Left;
+      if (precision == LRCC_FP64) {
+        c.sigma64(sd, nvec, din.p, dout.p);
+      } else {
+        s32.ensure(nvec * c.n * 8);
+        c.sigma32(sd, nvec, din.p, s32.p);
+        lrcc::launch_s2d(nvec * c.n, s32.p, dout.p, c.st);
+      }
+      if (shifts) {
+        shd.ensure(nvec * 8);
+        HIP_CHECK(hipMemcpyAsync(shd.p, shifts, nvec * 8, hipMemcpyHostToDevice, c.st));
+        lrcc::launch_residual<double>(nvec, c.n, dout.p, shd.as<double>(), din.p, nullptr, 0, dout.p, c.st);
+      }
+    }
+    copy_out(out, dout.p, nvec * vb, where, c.st);
+    c.collect_times();
+  });
+}
+
+int64_t lrcc_amplitude_length(const lrcc_ctx* ctx) { return (ctx && ctx->impl) ? ctx->impl->n : 0; }
+
+int lrcc_get_amplitudes(lrcc_ctx* ctx, int which, int idx, void* out, int where) {
+  return guard(ctx, [&](Context& c) {
+    c.require_sizes();
+    const size_t vb = c.n * 16;
+    const void* src = nullptr;
+    if (which == LRCC_AMP_T) {
+      LRCC_REQUIRE(c.have_t, LRCC_E_STATE, "no T amplitudes");
+      src = c.t.p;
+    } else if (which == LRCC_AMP_LAMBDA) {
+      LRCC_REQUIRE(c.have_lam, LRCC_E_STATE, "no Lambda amplitudes");
+      src = c.lam.p;
+    } else {
+      LRCC_REQUIRE(which == LRCC_AMP_X || which == LRCC_AMP_Y, LRCC_E_INVALID, "bad amplitude kind");
+      LRCC_REQUIRE(c.have_alpha, LRCC_E_STATE, "no response amplitudes");
+      int nr = (int)c.omegas.size() * c.ncomp;
+      LRCC_REQUIRE(idx >= 0 && idx < nr, LRCC_E_INVALID, "bad right-hand-side index");
+      src = (const char*)(which == LRCC_AMP_X ? c.X.p : c.Y.p) + idx * vb;
+    }
+    copy_out(out, src, vb, where, c.st);
+  });
+}
+
+int lrcc_set_amplitudes(lrcc_ctx* ctx, int which, int idx, const void* in, int where) {
+  return guard(ctx, [&](Context& c) {
+    (void)idx;
+    c.require_sizes();
+    LRCC_REQUIRE(c.have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+    LRCC_REQUIRE(in != nullptr, LRCC_E_INVALID, "null input");
+    LRCC_REQUIRE(where == LRCC_HOST || where == LRCC_DEVICE, LRCC_E_INVALID, "bad where");
+    const size_t vb = c.n * 16;
+    auto kind = where == LRCC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (which == LRCC_AMP_T) {
+      c.t.ensure(vb);
+      HIP_CHECK(hipMemcpyAsync(c.t.p, in, vb, kind, c.st));
+      c.sync();
+      c.have_t = true;
+      c.have_lam = c.have_alpha = false;
+      c.primal64 = c.primal32 = c.gradL_ready = 0;
+    } else if (which == LRCC_AMP_LAMBDA) {
+      LRCC_REQUIRE(c.have_t, LRCC_E_STATE, "set T before Lambda");
+      c.lam.ensure(vb);
+      HIP_CHECK(hipMemcpyAsync(c.lam.p, in, vb, kind, c.st));
+      c.sync();
+      c.have_lam = true;
+      c.gradL_ready = 0;
+      c.have_alpha = false;
+    } else {
+      throw Error(LRCC_E_INVALID, "only T and Lambda can be set");
+    }
+  });
+}
+
+int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k, const double alpha[2],
+              const void* A, int64_t lda, const void* B, int64_t ldb, const double beta[2], void* C, int64_t ldc,
+              void* stream) {
+  try {
+    LRCC_REQUIRE(alpha && beta && A && B && C, LRCC_E_INVALID, "null argument");
+    LRCC_REQUIRE(m >= 0 && n >= 0 && k >= 0, LRCC_E_INVALID, "negative size");
+    LRCC_REQUIRE(lda >= (transa ? m : k) && ldb >= (transb ? k : n) && ldc >= n, LRCC_E_INVALID, "leading dimension");
+    if (precision == LRCC_FP64)
+      lrcc::launch_gemm<double>(transa != 0, transb != 0, m, n, k, alpha[0], alpha[1], A, lda, B, ldb, beta[0],
+                                beta[1], C, ldc, (hipStream_t)stream);
+    else
+      lrcc::launch_gemm<float>(transa != 0, transb != 0, m, n, k, alpha[0], alpha[1], A, lda, B, ldb, beta[0],
+                               beta[1], C, ldc, (hipStream_t)stream);
+    return LRCC_OK;
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return LRCC_E_INTERNAL;
+  }
+}
+
+int64_t lrcc_program_text(int which, char* buf, int64_t cap) {
+  try {
+    static lrcc::CcPrograms P = [] {
+      lrcc::CcPrograms p;
+      lrcc::build_programs(p);
+      return p;
+    }();
+    const lrcc::OpList* lists[] = {&P.residual, &P.right, &P.left, &P.xi, &P.hvp, &P.eta0, &P.gradL};
+    if (which < 0 || which > 6) return -1;
+    std::string s = lrcc::serialize(P.m, *lists[which]);
+    if (buf && cap > 0) {
+      int64_t k = std::min<int64_t>(cap - 1, (int64_t)s.size());
+      std::memcpy(buf, s.data(), k);
+      buf[k] = 0;
+    }
+    return (int64_t)s.size();
+  } catch (...) {
+    return -1;
+  }
+}
+
+int lrcc_kernel_time(lrcc_ctx* ctx, int cls, double* ms, int64_t* launches, double* flops) {
+  return guard(ctx, [&](Context& c) {
+    LRCC_REQUIRE(cls >= 0 && cls <= 2, LRCC_E_INVALID, "bad class");
+    if (ms) *ms = c.kt.ms[cls];
+    if (launches) *launches = c.kt.launches[cls];
+    if (flops) *flops = c.kt.flops[cls];
+  });
+}
+
+int lrcc_set_timing(lrcc_ctx* ctx, int on) {
+  return guard(ctx, [&](Context& c) {
+    c.timing = on != 0;
+    if (c.x64) c.x64->set_timing(c.timing);
+    if (c.x32) c.x32->set_timing(c.timing);
+  });
+}
+
+const char* lrcc_build_info(void) { return "lrcc gfx950 HIP " __DATE__ " " __TIME__; }
+
+}  // extern "C"
+
+namespace lrcc {
+
+void Context::collect_times() {
+  if (x64) x64->collect_times(kt);
+  if (x32) x32->collect_times(kt);
+}
+
+void Context::fnspp_truncate(const double*, int, double, int, int*, double*) {
+  throw Error(LRCC_E_INTERNAL, "FNS++ truncation is not available in this build");
+}
+
+}  // namespace lrcc

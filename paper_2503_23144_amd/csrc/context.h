@@ -1,0 +1,124 @@
+// Solver context: device data of one system and the T, Lambda, X, Y solves.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "program.h"
+#include "runtime.h"
+
+namespace lrcc {
+
+using cplx = std::complex<double>;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void* ensure(size_t b) {
+    if (b > bytes) {
+      release();
+      HIP_CHECK(hipMalloc(&p, std::max<size_t>(b, 16)));
+      bytes = std::max<size_t>(b, 16);
+    }
+    return p;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+struct SolveStats {
+  int iterations = 0;
+  int converged = 0;
+  double residual = 0;
+  double seconds = 0;
+  int64_t sigma_evals = 0;
+};
+
+enum class Side { Right, Left };
+
+struct Context {
+  explicit Context(const lrcc_config& cfg);
+  ~Context();
+
+  lrcc_config cfg;
+  hipStream_t st = nullptr;
+  std::string err;
+
+  // sizes
+  int64_t o = 0, v = 0, naux = 0, nmo = 0, n1 = 0, n2 = 0, n = 0;
+  Dims dims;
+  CcPrograms P;
+  std::unique_ptr<Executor<double>> x64;
+  std::unique_ptr<Executor<float>> x32;
+
+  DevBuf B, fock, mu, D;     // FP64 inputs; D = real denominators [n]
+  std::vector<double> eps;   // Fock diagonal (host)
+  int ncomp = 0;
+  bool have_fock = false;
+  DevBuf t, t32, lam, lam32;
+  bool have_t = false, have_lam = false;
+  int primal64 = 0, primal32 = 0;  // 1 if primal intermediates are at the current t
+  int gradL_ready = 0;
+  cplx ecorr = 0;
+
+  // response
+  std::vector<double> omegas;
+  DevBuf X, Y, xi, eta;      // [nrhs][n], [ncomp][n]
+  std::vector<cplx> alpha;   // [nw][ncomp][ncomp]
+  bool have_alpha = false;
+
+  KernelTimes kt;
+  bool timing = false;
+
+  // scratch
+  DevBuf work, dotbuf;
+
+  // ---- setup
+  void load_df(int nocc, int nvir, int naux_, const void* Bp, int where);
+  void load_fock(const void* F, int where);
+  void load_dipoles(int nc, const void* m, int where);
+  void fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out);
+
+  // ---- solves
+  void solve_ground(double ecorr_out[2], SolveStats& s);
+  void solve_lambda(SolveStats& s);
+  void solve_response(int nw, const double* om, std::vector<SolveStats>& per);
+
+  // ---- Jacobian products on device FP64 vectors [nb][n] (in/out may alias no)
+  void residual64(const void* tvec, void* R, cplx* E);
+  void ensure_primal(int prec);
+  void sigma64(Side side, int nb, const void* in, void* out);
+  void sigma32(Side side, int nb, const void* in64, void* out32);  // FP64 in, FP32 out
+  void xi_vectors(void* out);                                       // [ncomp][n]
+  void hvp(int nb, const int* comp, const void* Xdt, void* out);    // eta^B + F X (Xdt may be null)
+
+  // generic batched linear solve: for r < nb, (op + s_r) x_r = -b_r
+  void solve_linear(Side side, int nb, const double* shifts, const void* b, void* x, int prec, double tol,
+                    std::vector<SolveStats>& st_out);
+
+  int64_t sigma_count = 0;
+  void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
+  void require_sizes() const;
+  void upload_fock_blocks();
+  void build_integrals();
+  void reset_solutions();
+  void collect_times();
+};
+
+}  // namespace lrcc

@@ -1,0 +1,105 @@
+// Launch wrappers of the HIP kernels (gfx950).  All complex data are
+// interleaved {re, im} of T = double or float; all calls are asynchronous on
+// `st`.  Sizes and strides are in complex elements.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lrcc {
+
+constexpr int kMaxRank = 8;
+
+struct PermDesc {
+  int rank;
+  int64_t dims[kMaxRank];     // output dims (row-major)
+  int64_t istride[kMaxRank];  // input stride for each output dim
+};
+
+// out = alpha * in[perm] + beta * out   (beta == 0: out is not read)
+template <typename T>
+void launch_permute(const void* in, void* out, const PermDesc& d, double are, double aim, double bre,
+                    double bim, hipStream_t st);
+
+// Pair-packing view.  The packed tensor has `rank` dims; dim k is either a
+// plain dim (pair[k] == 0, size dims[k], full-tensor stride fstride[k]) or a
+// packed pair of an n x n block (pair[k] == 1, n = npair[k], strides fp[k]
+// (first index) and fq[k] (second index) in the full tensor, mode[k]).
+struct PackDesc {
+  int rank;
+  int64_t dims[kMaxRank];     // packed dims
+  int64_t fstride[kMaxRank];  // plain dims: stride in the full tensor
+  int pair[kMaxRank];
+  int64_t npair[kMaxRank];
+  int64_t fp[kMaxRank], fq[kMaxRank];
+  int mode[kMaxRank];
+  int64_t full_elems;  // total full-tensor elements (unpack: output size)
+  // unpack only: the full tensor's own dims and, per full dim, the packed
+  // dim it belongs to and whether it is the first (0) or second (1) index
+  int frank;
+  int64_t fdims[kMaxRank];
+  int fmap[kMaxRank];
+  int fsec[kMaxRank];
+  int64_t pstride[kMaxRank];  // packed stride of each packed dim
+};
+
+template <typename T>
+void launch_pack(const void* full, void* packed, const PackDesc& d, double are, double aim, bool acc,
+                 hipStream_t st);
+template <typename T>
+void launch_unpack(const void* packed, void* full, const PackDesc& d, double are, double aim, bool acc,
+                   hipStream_t st);
+
+template <typename T>
+void launch_fill_zero(void* p, int64_t n, hipStream_t st);
+
+// out[r] = sum_k opx(x[r*ldx + k]) * y[r*ldy + k], r < nvec (FP64 result
+// {re, im} in device memory).  conjx: conjugate x.  `work` holds at least
+// nvec * 1024 * 16 bytes.
+template <typename T>
+void launch_batched_dot(int64_t nvec, int64_t n, const void* x, int64_t ldx, const void* y, int64_t ldy,
+                        bool conjx, void* out, void* work, hipStream_t st);
+
+// Gram rows: out[r*m + k] = sum_i conj(h[(r*hs + k)*n + i]) * e[r*n + i]
+// (k < m) for r < nvec.  `work`: nvec*m*1024*16 bytes.
+void launch_gram(int64_t nvec, int m, int64_t n, const void* h, int64_t hs, const void* e, void* out,
+                 void* work, hipStream_t st);
+
+// Dense complex GEMM C = alpha op(A) op(B) + beta C (no conjugation).
+// FP64: 4 real MFMA products per complex product; FP32: 3 (Gauss).
+template <typename T>
+void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
+                 int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
+                 hipStream_t st);
+
+// Solver kernels (FP64 vectors, nvec right-hand sides of length n).
+// R = s_r * X + b_r + sig (sig in Ts), optionally returning R.
+template <typename Ts>
+void launch_residual(int64_t nvec, int64_t n, const void* sig, const double* shift_dev, const void* X,
+                     const void* b, int64_t bstride, void* R, hipStream_t st);
+// Xn = X - R / (D + s_r);  E = Xn - X  (either output may be null)
+void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X,
+                   const void* R, void* Xn, void* E, hipStream_t st);
+// X[r] = sum_k c[r*m + k] * H[(r*hs + k)*n + ...]
+void launch_combine(int64_t nvec, int m, int64_t n, const void* c, const void* H, int64_t hs, void* X,
+                    hipStream_t st);
+// dst[r*dld + i] = (To) src[r*sld + i], i < w, r < rows (complex; strided row copy)
+template <typename Ti, typename To>
+void launch_copy_rows(int64_t rows, int64_t w, const void* src, int64_t sld, void* dst, int64_t dld,
+                      hipStream_t st);
+// D[n]: D1[i][a] = e_a - e_i, D2[P(i,j)][P(a,b)] = e_a + e_b - e_i - e_j (eps on device, FP64 real)
+void launch_denominators(int64_t o, int64_t v, const double* eps, double* D, hipStream_t st);
+// precision conversion (complex)
+void launch_d2s(int64_t n, const void* in, void* out, hipStream_t st);
+void launch_s2d(int64_t n, const void* in, void* out, hipStream_t st);
+
+// Integral builder: W[P(a,b)][P(e,f)] = C[a-a0][e][b-b0][f] - C[a-a0][f][b-b0][e]
+// for a in [a0, a1), b in (a, v), e < f; C holds (ae|bf) for b >= b0
+// (row (a-a0)*v + e, column (b-b0)*v + f, row length (v-b0)*v).
+template <typename T>
+void launch_pack_vvvv(int64_t v, int64_t a0, int64_t a1, int64_t b0, const void* C, void* W, hipStream_t st);
+// dst[x][p][r] = src[x][p0 + p][r0 + r] (sub-block gather), p < np, r < nr
+void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
+                         const void* src, void* dst, hipStream_t st);
+
+}  // namespace lrcc

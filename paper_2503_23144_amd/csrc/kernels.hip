@@ -1,0 +1,544 @@
+// Streaming kernels of the lrcc runtime (gfx950): index permutation, pair
+// (un)packing with antisymmetry, reductions with wavefront shuffles, solver
+// updates and integral-block assembly.  These are HBM-bound; each reads and
+// writes every element once, with the output linear index driving the
+// thread mapping so that stores are coalesced.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace lrcc {
+
+template <typename T>
+struct cplx2;
+template <>
+struct cplx2<double> {
+  using type = double2;
+};
+template <>
+struct cplx2<float> {
+  using type = float2;
+};
+
+static inline unsigned nblocks(int64_t total, int threads = 256, int64_t cap = 1 << 20) {
+  int64_t b = (total + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+#define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// ---------------------------------------------------------------- permute
+template <typename T, typename I>
+__global__ void __launch_bounds__(256) permute_kernel(const typename cplx2<T>::type* __restrict__ in,
+                                                      typename cplx2<T>::type* __restrict__ out, PermDesc d,
+                                                      I total, T are, T aim, T bre, T bim, int use_beta) {
+  for (I lin = (I)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += (I)gridDim.x * blockDim.x) {
+    I rem = lin;
+    int64_t off = 0;
+    for (int k = d.rank - 1; k >= 0; --k) {
+      I dk = (I)d.dims[k];
+      I q = rem / dk;
+      off += (int64_t)(rem - q * dk) * d.istride[k];
+      rem = q;
+    }
+    auto x = in[off];
+    T re = are * x.x - aim * x.y;
+    T im = are * x.y + aim * x.x;
+    if (use_beta) {
+      auto y = out[lin];
+      re += bre * y.x - bim * y.y;
+      im += bre * y.y + bim * y.x;
+    }
+    out[lin] = {re, im};
+  }
+}
+
+template <typename T>
+void launch_permute(const void* in, void* out, const PermDesc& d, double are, double aim, double bre, double bim,
+                    hipStream_t st) {
+  int64_t total = 1;
+  for (int k = 0; k < d.rank; ++k) total *= d.dims[k];
+  if (total == 0) return;
+  using C = typename cplx2<T>::type;
+  int ub = (bre != 0.0 || bim != 0.0) ? 1 : 0;
+  if (total < (int64_t(1) << 31))
+    hipLaunchKernelGGL((permute_kernel<T, uint32_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)in,
+                       (C*)out, d, (uint32_t)total, (T)are, (T)aim, (T)bre, (T)bim, ub);
+  else
+    hipLaunchKernelGGL((permute_kernel<T, int64_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)in,
+                       (C*)out, d, total, (T)are, (T)aim, (T)bre, (T)bim, ub);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- pair index
+__device__ inline void decode_pair(int64_t P, int64_t& p, int64_t& q) {
+  int64_t qq = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)P)) * 0.5);
+  while (qq * (qq - 1) / 2 > P) --qq;
+  while ((qq + 1) * qq / 2 <= P) ++qq;
+  q = qq;
+  p = P - qq * (qq - 1) / 2;
+}
+
+// ---------------------------------------------------------------- pack
+template <typename T>
+__global__ void __launch_bounds__(256) pack_kernel(const typename cplx2<T>::type* __restrict__ full,
+                                                   typename cplx2<T>::type* __restrict__ packed, PackDesc d,
+                                                   int64_t total, T are, T aim, int acc) {
+  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total;
+       lin += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = lin, off = 0;
+    int np = 0;
+    int64_t o1[2] = {0, 0}, o2[2] = {0, 0};
+    int md[2] = {0, 0};
+    for (int k = d.rank - 1; k >= 0; --k) {
+      int64_t q = rem / d.dims[k];
+      int64_t i = rem - q * d.dims[k];
+      rem = q;
+      if (d.pair[k]) {
+        int64_t a, b;
+        decode_pair(i, a, b);
+        o1[np] = a * d.fp[k] + b * d.fq[k];
+        o2[np] = b * d.fp[k] + a * d.fq[k];
+        md[np] = d.mode[k];
+        ++np;
+      } else {
+        off += i * d.fstride[k];
+      }
+    }
+    T re = 0, im = 0;
+    for (int mask = 0; mask < (1 << np); ++mask) {
+      bool ok = true;
+      int64_t o = off;
+      T s = 1;
+      for (int j = 0; j < np; ++j) {
+        if (mask & (1 << j)) {
+          if (!md[j]) ok = false;
+          o += o2[j];
+          s = -s;
+        } else {
+          o += o1[j];
+        }
+      }
+      if (!ok) continue;
+      auto x = full[o];
+      re += s * x.x;
+      im += s * x.y;
+    }
+    T rr = are * re - aim * im, ii = are * im + aim * re;
+    if (acc) {
+      auto y = packed[lin];
+      rr += y.x;
+      ii += y.y;
+    }
+    packed[lin] = {rr, ii};
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) unpack_kernel(const typename cplx2<T>::type* __restrict__ packed,
+                                                     typename cplx2<T>::type* __restrict__ full, PackDesc d,
+                                                     int64_t total, T are, T aim, int acc) {
+  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total;
+       lin += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = lin;
+    int64_t pidx[kMaxRank], qidx[kMaxRank], plain[kMaxRank];
+    for (int k = d.frank - 1; k >= 0; --k) {
+      int64_t q = rem / d.fdims[k];
+      int64_t i = rem - q * d.fdims[k];
+      rem = q;
+      int j = d.fmap[k];
+      if (d.fsec[k] < 0)
+        plain[j] = i;
+      else if (d.fsec[k] == 0)
+        pidx[j] = i;
+      else
+        qidx[j] = i;
+    }
+    int64_t off = 0;
+    T s = 1;
+    bool zero = false;
+    for (int j = 0; j < d.rank; ++j) {
+      if (!d.pair[j]) {
+        off += plain[j] * d.pstride[j];
+        continue;
+      }
+      int64_t p = pidx[j], q = qidx[j];
+      if (p == q) {
+        zero = true;
+      } else if (p < q) {
+        off += (q * (q - 1) / 2 + p) * d.pstride[j];
+      } else if (d.mode[j]) {
+        off += (p * (p - 1) / 2 + q) * d.pstride[j];
+        s = -s;
+      } else {
+        zero = true;
+      }
+    }
+    T re = 0, im = 0;
+    if (!zero) {
+      auto x = packed[off];
+      re = s * (are * x.x - aim * x.y);
+      im = s * (are * x.y + aim * x.x);
+    }
+    if (acc) {
+      auto y = full[lin];
+      re += y.x;
+      im += y.y;
+    }
+    full[lin] = {re, im};
+  }
+}
+
+template <typename T>
+void launch_pack(const void* full, void* packed, const PackDesc& d, double are, double aim, bool acc,
+                 hipStream_t st) {
+  int64_t total = 1;
+  for (int k = 0; k < d.rank; ++k) total *= d.dims[k];
+  if (total == 0) return;
+  using C = typename cplx2<T>::type;
+  hipLaunchKernelGGL(pack_kernel<T>, dim3(nblocks(total)), dim3(256), 0, st, (const C*)full, (C*)packed, d, total,
+                     (T)are, (T)aim, acc ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_unpack(const void* packed, void* full, const PackDesc& d, double are, double aim, bool acc,
+                   hipStream_t st) {
+  int64_t total = d.full_elems;
+  if (total == 0) return;
+  using C = typename cplx2<T>::type;
+  hipLaunchKernelGGL(unpack_kernel<T>, dim3(nblocks(total)), dim3(256), 0, st, (const C*)packed, (C*)full, d,
+                     total, (T)are, (T)aim, acc ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- fill
+template <typename T>
+__global__ void fill_zero_kernel(typename cplx2<T>::type* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = {T(0), T(0)};
+}
+
+template <typename T>
+void launch_fill_zero(void* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel<T>, dim3(nblocks(n)), dim3(256), 0, st, (typename cplx2<T>::type*)p, n);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- reductions
+// Block-wide sum of a complex double over 256 threads (4 wavefronts of 64):
+// shuffle within the wavefront, then one LDS slot per wavefront.
+__device__ inline double2 block_sum(double re, double im) {
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_down(re, o, 64);
+    im += __shfl_down(im, o, 64);
+  }
+  __shared__ double2 part[4];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = {re, im};
+  __syncthreads();
+  double2 s = {0.0, 0.0};
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      s.x += part[k].x;
+      s.y += part[k].y;
+    }
+  return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) dot_partial_kernel(const typename cplx2<T>::type* __restrict__ x, int64_t ldx,
+                                                          const typename cplx2<T>::type* __restrict__ y, int64_t ldy,
+                                                          int64_t n, int conjx, double2* __restrict__ part) {
+  int64_t r = blockIdx.y;
+  const auto* xr = x + r * ldx;
+  const auto* yr = y + r * ldy;
+  double re = 0, im = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double ar = xr[i].x, ai = conjx ? -(double)xr[i].y : (double)xr[i].y;
+    double br = yr[i].x, bi = yr[i].y;
+    re += ar * br - ai * bi;
+    im += ar * bi + ai * br;
+  }
+  double2 s = block_sum(re, im);
+  if (threadIdx.x == 0) part[r * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) reduce_rows_kernel(const double2* __restrict__ part, int nparts,
+                                                          double2* __restrict__ out) {
+  int64_t r = blockIdx.x;
+  double re = 0, im = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    re += part[r * nparts + i].x;
+    im += part[r * nparts + i].y;
+  }
+  double2 s = block_sum(re, im);
+  if (threadIdx.x == 0) out[r] = s;
+}
+
+template <typename T>
+void launch_batched_dot(int64_t nvec, int64_t n, const void* x, int64_t ldx, const void* y, int64_t ldy,
+                        bool conjx, void* out, void* work, hipStream_t st) {
+  if (nvec <= 0) return;
+  int nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
+  using C = typename cplx2<T>::type;
+  hipLaunchKernelGGL(dot_partial_kernel<T>, dim3(nparts, (unsigned)nvec), dim3(256), 0, st, (const C*)x, ldx,
+                     (const C*)y, ldy, n, conjx ? 1 : 0, (double2*)work);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)nvec), dim3(256), 0, st, (const double2*)work, nparts,
+                     (double2*)out);
+  LAUNCH_CHECK();
+}
+
+__global__ void __launch_bounds__(256) gram_partial_kernel(const double2* __restrict__ h, int64_t hs, int m,
+                                                           const double2* __restrict__ e, int64_t n,
+                                                           double2* __restrict__ part) {
+  int64_t rk = blockIdx.y;
+  int64_t r = rk / m, k = rk - r * m;
+  const double2* hr = h + (r * hs + k) * n;
+  const double2* er = e + r * n;
+  double re = 0, im = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double2 a = hr[i], b = er[i];
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  double2 s = block_sum(re, im);
+  if (threadIdx.x == 0) part[rk * gridDim.x + blockIdx.x] = s;
+}
+
+void launch_gram(int64_t nvec, int m, int64_t n, const void* h, int64_t hs, const void* e, void* out, void* work,
+                 hipStream_t st) {
+  if (nvec <= 0 || m <= 0) return;
+  int nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 4095) / 4096));
+  hipLaunchKernelGGL(gram_partial_kernel, dim3(nparts, (unsigned)(nvec * m)), dim3(256), 0, st, (const double2*)h,
+                     hs, m, (const double2*)e, n, (double2*)work);
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3((unsigned)(nvec * m)), dim3(256), 0, st, (const double2*)work, nparts,
+                     (double2*)out);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- solver updates
+template <typename Ts>
+__global__ void __launch_bounds__(256) residual_kernel(int64_t n, const typename cplx2<Ts>::type* sig,
+                                                       const double* __restrict__ shift, const double2* X,
+                                                       const double2* b, int64_t bstride, double2* R) {
+  int64_t r = blockIdx.y;
+  double s = shift ? shift[r] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = r * n + i;
+    double re = (double)sig[k].x, im = (double)sig[k].y;
+    if (X) {
+      re += s * X[k].x;
+      im += s * X[k].y;
+    }
+    if (b) {
+      re += b[r * bstride + i].x;
+      im += b[r * bstride + i].y;
+    }
+    R[k] = {re, im};
+  }
+}
+
+template <typename Ts>
+void launch_residual(int64_t nvec, int64_t n, const void* sig, const double* shift_dev, const void* X,
+                     const void* b, int64_t bstride, void* R, hipStream_t st) {
+  if (nvec <= 0) return;
+  unsigned gx = nblocks(n, 256, 4096);
+  using C = typename cplx2<Ts>::type;
+  hipLaunchKernelGGL(residual_kernel<Ts>, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, (const C*)sig, shift_dev,
+                     (const double2*)X, (const double2*)b, bstride, (double2*)R);
+  LAUNCH_CHECK();
+}
+
+__global__ void __launch_bounds__(256) jacobi_kernel(int64_t n, const double* __restrict__ D,
+                                                     const double* __restrict__ shift, const double2* __restrict__ X,
+                                                     const double2* __restrict__ R, double2* __restrict__ Xn,
+                                                     double2* __restrict__ E) {
+  int64_t r = blockIdx.y;
+  double s = shift ? shift[r] : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = r * n + i;
+    double inv = 1.0 / (D[i] + s);
+    double2 d = {-R[k].x * inv, -R[k].y * inv};
+    if (Xn) Xn[k] = X ? double2{X[k].x + d.x, X[k].y + d.y} : d;
+    if (E) E[k] = d;
+  }
+}
+
+void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X, const void* R,
+                   void* Xn, void* E, hipStream_t st) {
+  if (nvec <= 0) return;
+  unsigned gx = nblocks(n, 256, 4096);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, D, shift_dev, (const double2*)X,
+                     (const double2*)R, (double2*)Xn, (double2*)E);
+  LAUNCH_CHECK();
+}
+
+__global__ void __launch_bounds__(256) combine_kernel(int64_t n, int m, const double2* __restrict__ c,
+                                                      const double2* __restrict__ H, int64_t hs,
+                                                      double2* __restrict__ X) {
+  int64_t r = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double re = 0, im = 0;
+    for (int k = 0; k < m; ++k) {
+      double2 a = c[r * m + k], h = H[(r * hs + k) * n + i];
+      re += a.x * h.x - a.y * h.y;
+      im += a.x * h.y + a.y * h.x;
+    }
+    X[r * n + i] = {re, im};
+  }
+}
+
+void launch_combine(int64_t nvec, int m, int64_t n, const void* c, const void* H, int64_t hs, void* X,
+                    hipStream_t st) {
+  if (nvec <= 0) return;
+  unsigned gx = nblocks(n, 256, 4096);
+  hipLaunchKernelGGL(combine_kernel, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, m, (const double2*)c,
+                     (const double2*)H, hs, (double2*)X);
+  LAUNCH_CHECK();
+}
+
+__global__ void d2s_kernel(int64_t n, const double2* __restrict__ in, float2* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = {(float)in[i].x, (float)in[i].y};
+}
+__global__ void s2d_kernel(int64_t n, const float2* __restrict__ in, double2* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = {(double)in[i].x, (double)in[i].y};
+}
+void launch_d2s(int64_t n, const void* in, void* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(d2s_kernel, dim3(nblocks(n)), dim3(256), 0, st, n, (const double2*)in, (float2*)out);
+  LAUNCH_CHECK();
+}
+void launch_s2d(int64_t n, const void* in, void* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(s2d_kernel, dim3(nblocks(n)), dim3(256), 0, st, n, (const float2*)in, (double2*)out);
+  LAUNCH_CHECK();
+}
+
+template <typename Ti, typename To>
+__global__ void copy_rows_kernel(int64_t w, const typename cplx2<Ti>::type* __restrict__ src, int64_t sld,
+                                 typename cplx2<To>::type* __restrict__ dst, int64_t dld) {
+  int64_t r = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < w; i += (int64_t)gridDim.x * blockDim.x) {
+    auto x = src[r * sld + i];
+    dst[r * dld + i] = {(To)x.x, (To)x.y};
+  }
+}
+
+template <typename Ti, typename To>
+void launch_copy_rows(int64_t rows, int64_t w, const void* src, int64_t sld, void* dst, int64_t dld,
+                      hipStream_t st) {
+  if (rows <= 0 || w <= 0) return;
+  LRCC_REQUIRE(rows < 65536, LRCC_E_INVALID, "too many rows");
+  hipLaunchKernelGGL((copy_rows_kernel<Ti, To>), dim3(nblocks(w, 256, 8192), (unsigned)rows), dim3(256), 0, st, w,
+                     (const typename cplx2<Ti>::type*)src, sld, (typename cplx2<To>::type*)dst, dld);
+  LAUNCH_CHECK();
+}
+template void launch_copy_rows<double, double>(int64_t, int64_t, const void*, int64_t, void*, int64_t, hipStream_t);
+template void launch_copy_rows<double, float>(int64_t, int64_t, const void*, int64_t, void*, int64_t, hipStream_t);
+template void launch_copy_rows<float, float>(int64_t, int64_t, const void*, int64_t, void*, int64_t, hipStream_t);
+template void launch_copy_rows<float, double>(int64_t, int64_t, const void*, int64_t, void*, int64_t, hipStream_t);
+
+__global__ void denominators_kernel(int64_t o, int64_t v, const double* __restrict__ eps, double* __restrict__ D) {
+  int64_t n1 = o * v, V = v * (v - 1) / 2, O = o * (o - 1) / 2;
+  int64_t n = n1 + O * V;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < n1) {
+      int64_t i = k / v, a = k - i * v;
+      D[k] = eps[o + a] - eps[i];
+    } else {
+      int64_t q = k - n1;
+      int64_t I = q / V, A = q - I * V;
+      int64_t i, j, a, b;
+      decode_pair(I, i, j);
+      decode_pair(A, a, b);
+      D[k] = eps[o + a] + eps[o + b] - eps[i] - eps[j];
+    }
+  }
+}
+
+void launch_denominators(int64_t o, int64_t v, const double* eps, double* D, hipStream_t st) {
+  int64_t n = o * v + (o * (o - 1) / 2) * (v * (v - 1) / 2);
+  hipLaunchKernelGGL(denominators_kernel, dim3(nblocks(n)), dim3(256), 0, st, o, v, eps, D);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- integral assembly
+template <typename T>
+__global__ void __launch_bounds__(256) pack_vvvv_kernel(int64_t v, int64_t a0, int64_t b0,
+                                                        const typename cplx2<T>::type* __restrict__ C,
+                                                        typename cplx2<T>::type* __restrict__ W) {
+  // grid.y: (a - a0) * v + b ; grid.x * 256: E
+  int64_t ab = blockIdx.y;
+  int64_t al = ab / v, b = ab - al * v;
+  int64_t a = a0 + al;
+  if (b <= a) return;
+  int64_t V = v * (v - 1) / 2;
+  int64_t row = b * (b - 1) / 2 + a;
+  int64_t ld = (v - b0) * v;
+  const auto* Ca = C + al * v * ld + (b - b0) * v;  // C[al][e][b][f] at Ca[e*ld + f]
+  for (int64_t E = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; E < V; E += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e, f;
+    decode_pair(E, e, f);
+    auto x = Ca[e * ld + f];
+    auto y = Ca[f * ld + e];
+    W[row * V + E] = {x.x - y.x, x.y - y.y};
+  }
+}
+
+template <typename T>
+void launch_pack_vvvv(int64_t v, int64_t a0, int64_t a1, int64_t b0, const void* C, void* W, hipStream_t st) {
+  int64_t V = v * (v - 1) / 2;
+  if (V == 0 || a1 <= a0) return;
+  using Cx = typename cplx2<T>::type;
+  unsigned gx = nblocks(V, 256, 64);
+  hipLaunchKernelGGL(pack_vvvv_kernel<T>, dim3(gx, (unsigned)((a1 - a0) * v)), dim3(256), 0, st, v, a0, b0,
+                     (const Cx*)C, (Cx*)W);
+  LAUNCH_CHECK();
+}
+
+__global__ void gather_block_kernel(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
+                                    const double2* __restrict__ src, double2* __restrict__ dst) {
+  int64_t total = naux * np * nr;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = i % nr, t = i / nr;
+    int64_t p = t % np, x = t / np;
+    dst[i] = src[(x * nmo + p0 + p) * nmo + r0 + r];
+  }
+}
+
+void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr, const void* src,
+                         void* dst, hipStream_t st) {
+  int64_t total = naux * np * nr;
+  if (total == 0) return;
+  hipLaunchKernelGGL(gather_block_kernel, dim3(nblocks(total)), dim3(256), 0, st, naux, nmo, p0, np, r0, nr,
+                     (const double2*)src, (double2*)dst);
+  LAUNCH_CHECK();
+}
+
+// explicit instantiations
+#define INST(T)                                                                                               \
+  template void launch_permute<T>(const void*, void*, const PermDesc&, double, double, double, double,       \
+                                  hipStream_t);                                                              \
+  template void launch_pack<T>(const void*, void*, const PackDesc&, double, double, bool, hipStream_t);      \
+  template void launch_unpack<T>(const void*, void*, const PackDesc&, double, double, bool, hipStream_t);    \
+  template void launch_fill_zero<T>(void*, int64_t, hipStream_t);                                            \
+  template void launch_batched_dot<T>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, bool,    \
+                                      void*, void*, hipStream_t);                                            \
+  template void launch_residual<T>(int64_t, int64_t, const void*, const double*, const void*, const void*,   \
+                                   int64_t, void*, hipStream_t);                                             \
+  template void launch_pack_vvvv<T>(int64_t, int64_t, int64_t, int64_t, const void*, void*, hipStream_t);
+INST(double)
+INST(float)
+
+}  // namespace lrcc

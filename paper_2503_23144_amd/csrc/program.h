@@ -1,0 +1,121 @@
+// Contraction-program IR for the CC residual and its derivatives.
+//
+// The CCSD residual Omega(t) = <mu| exp(-T) H exp(T) |0> (Section II.A,
+// Eqs. 9-10) is held once, as a list of tensor operations over named
+// tensors with occupied/virtual index classes.  The Jacobian products the
+// response theory needs are derived from it mechanically:
+//   * right sigma  A X         (Eqs. 29-30)  = forward-mode tangent of Omega
+//   * left sigma   lambda A    (Eqs. 22, 32) = reverse-mode adjoint of Omega
+//   * xi^B                     (Eq. 31)      = tangent of Omega along f -> mu_B
+//   * eta^B + F X^B            (Eqs. 33-34)  = tangent of grad_t L, L = E + lambda.Omega
+// Every derived operation is again one of the four kinds below, so one
+// executor (HIP kernels) runs them all.
+//
+// Index letters: i..n occupied, a..h virtual, I..N packed occupied pairs
+// (i<j), A..H packed virtual pairs (a<b); '#' is the batch (right-hand
+// side) index of batched tensors and is added by the planner.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <set>
+#include <string>
+#include <vector>
+
+namespace lrcc {
+
+enum class Role { Input, Fock, Const, Temp, Tangent, Adjoint, Scalar1 };
+
+struct TensorDecl {
+  std::string name;
+  std::string cls;   // one char per dim: 'o','v' (orbital), 'O','V' (packed pair)
+  Role role;
+  bool batched = false;
+};
+
+enum class OpKind { Add, Contract, Pack, Unpack, Zero };
+
+// out[oi] (+)= alpha * a[ai] (* b[bi])
+// Pack:   out (packed) <- a (full);   Unpack: out (full) <- a (packed).
+// Pair modes per packed letter, in order: 0 = take upper triangle / scatter to
+// upper triangle; 1 = antisymmetric gather x[pq]-x[qp] / antisymmetric expand.
+struct Op {
+  OpKind kind = OpKind::Add;
+  bool acc = false;
+  double are = 1.0, aim = 0.0;
+  int out = -1;
+  std::string oi;
+  int a = -1;
+  std::string ai;
+  int b = -1;
+  std::string bi;
+  int mode[2] = {0, 0};
+};
+
+using OpList = std::vector<Op>;
+
+struct Module {
+  std::vector<TensorDecl> tensors;
+  std::map<std::string, int> by_name;
+  int add(const std::string& name, const std::string& cls, Role role, bool batched = false);
+  int find(const std::string& name) const;  // -1 if absent
+  const TensorDecl& operator[](int i) const { return tensors.at(i); }
+};
+
+char letter_class(char c);
+
+// Parse the statement language (one statement per line, '#' comments):
+//   input  t1[ia] t2p[IA]         declares tensors with a role
+//   fock   foo[ij] ...
+//   const  goovv[ijab] ...
+//   X[idx]  = [c *] A[idx]                      Add (permuted copy)
+//   X[idx] += [c *] A[idx] * B[idx]             Contract
+//   X[idx] += [c *] pack(A[idx], m1[, m2])      Pack / unpack(...) Unpack
+OpList parse_program(Module& m, const std::string& text);
+
+// Forward-mode tangent program.  `tan` maps seed tensors to their (batched)
+// tangent tensors on entry and is extended with every tangent created.
+// `want` lists primal tensors whose tangents must be produced (zero-filled
+// if they receive no contribution).
+OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::vector<int>& want,
+           const std::string& tag = "d");
+
+// Reverse-mode adjoint program.  `adj` maps output tensors to their
+// cotangent tensors on entry; `wrt` lists inputs whose adjoints are wanted.
+// Adjoints are created batched if `batched`.
+OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::vector<int>& wrt,
+           bool batched, const std::string& tag = "g");
+
+// Remove ops that do not contribute to `keep`.
+OpList prune(const Module& m, const OpList& prog, const std::vector<int>& keep);
+
+std::string dump(const Module& m, const OpList& prog);
+// Machine-readable form: the tensor table, then one line per op.
+//   T <id> <name> <cls|-> <role> <batched>
+//   O <kind> <acc> <are> <aim> <out> <oi|-> <a> <ai|-> <b> <bi|-> <m0> <m1>
+std::string serialize(const Module& m, const OpList& prog);
+
+// The CCSD residual and energy as a program over the module's tensors.
+extern const char* kCcsdProgram;
+
+// All programs the solvers run, derived from kCcsdProgram.
+struct CcPrograms {
+  Module m;
+  OpList residual;  // O1, O2p, E from t1, t2p, f, <||>          (primal, all temps kept)
+  OpList right;     // dO = A dt                                 (tangent, batched)
+  OpList left;      // g_t = gO A                                (adjoint, batched)
+  OpList eta0;      // dE/dt                                     (adjoint of E, unbatched)
+  OpList xi;        // dO along f -> mu                          (tangent in f, batched)
+  OpList gradL;     // d/dt (E + lambda.Omega)                   (adjoint, unbatched)
+  OpList hvp;       // tangent of gradL along (dt, df)           (batched)
+  // tensor ids
+  int t1, t2p, foo, fov, fvo, fvv, O1, O2p, E, one;
+  int r_dt1, r_dt2p, r_dO1, r_dO2p;           // right
+  int l_gO1, l_gO2p, l_gt1, l_gt2p;           // left
+  int e_gt1, e_gt2p;                          // eta0
+  int x_df[4], x_dO1, x_dO2p;                 // xi (df in foo, fov, fvo, fvv order)
+  int g_lam1, g_lam2p, g_gt1, g_gt2p;         // gradL
+  int h_dt1, h_dt2p, h_df[4], h_out1, h_out2p;  // hvp
+};
+void build_programs(CcPrograms& P);
+
+}  // namespace lrcc

@@ -1,0 +1,101 @@
+// Executor of contraction programs on one GPU.
+//
+// Every operation of an OpList becomes HIP kernel launches on one stream:
+//   Contract  -> (optional) index permutation of each operand into GEMM
+//                order, one complex MFMA GEMM, (optional) permutation of the
+//                product into the output order  (transpose-transpose-GEMM-
+//                transpose); a full contraction to a scalar is a reduction.
+//   Add       -> one permutation kernel (alpha, beta)
+//   Pack/Unpack -> one pair (un)packing kernel
+//   Zero      -> fill kernel
+// Batched tensors (tangents/adjoints of nb right-hand sides) carry a leading
+// batch index '#', which the planner folds into the GEMM M dimension.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "program.h"
+
+namespace lrcc {
+
+struct Dims {
+  int64_t o = 0, v = 0, O = 0, V = 0;
+  int64_t of(char cls) const { return cls == 'o' ? o : cls == 'v' ? v : cls == 'O' ? O : V; }
+};
+
+struct KernelTimes {
+  double ms[3] = {0, 0, 0};     // ladder GEMM, all GEMM, everything
+  int64_t launches[3] = {0, 0, 0};
+  double flops[3] = {0, 0, 0};  // executed real flops (ladder, all GEMM)
+  void clear() { *this = KernelTimes(); }
+};
+
+template <typename T>
+class Executor {
+ public:
+  Executor(const Module& m, Dims d, hipStream_t st);
+  ~Executor();
+  Executor(const Executor&) = delete;
+  Executor& operator=(const Executor&) = delete;
+
+  int64_t elems(int id, int nb) const;  // complex elements of tensor id at batch nb
+  // Storage: owned (allocated on first use for the current max batch) or bound.
+  void* ptr(int id);
+  void bind(int id, void* p);
+  void unbind(int id);
+  void set_max_batch(int nb);
+  int max_batch() const { return max_nb_; }
+  // Copy host/device data into an owned tensor (converting FP64 -> T).
+  void upload(int id, const void* src_fp64, int nb = 1);
+  void run(const OpList& ops, int nb);
+  void release_batched();
+  size_t bytes_allocated() const;
+
+  // optional per-launch timing (HIP events on the stream)
+  void set_timing(bool on) { timing_ = on; }
+  void collect_times(KernelTimes& kt);  // synchronizes; accumulates and clears pending events
+  int ladder_const = -1;                // tensor id whose contractions count as the ladder
+
+ private:
+  void contract(const Op& op, int nb);
+  void add(const Op& op, int nb);
+  void pack(const Op& op, int nb);
+  void unpack(const Op& op, int nb);
+  void permute_into(const void* src, int64_t src_cap, const std::string& sl, void* dst, int64_t dst_cap,
+                    const std::string& dl, double are, double aim, double bre, double bim);
+  void* scratch(int slot, size_t bytes);
+  int64_t scratch_elems(int slot) const { return (int64_t)(scr_cap_[slot] / (2 * sizeof(T))); }
+  int64_t capacity(int id);  // complex elements addressable through ptr(id) (allocates if needed)
+  int64_t dim(char letter) const;
+  std::string letters(int id, const std::string& idx) const;
+  void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
+            int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
+            int64_t capC, bool ladder);
+
+  const Module& m_;
+  Dims d_;
+  hipStream_t st_;
+  int max_nb_ = 1;
+  std::vector<void*> buf_;
+  std::vector<int64_t> cap_;  // allocated elements
+  std::vector<char> bound_;
+  std::vector<void*> scr_;
+  std::vector<size_t> scr_cap_;
+  void* dot_out_ = nullptr;
+  void* dot_work_ = nullptr;
+  bool timing_ = false;
+  struct Pending {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> event_pool_;
+  hipEvent_t get_event();
+  int cur_cls_ = -1;
+};
+
+}  // namespace lrcc

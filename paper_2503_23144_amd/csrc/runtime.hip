@@ -1,0 +1,544 @@
+// Executor of contraction programs (see runtime.h).
+#include "runtime.h"
+
+#include <algorithm>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace lrcc {
+
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<double> {
+  using type = double2;
+};
+template <>
+struct vec2_of<float> {
+  using type = float2;
+};
+
+// c = alpha * d (+ c if acc); d is an FP64 complex scalar in device memory.
+template <typename T>
+__global__ void scalar_set_kernel(const double2* d, typename vec2_of<T>::type* c, double are, double aim, int acc) {
+  double re = are * d->x - aim * d->y, im = are * d->y + aim * d->x;
+  if (acc) {
+    re += (double)c->x;
+    im += (double)c->y;
+  }
+  *c = {(T)re, (T)im};
+}
+
+template <typename T>
+Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), st_(st) {
+  size_t n = m.tensors.size();
+  buf_.assign(n, nullptr);
+  cap_.assign(n, 0);
+  bound_.assign(n, 0);
+  scr_.assign(4, nullptr);
+  scr_cap_.assign(4, 0);
+  HIP_CHECK(hipMalloc(&dot_out_, 64));
+  HIP_CHECK(hipMalloc(&dot_work_, 1024 * 16));
+}
+
+template <typename T>
+Executor<T>::~Executor() {
+  for (size_t k = 0; k < buf_.size(); ++k)
+    if (buf_[k] && !bound_[k]) (void)hipFree(buf_[k]);
+  for (void* p : scr_)
+    if (p) (void)hipFree(p);
+  (void)hipFree(dot_out_);
+  (void)hipFree(dot_work_);
+  for (auto& p : pending_) {
+    event_pool_.push_back(p.a);
+    event_pool_.push_back(p.b);
+  }
+  for (auto e : event_pool_) (void)hipEventDestroy(e);
+}
+
+template <typename T>
+int64_t Executor<T>::elems(int id, int nb) const {
+  const TensorDecl& t = m_[id];
+  int64_t n = t.batched ? nb : 1;
+  for (char c : t.cls) n *= d_.of(c);
+  return n;
+}
+
+template <typename T>
+void* Executor<T>::ptr(int id) {
+  if (bound_[id]) return buf_[id];
+  int64_t need = elems(id, max_nb_);
+  if (cap_[id] < need) {
+    if (buf_[id]) {
+      HIP_CHECK(hipStreamSynchronize(st_));
+      HIP_CHECK(hipFree(buf_[id]));
+      buf_[id] = nullptr;
+    }
+    HIP_CHECK(hipMalloc(&buf_[id], std::max<int64_t>(need, 1) * sizeof(T) * 2));
+    cap_[id] = need;
+  }
+  return buf_[id];
+}
+
+template <typename T>
+void Executor<T>::bind(int id, void* p) {
+  if (buf_[id] && !bound_[id]) {
+    HIP_CHECK(hipStreamSynchronize(st_));
+    HIP_CHECK(hipFree(buf_[id]));
+  }
+  buf_[id] = p;
+  cap_[id] = 0;
+  bound_[id] = 1;
+}
+
+template <typename T>
+void Executor<T>::unbind(int id) {
+  if (bound_[id]) {
+    buf_[id] = nullptr;
+    bound_[id] = 0;
+    cap_[id] = 0;
+  }
+}
+
+template <typename T>
+void Executor<T>::set_max_batch(int nb) {
+  if (nb <= max_nb_) return;
+  max_nb_ = nb;  // batched buffers grow on next use
+}
+
+template <typename T>
+void Executor<T>::release_batched() {
+  HIP_CHECK(hipStreamSynchronize(st_));
+  for (size_t k = 0; k < buf_.size(); ++k)
+    if (m_[k].batched && buf_[k] && !bound_[k]) {
+      HIP_CHECK(hipFree(buf_[k]));
+      buf_[k] = nullptr;
+      cap_[k] = 0;
+    }
+}
+
+template <typename T>
+size_t Executor<T>::bytes_allocated() const {
+  size_t s = 0;
+  for (size_t k = 0; k < buf_.size(); ++k)
+    if (!bound_[k]) s += cap_[k] * sizeof(T) * 2;
+  for (size_t c : scr_cap_) s += c;
+  return s;
+}
+
+template <typename T>
+void Executor<T>::upload(int id, const void* src, int nb) {
+  int64_t n = elems(id, nb);
+  void* dst = ptr(id);
+  if constexpr (sizeof(T) == 8) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, n * 16, hipMemcpyDefault, st_));
+  } else {
+    void* tmp = scratch(3, n * 16);
+    HIP_CHECK(hipMemcpyAsync(tmp, src, n * 16, hipMemcpyDefault, st_));
+    launch_d2s(n, tmp, dst, st_);
+  }
+}
+
+template <typename T>
+void* Executor<T>::scratch(int slot, size_t bytes) {
+  if (scr_cap_[slot] < bytes) {
+    if (scr_[slot]) {
+      HIP_CHECK(hipStreamSynchronize(st_));
+      HIP_CHECK(hipFree(scr_[slot]));
+    }
+    size_t b = std::max(bytes, scr_cap_[slot] + scr_cap_[slot] / 4);
+    HIP_CHECK(hipMalloc(&scr_[slot], b));
+    scr_cap_[slot] = b;
+  }
+  return scr_[slot];
+}
+
+// current batch of the op being executed (dims of '#')
+static thread_local int64_t g_nb = 1;
+
+template <typename T>
+int64_t Executor<T>::capacity(int id) {
+  if (bound_[id]) return elems(id, (int)g_nb);
+  ptr(id);
+  return cap_[id];
+}
+
+template <typename T>
+int64_t Executor<T>::dim(char l) const {
+  if (l == '#') return max_nb_;  // replaced by the actual batch in run()
+  return d_.of(letter_class(l));
+}
+
+template <typename T>
+std::string Executor<T>::letters(int id, const std::string& idx) const {
+  return (m_[id].batched ? std::string("#") : std::string()) + idx;
+}
+
+template <typename T>
+hipEvent_t Executor<T>::get_event() {
+  if (event_pool_.empty()) {
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    return e;
+  }
+  hipEvent_t e = event_pool_.back();
+  event_pool_.pop_back();
+  return e;
+}
+
+template <typename T>
+void Executor<T>::collect_times(KernelTimes& kt) {
+  if (pending_.empty()) return;
+  HIP_CHECK(hipStreamSynchronize(st_));
+  for (auto& p : pending_) {
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
+    for (int c = p.cls; c < 3; ++c) {
+      if (c == 0 && p.cls != 0) continue;
+      kt.ms[c] += ms;
+      kt.launches[c] += 1;
+      kt.flops[c] += p.flops;
+    }
+    event_pool_.push_back(p.a);
+    event_pool_.push_back(p.b);
+  }
+  pending_.clear();
+}
+
+template <typename T>
+void Executor<T>::permute_into(const void* src, int64_t src_cap, const std::string& sl, void* dst, int64_t dst_cap,
+                               const std::string& dl, double are, double aim, double bre, double bim) {
+  LRCC_REQUIRE((int)dl.size() <= kMaxRank, LRCC_E_INTERNAL, "rank too large");
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  // source strides (row-major)
+  std::vector<int64_t> sstr(sl.size());
+  int64_t s = 1;
+  for (int k = (int)sl.size() - 1; k >= 0; --k) {
+    sstr[k] = s;
+    s *= dimof(sl[k]);
+  }
+  // merge runs of output letters that are also consecutive in the source
+  PermDesc d{};
+  d.rank = 0;
+  for (size_t k = 0; k < dl.size(); ++k) {
+    size_t p = sl.find(dl[k]);
+    LRCC_REQUIRE(p != std::string::npos, LRCC_E_INTERNAL, "permute letter missing");
+    int64_t n = dimof(dl[k]);
+    if (d.rank > 0 && k > 0) {
+      size_t pp = sl.find(dl[k - 1]);
+      if (pp + 1 == p) {  // previous output letter directly precedes in source
+        d.dims[d.rank - 1] *= n;
+        d.istride[d.rank - 1] = sstr[p];
+        continue;
+      }
+    }
+    d.dims[d.rank] = n;
+    d.istride[d.rank] = sstr[p];
+    ++d.rank;
+  }
+  if (d.rank == 0) {
+    d.rank = 1;
+    d.dims[0] = 1;
+    d.istride[0] = 1;
+  }
+  int64_t total = 1, maxin = 0;
+  for (int k = 0; k < d.rank; ++k) {
+    total *= d.dims[k];
+    maxin += (d.dims[k] - 1) * d.istride[k];
+  }
+  LRCC_REQUIRE(total <= dst_cap && maxin < src_cap, LRCC_E_INTERNAL,
+               "permute " + sl + "->" + dl + " exceeds its buffers");
+  launch_permute<T>(src, dst, d, are, aim, bre, bim, st_);
+}
+
+template <typename T>
+void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
+                       int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C,
+                       int64_t ldc, int64_t capC, bool ladder) {
+  if (M > 0 && N > 0 && K > 0) {
+    int64_t spanA = ta ? (K - 1) * lda + M : (M - 1) * lda + K;
+    int64_t spanB = tb ? (N - 1) * ldb + K : (K - 1) * ldb + N;
+    LRCC_REQUIRE(spanA <= capA && spanB <= capB && (M - 1) * ldc + N <= capC && lda >= (ta ? M : K) &&
+                     ldb >= (tb ? K : N) && ldc >= N,
+                 LRCC_E_INTERNAL, "gemm operands exceed their buffers");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timing_) {
+    e0 = get_event();
+    HIP_CHECK(hipEventRecord(e0, st_));
+  }
+  launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_);
+  if (timing_) {
+    e1 = get_event();
+    HIP_CHECK(hipEventRecord(e1, st_));
+    double fl = (sizeof(T) == 8 ? 8.0 : 6.0) * (double)M * (double)N * (double)K;
+    pending_.push_back({e0, e1, ladder ? 0 : 1, fl});
+  }
+}
+
+template <typename T>
+void Executor<T>::contract(const Op& op, int nb) {
+  (void)nb;
+  std::string a = letters(op.a, op.ai), b = letters(op.b, op.bi), c = letters(op.out, op.oi);
+  const void* pa = ptr(op.a);
+  const void* pb = ptr(op.b);
+  void* pc = ptr(op.out);
+  int64_t ca = capacity(op.a), cb = capacity(op.b), cc = capacity(op.out);
+  auto size_of = [&](const std::string& sx) {
+    int64_t p = 1;
+    for (char ch : sx) p *= (ch == '#' ? g_nb : dim(ch));
+    return p;
+  };
+  bool ladder = (op.a == ladder_const || op.b == ladder_const);
+  if (m_[op.b].batched && !m_[op.a].batched) {
+    std::swap(a, b);
+    std::swap(pa, pb);
+    std::swap(ca, cb);
+  }
+  LRCC_REQUIRE(size_of(a) <= ca && size_of(b) <= cb && size_of(c) <= cc, LRCC_E_INTERNAL,
+               "contraction operand larger than its buffer");
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  auto size = [&](const std::string& s) {
+    int64_t p = 1;
+    for (char ch : s) p *= dimof(ch);
+    return p;
+  };
+  std::string K, Mc, Nc;
+  for (char ch : a)
+    if (b.find(ch) != std::string::npos) {
+      LRCC_REQUIRE(c.find(ch) == std::string::npos, LRCC_E_INTERNAL, "index in all three operands");
+      K += ch;
+    }
+  for (char ch : c) {
+    if (a.find(ch) != std::string::npos)
+      Mc += ch;
+    else if (b.find(ch) != std::string::npos)
+      Nc += ch;
+    else
+      throw Error(LRCC_E_INTERNAL, "output index not in operands");
+  }
+  LRCC_REQUIRE(Mc.size() + K.size() == a.size() && Nc.size() + K.size() == b.size(), LRCC_E_INTERNAL,
+               "contraction letters inconsistent");
+  const bool acc = op.acc;
+
+  if (Mc.empty() && Nc.empty()) {  // full contraction to a scalar
+    LRCC_REQUIRE(!m_[op.out].batched, LRCC_E_INTERNAL, "batched scalar output");
+    const void* pb2 = pb;
+    if (b != a) {
+      void* t = scratch(1, size(b) * sizeof(T) * 2);
+      permute_into(pb, cb, b, t, scratch_elems(1), a, 1, 0, 0, 0);
+      pb2 = t;
+    }
+    launch_batched_dot<T>(1, size(a), pa, 0, pb2, 0, false, dot_out_, dot_work_, st_);
+    hipLaunchKernelGGL(scalar_set_kernel<T>, dim3(1), dim3(1), 0, st_, (const double2*)dot_out_,
+                       (typename vec2_of<T>::type*)pc, op.are, op.aim, acc ? 1 : 0);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+
+  bool direct = (c == Mc + Nc);
+  if (!direct && c == Nc + Mc && a.find('#') == std::string::npos) {
+    std::swap(a, b);
+    std::swap(pa, pb);
+    std::swap(ca, cb);
+    std::swap(Mc, Nc);
+    direct = true;
+  }
+  const int64_t Ms = size(Mc), Ns = size(Nc), Ks = size(K);
+  // choose the K order needing the fewest operand permutations
+  std::string Ka, Kb;
+  for (char ch : a)
+    if (K.find(ch) != std::string::npos) Ka += ch;
+  for (char ch : b)
+    if (K.find(ch) != std::string::npos) Kb += ch;
+  auto a_ok = [&](const std::string& Kx) { return a == Mc + Kx || a == Kx + Mc; };
+  auto b_ok = [&](const std::string& Kx) { return b == Kx + Nc || b == Nc + Kx; };
+  auto cost = [&](const std::string& Kx) {
+    return (a_ok(Kx) ? 0 : size(a)) + (b_ok(Kx) ? 0 : size(b));
+  };
+  std::string Kx = cost(Ka) <= cost(Kb) ? Ka : Kb;
+
+  bool ta, tb;
+  int64_t lda, ldb;
+  const void* A = pa;
+  const void* B = pb;
+  int64_t capA = ca, capB = cb;
+  if (a == Mc + Kx) {
+    ta = false;
+    lda = Ks;
+  } else if (a == Kx + Mc) {
+    ta = true;
+    lda = Ms;
+  } else {
+    void* t = scratch(0, size(a) * sizeof(T) * 2);
+    permute_into(pa, ca, a, t, scratch_elems(0), Mc + Kx, 1, 0, 0, 0);
+    A = t;
+    capA = scratch_elems(0);
+    ta = false;
+    lda = Ks;
+  }
+  if (b == Kx + Nc) {
+    tb = false;
+    ldb = Ns;
+  } else if (b == Nc + Kx) {
+    tb = true;
+    ldb = Ks;
+  } else {
+    void* t = scratch(1, size(b) * sizeof(T) * 2);
+    permute_into(pb, cb, b, t, scratch_elems(1), Kx + Nc, 1, 0, 0, 0);
+    B = t;
+    capB = scratch_elems(1);
+    tb = false;
+    ldb = Ns;
+  }
+  if (direct) {
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder);
+  } else {
+    void* t = scratch(2, (size_t)Ms * Ns * sizeof(T) * 2);
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, 0.0, t, Ns, scratch_elems(2), ladder);
+    permute_into(t, scratch_elems(2), Mc + Nc, pc, cc, c, 1, 0, acc ? 1 : 0, 0);
+  }
+}
+
+template <typename T>
+void Executor<T>::add(const Op& op, int nb) {
+  (void)nb;
+  std::string a = letters(op.a, op.ai), c = letters(op.out, op.oi);
+  LRCC_REQUIRE(m_[op.a].batched == m_[op.out].batched, LRCC_E_INTERNAL, "add: batch mismatch");
+  permute_into(ptr(op.a), capacity(op.a), a, ptr(op.out), capacity(op.out), c, op.are, op.aim, op.acc ? 1 : 0, 0);
+}
+
+// Align packed letters `pk` with full letters `fl`: for each packed position,
+// the first full position it covers and whether it is a pair.
+static void align(const std::string& pk, const std::string& fl, std::vector<int>& fpos, std::vector<int>& ispair) {
+  size_t p = 0;
+  fpos.clear();
+  ispair.clear();
+  for (char ch : pk) {
+    if (p < fl.size() && fl[p] == ch) {
+      fpos.push_back((int)p);
+      ispair.push_back(0);
+      p += 1;
+    } else {
+      LRCC_REQUIRE(p + 1 < fl.size(), LRCC_E_INTERNAL, "pack alignment");
+      fpos.push_back((int)p);
+      ispair.push_back(1);
+      p += 2;
+    }
+  }
+  LRCC_REQUIRE(p == fl.size(), LRCC_E_INTERNAL, "pack alignment (length)");
+}
+
+template <typename T>
+void Executor<T>::pack(const Op& op, int nb) {
+  (void)nb;
+  std::string pk = letters(op.out, op.oi), fl = letters(op.a, op.ai);
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  std::vector<int> fpos, isp;
+  align(pk, fl, fpos, isp);
+  std::vector<int64_t> fstr(fl.size());
+  int64_t s = 1;
+  for (int k = (int)fl.size() - 1; k >= 0; --k) {
+    fstr[k] = s;
+    s *= dimof(fl[k]);
+  }
+  PackDesc d{};
+  d.rank = (int)pk.size();
+  int np = 0;
+  for (int k = 0; k < d.rank; ++k) {
+    int p = fpos[k];
+    if (!isp[k]) {
+      d.dims[k] = dimof(fl[p]);
+      d.fstride[k] = fstr[p];
+      d.pair[k] = 0;
+    } else {
+      int64_t n = dimof(fl[p]);
+      d.dims[k] = n * (n - 1) / 2;
+      d.pair[k] = 1;
+      d.npair[k] = n;
+      d.fp[k] = fstr[p];
+      d.fq[k] = fstr[p + 1];
+      d.mode[k] = op.mode[np++];
+    }
+  }
+  int64_t ptot = 1, fmax = 0;
+  for (int k = 0; k < d.rank; ++k) {
+    ptot *= d.dims[k];
+    if (d.pair[k])
+      fmax += (d.npair[k] - 1) * (d.fp[k] + d.fq[k]);
+    else
+      fmax += (d.dims[k] - 1) * d.fstride[k];
+  }
+  LRCC_REQUIRE(ptot <= capacity(op.out) && fmax < capacity(op.a) && s <= capacity(op.a), LRCC_E_INTERNAL,
+               "pack exceeds its buffers");
+  launch_pack<T>(ptr(op.a), ptr(op.out), d, op.are, op.aim, op.acc, st_);
+}
+
+template <typename T>
+void Executor<T>::unpack(const Op& op, int nb) {
+  (void)nb;
+  std::string pk = letters(op.a, op.ai), fl = letters(op.out, op.oi);
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  std::vector<int> fpos, isp;
+  align(pk, fl, fpos, isp);
+  PackDesc d{};
+  d.rank = (int)pk.size();
+  d.frank = (int)fl.size();
+  int np = 0;
+  for (int k = 0; k < d.rank; ++k) {
+    int p = fpos[k];
+    int64_t n = dimof(fl[p]);
+    if (!isp[k]) {
+      d.dims[k] = n;
+      d.pair[k] = 0;
+      d.fmap[p] = k;
+      d.fsec[p] = -1;
+    } else {
+      d.dims[k] = n * (n - 1) / 2;
+      d.pair[k] = 1;
+      d.npair[k] = n;
+      d.mode[k] = op.mode[np++];
+      d.fmap[p] = k;
+      d.fsec[p] = 0;
+      d.fmap[p + 1] = k;
+      d.fsec[p + 1] = 1;
+    }
+  }
+  int64_t s = 1;
+  for (int k = d.rank - 1; k >= 0; --k) {
+    d.pstride[k] = s;
+    s *= d.dims[k];
+  }
+  d.full_elems = 1;
+  for (int k = 0; k < d.frank; ++k) {
+    d.fdims[k] = dimof(fl[k]);
+    d.full_elems *= d.fdims[k];
+  }
+  LRCC_REQUIRE(d.full_elems <= capacity(op.out) && s <= capacity(op.a), LRCC_E_INTERNAL,
+               "unpack exceeds its buffers");
+  launch_unpack<T>(ptr(op.a), ptr(op.out), d, op.are, op.aim, op.acc, st_);
+}
+
+template <typename T>
+void Executor<T>::run(const OpList& ops, int nb) {
+  LRCC_REQUIRE(nb >= 1 && nb <= max_nb_, LRCC_E_INTERNAL, "batch exceeds executor maximum");
+  g_nb = nb;
+  for (const Op& op : ops) {
+    switch (op.kind) {
+      case OpKind::Contract: contract(op, nb); break;
+      case OpKind::Add: add(op, nb); break;
+      case OpKind::Pack: pack(op, nb); break;
+      case OpKind::Unpack: unpack(op, nb); break;
+      case OpKind::Zero:
+        LRCC_REQUIRE(elems(op.out, nb) <= capacity(op.out), LRCC_E_INTERNAL, "zero-fill exceeds its buffer");
+        launch_fill_zero<T>(ptr(op.out), elems(op.out, nb), st_);
+        break;
+    }
+  }
+}
+
+template class Executor<double>;
+template class Executor<float>;
+
+}  // namespace lrcc

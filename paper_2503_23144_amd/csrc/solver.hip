@@ -1,0 +1,725 @@
+// T, Lambda, X(w), Y(w) solves and the polarizability (Section II.A).
+//
+// All vectors are FP64 on the device.  Each solve is a batched Jacobi
+// iteration x <- x - R / (D + s) with the orbital-energy denominators D and
+// per right-hand-side shift s, accelerated by DIIS on the preconditioned
+// residuals; the residual R, its norm, the update, the DIIS Gram matrix and
+// the extrapolation are FP64.  Only the Jacobian product inside R may run in
+// FP32 (mixed mode), in which case an outer FP64 residual drives iterative
+// refinement: solve (A + s) delta = -R64 with FP32 products, x += delta.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "context.h"
+#include "integrals.h"
+#include "kernels.h"
+
+namespace lrcc {
+
+static const char* kBlocks[][2] = {{"goooo", "oooo"}, {"gooov", "ooov"}, {"goovv", "oovv"}, {"govvo", "ovvo"},
+                                   {"govvv", "ovvv"}, {"gvvoo", "vvoo"}, {"gvvvo", "vvvo"}, {"govoo", "ovoo"}};
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+Context::Context(const lrcc_config& c) : cfg(c) {
+  HIP_CHECK(hipSetDevice(cfg.device));
+  st = (hipStream_t)cfg.stream;
+  build_programs(P);
+}
+
+Context::~Context() {
+  if (st) (void)hipStreamSynchronize(st);
+  x64.reset();
+  x32.reset();
+}
+
+void Context::require_sizes() const { LRCC_REQUIRE(n > 0, LRCC_E_STATE, "lrcc_load_df has not been called"); }
+
+void Context::reset_solutions() {
+  have_t = have_lam = have_alpha = false;
+  primal64 = primal32 = 0;
+  gradL_ready = 0;
+  omegas.clear();
+  alpha.clear();
+}
+
+static void copy_in(void* dst, const void* src, size_t bytes, int where, hipStream_t st) {
+  LRCC_REQUIRE(where == LRCC_HOST || where == LRCC_DEVICE, LRCC_E_INVALID, "where must be LRCC_HOST or LRCC_DEVICE");
+  HIP_CHECK(hipMemcpyAsync(dst, src, bytes, where == LRCC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
+  LRCC_REQUIRE(Bp != nullptr, LRCC_E_INVALID, "B is null");
+  LRCC_REQUIRE(nocc >= 2 && nvir >= 2 && na >= 1, LRCC_E_INVALID, "need nocc >= 2, nvir >= 2, naux >= 1");
+  x64.reset();
+  x32.reset();
+  o = nocc, v = nvir, naux = na, nmo = o + v;
+  n1 = o * v;
+  dims = Dims{o, v, o * (o - 1) / 2, v * (v - 1) / 2};
+  n2 = dims.O * dims.V;
+  n = n1 + n2;
+  B.ensure(naux * nmo * nmo * 16);
+  copy_in(B.p, Bp, naux * nmo * nmo * 16, where, st);
+  x64.reset(new Executor<double>(P.m, dims, st));
+  x64->ladder_const = P.m.find("W");
+  x64->set_timing(timing);
+  build_integrals();
+  have_fock = false;
+  ncomp = 0;
+  reset_solutions();
+}
+
+void Context::build_integrals() {
+  for (auto& b : kBlocks) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
+  build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
+  pack_last_pair(x64->ptr(P.m.find("govvv")), o, v, v, x64->ptr(P.m.find("govvp")), st);
+  const double one[2] = {1.0, 0.0};
+  HIP_CHECK(hipMemcpyAsync(x64->ptr(P.one), one, 16, hipMemcpyHostToDevice, st));
+  sync();
+}
+
+static void ensure_x32(Context& c) {
+  if (c.x32) return;
+  c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
+  c.x32->ladder_const = c.P.m.find("W");
+  c.x32->set_timing(c.timing);
+  for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
+    Role r = c.P.m[(int)id].role;
+    if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))
+      launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
+  }
+  c.sync();
+}
+
+void Context::upload_fock_blocks() {
+  const int ids[4] = {P.foo, P.fov, P.fvo, P.fvv};
+  const int64_t p0[4] = {0, 0, o, o}, np[4] = {o, o, v, v}, r0[4] = {0, o, 0, o}, nr[4] = {o, v, o, v};
+  for (int k = 0; k < 4; ++k) {
+    launch_gather_block(1, nmo, p0[k], np[k], r0[k], nr[k], fock.p, x64->ptr(ids[k]), st);
+    if (x32) launch_d2s(np[k] * nr[k], x64->ptr(ids[k]), x32->ptr(ids[k]), st);
+  }
+}
+
+void Context::load_fock(const void* F, int where) {
+  require_sizes();
+  LRCC_REQUIRE(F != nullptr, LRCC_E_INVALID, "F is null");
+  fock.ensure(nmo * nmo * 16);
+  copy_in(fock.p, F, nmo * nmo * 16, where, st);
+  std::vector<cplx> h(nmo * nmo);
+  HIP_CHECK(hipMemcpy(h.data(), fock.p, nmo * nmo * 16, hipMemcpyDeviceToHost));
+  double herm = 0, scale = 0;
+  for (int64_t p = 0; p < nmo; ++p)
+    for (int64_t q = 0; q < nmo; ++q) {
+      herm = std::max(herm, std::abs(h[p * nmo + q] - std::conj(h[q * nmo + p])));
+      scale = std::max(scale, std::abs(h[p * nmo + q]));
+    }
+  LRCC_REQUIRE(herm <= 1e-10 * std::max(1.0, scale), LRCC_E_INVALID, "Fock matrix is not Hermitian");
+  eps.resize(nmo);
+  for (int64_t p = 0; p < nmo; ++p) eps[p] = h[p * nmo + p].real();
+  double emax_o = *std::max_element(eps.begin(), eps.begin() + o);
+  double emin_v = *std::min_element(eps.begin() + o, eps.end());
+  LRCC_REQUIRE(emin_v - emax_o > 1e-8, LRCC_E_SINGULAR, "no gap between occupied and virtual Fock diagonals");
+  DevBuf e;
+  e.ensure(nmo * 8);
+  HIP_CHECK(hipMemcpy(e.p, eps.data(), nmo * 8, hipMemcpyHostToDevice));
+  D.ensure(n * 8);
+  launch_denominators(o, v, e.as<double>(), D.as<double>(), st);
+  upload_fock_blocks();
+  sync();
+  have_fock = true;
+  reset_solutions();
+}
+
+void Context::load_dipoles(int nc, const void* m, int where) {
+  require_sizes();
+  LRCC_REQUIRE(m != nullptr && nc >= 1 && nc <= 3, LRCC_E_INVALID, "need 1..3 dipole matrices");
+  mu.ensure(nc * nmo * nmo * 16);
+  copy_in(mu.p, m, nc * nmo * nmo * 16, where, st);
+  std::vector<cplx> h(nc * nmo * nmo);
+  HIP_CHECK(hipMemcpy(h.data(), mu.p, h.size() * 16, hipMemcpyDeviceToHost));
+  for (int c = 0; c < nc; ++c)
+    for (int64_t p = 0; p < nmo; ++p)
+      for (int64_t q = 0; q <= p; ++q) {
+        cplx a = h[(c * nmo + p) * nmo + q], b = h[(c * nmo + q) * nmo + p];
+        LRCC_REQUIRE(std::abs(a - std::conj(b)) <= 1e-10 * (1.0 + std::abs(a)), LRCC_E_INVALID,
+                     "dipole matrix is not Hermitian");
+      }
+  ncomp = nc;
+  have_alpha = false;
+}
+
+// ---------------------------------------------------------------- Jacobian products
+
+void Context::residual64(const void* tvec, void* R, cplx* E) {
+  x64->bind(P.t1, const_cast<void*>(tvec));
+  x64->bind(P.t2p, (char*)const_cast<void*>(tvec) + n1 * 16);
+  x64->bind(P.O1, R);
+  x64->bind(P.O2p, (char*)R + n1 * 16);
+  x64->run(P.residual, 1);
+  x64->unbind(P.O1);
+  x64->unbind(P.O2p);
+  primal64 = (tvec == t.p) ? 1 : 0;
+  gradL_ready = 0;
+  if (E) {
+    double e[2];
+    HIP_CHECK(hipMemcpyAsync(e, x64->ptr(P.E), 16, hipMemcpyDeviceToHost, st));
+    sync();
+    *E = cplx(e[0], e[1]);
+  }
+}
+
+void Context::ensure_primal(int prec) {
+  LRCC_REQUIRE(have_t, LRCC_E_STATE, "no ground-state amplitudes (call lrcc_solve_ground first)");
+  if (prec == 64) {
+    if (!primal64) {
+      work.ensure(n * 16);
+      residual64(t.p, work.p, nullptr);
+    }
+    return;
+  }
+  ensure_x32(*this);
+  if (!primal32) {
+    t32.ensure(n * 8);
+    launch_d2s(n, t.p, t32.p, st);
+    x32->bind(P.t1, t32.p);
+    x32->bind(P.t2p, (char*)t32.p + n1 * 8);
+    x32->run(P.residual, 1);
+    primal32 = 1;
+  }
+}
+
+void Context::sigma64(Side side, int nb, const void* in, void* out) {
+  ensure_primal(64);
+  x64->set_max_batch(nb);
+  const bool r = side == Side::Right;
+  int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
+  int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
+  launch_copy_rows<double, double>(nb, n1, in, n, x64->ptr(a1), n1, st);
+  launch_copy_rows<double, double>(nb, n2, (const char*)in + n1 * 16, n, x64->ptr(a2), n2, st);
+  x64->run(r ? P.right : P.left, nb);
+  launch_copy_rows<double, double>(nb, n1, x64->ptr(o1), n1, out, n, st);
+  launch_copy_rows<double, double>(nb, n2, x64->ptr(o2), n2, (char*)out + n1 * 16, n, st);
+  sigma_count += nb;
+}
+
+void Context::sigma32(Side side, int nb, const void* in64, void* out32) {
+  ensure_primal(32);
+  x32->set_max_batch(nb);
+  const bool r = side == Side::Right;
+  int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
+  int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
+  launch_copy_rows<double, float>(nb, n1, in64, n, x32->ptr(a1), n1, st);
+  launch_copy_rows<double, float>(nb, n2, (const char*)in64 + n1 * 16, n, x32->ptr(a2), n2, st);
+  x32->run(r ? P.right : P.left, nb);
+  launch_copy_rows<float, float>(nb, n1, x32->ptr(o1), n1, out32, n, st);
+  launch_copy_rows<float, float>(nb, n2, x32->ptr(o2), n2, (char*)out32 + n1 * 8, n, st);
+  sigma_count += nb;
+}
+
+static void gather_mu_blocks(Context& c, int nb, const int* comp, const int* dst_ids) {
+  const int64_t p0[4] = {0, 0, c.o, c.o}, np[4] = {c.o, c.o, c.v, c.v}, r0[4] = {0, c.o, 0, c.o},
+                nr[4] = {c.o, c.v, c.o, c.v};
+  for (int k = 0; k < 4; ++k) {
+    char* dst = (char*)c.x64->ptr(dst_ids[k]);
+    for (int r = 0; r < nb; ++r)
+      launch_gather_block(1, c.nmo, p0[k], np[k], r0[k], nr[k], (const char*)c.mu.p + comp[r] * c.nmo * c.nmo * 16,
+                          dst + r * np[k] * nr[k] * 16, c.st);
+  }
+}
+
+void Context::xi_vectors(void* out) {
+  ensure_primal(64);
+  x64->set_max_batch(ncomp);
+  std::vector<int> comp(ncomp);
+  for (int c = 0; c < ncomp; ++c) comp[c] = c;
+  gather_mu_blocks(*this, ncomp, comp.data(), P.x_df);
+  x64->run(P.xi, ncomp);
+  launch_copy_rows<double, double>(ncomp, n1, x64->ptr(P.x_dO1), n1, out, n, st);
+  launch_copy_rows<double, double>(ncomp, n2, x64->ptr(P.x_dO2p), n2, (char*)out + n1 * 16, n, st);
+}
+
+void Context::hvp(int nb, const int* comp, const void* Xdt, void* out) {
+  ensure_primal(64);
+  LRCC_REQUIRE(have_lam, LRCC_E_STATE, "no Lambda amplitudes (call lrcc_solve_lambda first)");
+  if (!gradL_ready) {
+    x64->bind(P.g_lam1, lam.p);
+    x64->bind(P.g_lam2p, (char*)lam.p + n1 * 16);
+    x64->run(P.gradL, 1);
+    gradL_ready = 1;
+  }
+  x64->set_max_batch(nb);
+  if (Xdt) {
+    launch_copy_rows<double, double>(nb, n1, Xdt, n, x64->ptr(P.h_dt1), n1, st);
+    launch_copy_rows<double, double>(nb, n2, (const char*)Xdt + n1 * 16, n, x64->ptr(P.h_dt2p), n2, st);
+  } else {
+    launch_fill_zero<double>(x64->ptr(P.h_dt1), nb * n1, st);
+    launch_fill_zero<double>(x64->ptr(P.h_dt2p), nb * n2, st);
+  }
+  gather_mu_blocks(*this, nb, comp, P.h_df);
+  x64->run(P.hvp, nb);
+  launch_copy_rows<double, double>(nb, n1, x64->ptr(P.h_out1), n1, out, n, st);
+  launch_copy_rows<double, double>(nb, n2, x64->ptr(P.h_out2p), n2, (char*)out + n1 * 16, n, st);
+}
+
+static void vec_norms(Context& c, int nb, const void* v, std::vector<double>& out) {
+  DevBuf d, w;
+  d.ensure(nb * 16);
+  w.ensure((size_t)nb * 1024 * 16);
+  launch_batched_dot<double>(nb, c.n, v, c.n, v, c.n, true, d.p, w.p, c.st);
+  std::vector<cplx> h(nb);
+  HIP_CHECK(hipMemcpyAsync(h.data(), d.p, nb * 16, hipMemcpyDeviceToHost, c.st));
+  c.sync();
+  out.resize(nb);
+  for (int r = 0; r < nb; ++r) out[r] = std::sqrt(std::max(0.0, h[r].real()));
+}
+
+// ---------------------------------------------------------------- DIIS
+
+// Solve the DIIS equations [G 1; 1^T 0][c; l] = [0; 1] (complex, small) by
+// Gaussian elimination with partial pivoting on the scale-normalized Gram
+// matrix.  Returns false if singular.
+static bool diis_coeffs(const std::vector<cplx>& G, int m, int cnt, const std::vector<int>& idx, std::vector<cplx>& c) {
+  int N = cnt + 1;
+  std::vector<cplx> A(N * N), b(N);
+  double sc = 0;
+  for (int i = 0; i < cnt; ++i) sc = std::max(sc, std::abs(G[idx[i] * m + idx[i]]));
+  if (sc == 0) return false;
+  for (int i = 0; i < cnt; ++i) {
+    for (int j = 0; j < cnt; ++j) A[i * N + j] = G[idx[i] * m + idx[j]] / sc;
+    A[i * N + cnt] = 1.0;
+    A[cnt * N + i] = 1.0;
+  }
+  A[cnt * N + cnt] = 0.0;
+  b[cnt] = 1.0;
+  for (int k = 0; k < N; ++k) {
+    int p = k;
+    for (int i = k + 1; i < N; ++i)
+      if (std::abs(A[i * N + k]) > std::abs(A[p * N + k])) p = i;
+    if (std::abs(A[p * N + k]) < 1e-14) return false;
+    if (p != k) {
+      for (int j = 0; j < N; ++j) std::swap(A[k * N + j], A[p * N + j]);
+      std::swap(b[k], b[p]);
+    }
+    for (int i = k + 1; i < N; ++i) {
+      cplx f = A[i * N + k] / A[k * N + k];
+      for (int j = k; j < N; ++j) A[i * N + j] -= f * A[k * N + j];
+      b[i] -= f * b[k];
+    }
+  }
+  std::vector<cplx> x(N);
+  for (int i = N - 1; i >= 0; --i) {
+    cplx s = b[i];
+    for (int j = i + 1; j < N; ++j) s -= A[i * N + j] * x[j];
+    x[i] = s / A[i * N + i];
+  }
+  c.assign(m, 0.0);
+  for (int i = 0; i < cnt; ++i) c[idx[i]] = x[i];
+  return true;
+}
+
+struct SlotMeta {
+  int rhs = -1;
+  int cnt = 0;    // entries stored
+  int next = 0;   // ring position of the next entry
+  int iters = 0;
+  int64_t sig = 0;
+  double bnorm = 0, rn = 0;
+  std::vector<cplx> G;  // m x m Gram matrix of stored errors
+};
+
+// Batched DIIS-accelerated Jacobi solver over `nb` slots.  Slots hold the
+// right-hand sides still iterating, compacted to [0, na): a converged slot
+// is replaced by the last active one.  resid(na, shift, X, B, R) writes the
+// residual of the first na slots (B: the slot-ordered driving terms, or null).
+// b (rhs order, may be null) also sets the reference norms; without it the
+// first residual norm is the reference.  Results go to x in rhs order.
+using ResidFn = std::function<void(int, const double*, const void*, const void*, void*)>;
+
+static void diis_solve(Context& c, int nb, const double* shifts_host, const void* b, void* x, double tol, int maxit,
+                       const ResidFn& resid, std::vector<SolveStats>& stats, int sig_per_eval) {
+  const int64_t n = c.n;
+  const int m = std::max(0, c.cfg.diis_size);
+  const size_t vb = n * 16;
+  double t0 = now_s();
+  DevBuf Xw, Bw, Rw, Xn, En, Hx, He, shift, coef, gram, dots, work;
+  Xw.ensure(nb * vb);
+  Rw.ensure(nb * vb);
+  Xn.ensure(nb * vb);
+  En.ensure(nb * vb);
+  if (b) {
+    Bw.ensure(nb * vb);
+    HIP_CHECK(hipMemcpyAsync(Bw.p, b, nb * vb, hipMemcpyDeviceToDevice, c.st));
+  }
+  if (m > 0) {
+    Hx.ensure((size_t)nb * m * vb);
+    He.ensure((size_t)nb * m * vb);
+    launch_fill_zero<double>(He.p, (int64_t)nb * m * n, c.st);
+    launch_fill_zero<double>(Hx.p, (int64_t)nb * m * n, c.st);
+    coef.ensure(nb * m * 16);
+    gram.ensure(nb * m * 16);
+  }
+  shift.ensure(nb * 8);
+  dots.ensure(nb * 16);
+  work.ensure((size_t)nb * std::max(m, 1) * 1024 * 16);
+  HIP_CHECK(hipMemcpyAsync(Xw.p, x, nb * vb, hipMemcpyDeviceToDevice, c.st));
+  std::vector<double> sh(nb, 0.0);
+  if (shifts_host) sh.assign(shifts_host, shifts_host + nb);
+  std::vector<SlotMeta> meta(nb);
+  std::vector<cplx> hd(nb), hg((size_t)nb * std::max(m, 1)), hc((size_t)nb * std::max(m, 1));
+  if (b) {
+    launch_batched_dot<double>(nb, n, Bw.p, n, Bw.p, n, true, dots.p, work.p, c.st);
+    HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, nb * 16, hipMemcpyDeviceToHost, c.st));
+    c.sync();
+  }
+  for (int s = 0; s < nb; ++s) {
+    meta[s].rhs = s;
+    meta[s].bnorm = b ? std::sqrt(std::max(0.0, hd[s].real())) : -1.0;
+    if (b && meta[s].bnorm == 0) meta[s].bnorm = 1e-300;
+    meta[s].G.assign(std::max(m, 1) * std::max(m, 1), 0.0);
+  }
+  stats.assign(nb, SolveStats());
+  auto slot_ptr = [&](DevBuf& buf, int s) { return (char*)buf.p + (size_t)s * vb; };
+  auto hist_ptr = [&](DevBuf& buf, int s, int k) { return (char*)buf.p + ((size_t)s * m + k) * vb; };
+  auto finalize = [&](int s, bool conv) {
+    SlotMeta& mt = meta[s];
+    HIP_CHECK(hipMemcpyAsync((char*)x + (size_t)mt.rhs * vb, slot_ptr(Xw, s), vb, hipMemcpyDeviceToDevice, c.st));
+    SolveStats& so = stats[mt.rhs];
+    so.iterations = mt.iters;
+    so.converged = conv ? 1 : 0;
+    so.residual = mt.bnorm > 0 ? mt.rn / mt.bnorm : mt.rn;
+    so.sigma_evals = mt.sig;
+    so.seconds = now_s() - t0;
+  };
+  auto move_slot = [&](int from, int to) {
+    if (from == to) return;
+    HIP_CHECK(hipMemcpyAsync(slot_ptr(Xw, to), slot_ptr(Xw, from), vb, hipMemcpyDeviceToDevice, c.st));
+    HIP_CHECK(hipMemcpyAsync(slot_ptr(Rw, to), slot_ptr(Rw, from), vb, hipMemcpyDeviceToDevice, c.st));
+    if (b) HIP_CHECK(hipMemcpyAsync(slot_ptr(Bw, to), slot_ptr(Bw, from), vb, hipMemcpyDeviceToDevice, c.st));
+    if (m > 0) {
+      HIP_CHECK(hipMemcpyAsync(hist_ptr(Hx, to, 0), hist_ptr(Hx, from, 0), m * vb, hipMemcpyDeviceToDevice, c.st));
+      HIP_CHECK(hipMemcpyAsync(hist_ptr(He, to, 0), hist_ptr(He, from, 0), m * vb, hipMemcpyDeviceToDevice, c.st));
+    }
+    meta[to] = meta[from];
+    sh[to] = sh[from];
+  };
+  int na = nb;
+  for (int it = 0; it <= maxit && na > 0; ++it) {
+    HIP_CHECK(hipMemcpyAsync(shift.p, sh.data(), na * 8, hipMemcpyHostToDevice, c.st));
+    resid(na, shift.as<double>(), Xw.p, b ? Bw.p : nullptr, Rw.p);
+    launch_batched_dot<double>(na, n, Rw.p, n, Rw.p, n, true, dots.p, work.p, c.st);
+    HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, na * 16, hipMemcpyDeviceToHost, c.st));
+    c.sync();
+    for (int s = 0; s < na; ++s) {
+      meta[s].rn = std::sqrt(std::max(0.0, hd[s].real()));
+      meta[s].sig += sig_per_eval;
+      if (meta[s].bnorm < 0) meta[s].bnorm = meta[s].rn > 0 ? meta[s].rn : 1.0;
+      LRCC_REQUIRE(std::isfinite(meta[s].rn), LRCC_E_NOCONV, "residual is not finite");
+    }
+    if (c.cfg.verbose >= 2) {
+      fprintf(stderr, "[lrcc] it %d active %d", it, na);
+      for (int s = 0; s < std::min(na, 4); ++s) fprintf(stderr, " %.3e", meta[s].rn / meta[s].bnorm);
+      fprintf(stderr, "\n");
+    }
+    for (int s = 0; s < na;) {
+      if (meta[s].rn <= tol * meta[s].bnorm) {
+        finalize(s, true);
+        move_slot(na - 1, s);
+        --na;
+      } else {
+        ++s;
+      }
+    }
+    if (na == 0 || it == maxit) break;
+    HIP_CHECK(hipMemcpyAsync(shift.p, sh.data(), na * 8, hipMemcpyHostToDevice, c.st));
+    launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Xn.p, En.p, c.st);
+    for (int s = 0; s < na; ++s) meta[s].iters += 1;
+    if (m == 0) {
+      HIP_CHECK(hipMemcpyAsync(Xw.p, Xn.p, na * vb, hipMemcpyDeviceToDevice, c.st));
+      continue;
+    }
+    for (int s = 0; s < na; ++s) {
+      int p = meta[s].next;
+      HIP_CHECK(hipMemcpyAsync(hist_ptr(Hx, s, p), slot_ptr(Xn, s), vb, hipMemcpyDeviceToDevice, c.st));
+      HIP_CHECK(hipMemcpyAsync(hist_ptr(He, s, p), slot_ptr(En, s), vb, hipMemcpyDeviceToDevice, c.st));
+    }
+    launch_gram(na, m, n, He.p, m, En.p, gram.p, work.p, c.st);
+    HIP_CHECK(hipMemcpyAsync(hg.data(), gram.p, (size_t)na * m * 16, hipMemcpyDeviceToHost, c.st));
+    c.sync();
+    for (int s = 0; s < na; ++s) {
+      SlotMeta& mt = meta[s];
+      int p = mt.next;
+      mt.cnt = std::min(mt.cnt + 1, m);
+      mt.next = (mt.next + 1) % m;
+      for (int k = 0; k < m; ++k) {
+        mt.G[k * m + p] = hg[(size_t)s * m + k];
+        mt.G[p * m + k] = std::conj(hg[(size_t)s * m + k]);
+      }
+      std::vector<int> idx;
+      for (int k = 0; k < mt.cnt; ++k) idx.push_back(((mt.next - mt.cnt + k) % m + m) % m);
+      std::vector<cplx> cf;
+      if (!diis_coeffs(mt.G, m, mt.cnt, idx, cf)) {
+        mt.cnt = 1;  // restart the subspace from the newest vector
+        cf.assign(m, 0.0);
+        cf[p] = 1.0;
+      }
+      for (int k = 0; k < m; ++k) hc[(size_t)s * m + k] = cf[k];
+    }
+    HIP_CHECK(hipMemcpyAsync(coef.p, hc.data(), (size_t)na * m * 16, hipMemcpyHostToDevice, c.st));
+    launch_combine(na, m, n, coef.p, Hx.p, m, Xw.p, c.st);
+  }
+  for (int s = 0; s < na; ++s) finalize(s, false);
+  c.sync();
+}
+
+// ---------------------------------------------------------------- solves
+
+void Context::solve_ground(double ecorr_out[2], SolveStats& so) {
+  require_sizes();
+  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+  t.ensure(n * 16);
+  launch_fill_zero<double>(t.p, n, st);
+  have_t = have_lam = have_alpha = false;
+  primal64 = primal32 = gradL_ready = 0;
+  std::vector<SolveStats> ss;
+  diis_solve(*this, 1, nullptr, nullptr, t.p, cfg.tol_residual, cfg.maxit,
+             [&](int, const double*, const void* X, const void*, void* R) { residual64(X, R, nullptr); }, ss, 0);
+  so = ss[0];
+  // evaluate once more at the solution: every stored intermediate then belongs to it
+  have_t = true;
+  work.ensure(n * 16);
+  cplx E;
+  residual64(t.p, work.p, &E);
+  ecorr = E;
+  if (ecorr_out) {
+    ecorr_out[0] = E.real();
+    ecorr_out[1] = E.imag();
+  }
+  LRCC_REQUIRE(so.converged, LRCC_E_NOCONV, "ground-state amplitudes did not converge");
+}
+
+// Batched linear solve (op + s_r) x_r = -b_r (op = A for Right, A^T for Left).
+// x holds the initial guesses on entry.  prec 64: FP64 products; prec 32:
+// iterative refinement with FP64 outer residuals and FP32 inner products.
+void Context::solve_linear(Side side, int nb, const double* shifts, const void* b, void* x, int prec, double tol,
+                           std::vector<SolveStats>& out) {
+  const size_t vb = n * 16;
+  DevBuf sig;
+  if (prec == 64) {
+    sig.ensure(nb * vb);
+    diis_solve(*this, nb, shifts, b, x, tol, cfg.maxit,
+               [&](int na, const double* sh, const void* X, const void* Bw, void* R) {
+                 sigma64(side, na, X, sig.p);
+                 launch_residual<double>(na, n, sig.p, sh, X, Bw, n, R, st);
+               },
+               out, 1);
+    return;
+  }
+  // mixed precision with iterative refinement
+  sig.ensure(nb * n * 8);
+  DevBuf Xa, Ba, R64, d, s64, shd;
+  Xa.ensure(nb * vb);
+  Ba.ensure(nb * vb);
+  R64.ensure(nb * vb);
+  d.ensure(nb * vb);
+  s64.ensure(nb * vb);
+  shd.ensure(nb * 8);
+  out.assign(nb, SolveStats());
+  std::vector<double> bn;
+  {
+    DevBuf dd, w;
+    dd.ensure(nb * 16);
+    w.ensure((size_t)nb * 1024 * 16);
+    launch_batched_dot<double>(nb, n, b, n, b, n, true, dd.p, w.p, st);
+    std::vector<cplx> h(nb);
+    HIP_CHECK(hipMemcpyAsync(h.data(), dd.p, nb * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int r = 0; r < nb; ++r) bn.push_back(std::max(1e-300, std::sqrt(std::max(0.0, h[r].real()))));
+  }
+  std::vector<int> act(nb);
+  for (int r = 0; r < nb; ++r) act[r] = r;
+  const double tol_in = std::max(1e-5, tol);
+  double t0 = now_s();
+  const int max_outer = 12;
+  for (int outer = 0; outer < max_outer && !act.empty(); ++outer) {
+    int na = (int)act.size();
+    std::vector<double> sh(na);
+    for (int k = 0; k < na; ++k) {
+      sh[k] = shifts ? shifts[act[k]] : 0.0;
+      HIP_CHECK(hipMemcpyAsync((char*)Xa.p + k * vb, (char*)x + act[k] * vb, vb, hipMemcpyDeviceToDevice, st));
+      HIP_CHECK(hipMemcpyAsync((char*)Ba.p + k * vb, (const char*)b + act[k] * vb, vb, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), na * 8, hipMemcpyHostToDevice, st));
+    sigma64(side, na, Xa.p, s64.p);
+    launch_residual<double>(na, n, s64.p, shd.as<double>(), Xa.p, Ba.p, n, R64.p, st);
+    std::vector<double> rn;
+    vec_norms(*this, na, R64.p, rn);
+    std::vector<int> keep;
+    std::vector<int> keep_slot;
+    for (int k = 0; k < na; ++k) {
+      SolveStats& so = out[act[k]];
+      so.sigma_evals += 1;
+      so.residual = rn[k] / bn[act[k]];
+      so.seconds = now_s() - t0;
+      if (rn[k] <= tol * bn[act[k]]) {
+        so.converged = 1;
+      } else {
+        keep.push_back(act[k]);
+        keep_slot.push_back(k);
+      }
+    }
+    if (keep.empty()) break;
+    if (outer == max_outer - 1) break;
+    // compact the unconverged right-hand sides
+    int nk = (int)keep.size();
+    std::vector<double> shk(nk);
+    for (int q = 0; q < nk; ++q) {
+      int k = keep_slot[q];
+      shk[q] = sh[k];
+      if (q != k) {
+        HIP_CHECK(hipMemcpyAsync((char*)R64.p + q * vb, (char*)R64.p + k * vb, vb, hipMemcpyDeviceToDevice, st));
+        HIP_CHECK(hipMemcpyAsync((char*)Xa.p + q * vb, (char*)Xa.p + k * vb, vb, hipMemcpyDeviceToDevice, st));
+      }
+    }
+    HIP_CHECK(hipMemcpyAsync(shd.p, shk.data(), nk * 8, hipMemcpyHostToDevice, st));
+    // correction equation (A + s) d = -R64 with FP32 products
+    launch_jacobi(nk, n, D.as<double>(), shd.as<double>(), nullptr, R64.p, d.p, nullptr, st);
+    std::vector<SolveStats> inner;
+    diis_solve(*this, nk, shk.data(), R64.p, d.p, tol_in, cfg.maxit,
+               [&](int na2, const double* sh2, const void* X, const void* Bw, void* R) {
+                 sigma32(side, na2, X, sig.p);
+                 launch_residual<float>(na2, n, sig.p, sh2, X, Bw, n, R, st);
+               },
+               inner, 1);
+    // x += d
+    for (int q = 0; q < nk; ++q) {
+      launch_residual<double>(1, n, (char*)d.p + q * vb, nullptr, nullptr, (char*)Xa.p + q * vb, n,
+                              (char*)Xa.p + q * vb, st);
+      HIP_CHECK(hipMemcpyAsync((char*)x + keep[q] * vb, (char*)Xa.p + q * vb, vb, hipMemcpyDeviceToDevice, st));
+      out[keep[q]].iterations += inner[q].iterations;
+      out[keep[q]].sigma_evals += inner[q].sigma_evals;
+    }
+    act = keep;
+  }
+  sync();
+}
+
+void Context::solve_lambda(SolveStats& so) {
+  require_sizes();
+  LRCC_REQUIRE(have_t, LRCC_E_STATE, "no ground-state amplitudes (call lrcc_solve_ground first)");
+  ensure_primal(64);
+  const size_t vb = n * 16;
+  DevBuf e0;
+  e0.ensure(vb);
+  x64->run(P.eta0, 1);
+  launch_copy_rows<double, double>(1, n1, x64->ptr(P.e_gt1), n1, e0.p, n, st);
+  launch_copy_rows<double, double>(1, n2, x64->ptr(P.e_gt2p), n2, (char*)e0.p + n1 * 16, n, st);
+  lam.ensure(vb);
+  launch_jacobi(1, n, D.as<double>(), nullptr, nullptr, e0.p, lam.p, nullptr, st);
+  std::vector<SolveStats> ss;
+  solve_linear(Side::Left, 1, nullptr, e0.p, lam.p, 64, cfg.tol_residual, ss);
+  so = ss[0];
+  have_lam = true;
+  gradL_ready = 0;
+  have_alpha = false;
+  LRCC_REQUIRE(so.converged, LRCC_E_NOCONV, "Lambda amplitudes did not converge");
+}
+
+void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& per) {
+  require_sizes();
+  LRCC_REQUIRE(have_lam, LRCC_E_STATE, "no Lambda amplitudes (call lrcc_solve_lambda first)");
+  LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
+  LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
+  // a frequency on a denominator makes (A -/+ w) singular in the Jacobi metric
+  {
+    std::vector<double> hD(n);
+    HIP_CHECK(hipMemcpy(hD.data(), D.p, n * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < nw; ++k)
+      for (int64_t i = 0; i < n; ++i)
+        LRCC_REQUIRE(std::abs(hD[i] - std::abs(om[k])) >= 1e-8, LRCC_E_SINGULAR,
+                     "frequency " + std::to_string(om[k]) + " lies on a denominator pole");
+  }
+  const int prec = cfg.precision == LRCC_MIXED ? 32 : 64;
+  const size_t vb = n * 16;
+  const int nrhs = nw * ncomp;
+  omegas.assign(om, om + nw);
+  xi.ensure(ncomp * vb);
+  eta.ensure(ncomp * vb);
+  xi_vectors(xi.p);
+  std::vector<int> comps(ncomp);
+  for (int c = 0; c < ncomp; ++c) comps[c] = c;
+  hvp(ncomp, comps.data(), nullptr, eta.p);
+  X.ensure(nrhs * vb);
+  Y.ensure(nrhs * vb);
+  per.assign(2 * nrhs, SolveStats());
+  const int chunk = cfg.rhs_chunk > 0 ? std::min(cfg.rhs_chunk, nrhs) : nrhs;
+  DevBuf bc, shd;
+  bc.ensure(chunk * vb);
+  shd.ensure(chunk * 8);
+  for (int side = 0; side < 2; ++side) {
+    for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+      int nc = std::min(chunk, nrhs - c0);
+      std::vector<double> sh(nc);
+      std::vector<int> cp(nc);
+      for (int q = 0; q < nc; ++q) {
+        int r = c0 + q;
+        cp[q] = r % ncomp;
+        sh[q] = side == 0 ? -omegas[r / ncomp] : omegas[r / ncomp];
+      }
+      void* xc = (char*)(side == 0 ? X.p : Y.p) + c0 * vb;
+      if (side == 0) {
+        for (int q = 0; q < nc; ++q)
+          HIP_CHECK(hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
+      } else {
+        hvp(nc, cp.data(), (char*)X.p + c0 * vb, bc.p);  // eta^B + F X^B
+      }
+      HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
+      launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);
+      std::vector<SolveStats> ss;
+      solve_linear(side == 0 ? Side::Right : Side::Left, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
+      for (int q = 0; q < nc; ++q) per[side * nrhs + c0 + q] = ss[q];
+    }
+  }
+  // alpha_AB(w) = -1/2 [f_AB + conj f_BA],  f_AB = Y^B . xi^A + eta^A . X^B
+  DevBuf d1, d2, w;
+  d1.ensure(nrhs * 16);
+  d2.ensure(nrhs * 16);
+  w.ensure((size_t)nrhs * 1024 * 16);
+  std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
+  for (int a = 0; a < ncomp; ++a) {
+    launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
+    std::vector<cplx> h(nrhs);
+    HIP_CHECK(hipMemcpyAsync(h.data(), d1.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int r = 0; r < nrhs; ++r) fy[r * ncomp + a] = h[r];
+    launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, d2.p, w.p, st);
+    HIP_CHECK(hipMemcpyAsync(h.data(), d2.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int r = 0; r < nrhs; ++r) fx[r * ncomp + a] = h[r];
+  }
+  alpha.assign(nw * ncomp * ncomp, 0.0);
+  for (int k = 0; k < nw; ++k) {
+    std::vector<cplx> f(ncomp * ncomp);
+    for (int a = 0; a < ncomp; ++a)
+      for (int bb = 0; bb < ncomp; ++bb) {
+        int r = k * ncomp + bb;
+        f[a * ncomp + bb] = fy[r * ncomp + a] + fx[r * ncomp + a];
+      }
+    for (int a = 0; a < ncomp; ++a)
+      for (int bb = 0; bb < ncomp; ++bb)
+        alpha[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
+  }
+  have_alpha = true;
+  bool all = true;
+  for (auto& s : per) all = all && s.converged;
+  LRCC_REQUIRE(all, LRCC_E_NOCONV, "some response equations did not converge");
+}
+
+}  // namespace lrcc

@@ -1,0 +1,140 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every test here needs an MI355X and calls liblrcc.so; the expected values
+come from oracle/ (or, for the GEMM kernel, from a plain complex128 matmul
+on the host).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2503_23144_amd.synth import make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _lrcc():
+    from paper_2503_23144_amd import lrcc
+    return lrcc
+
+
+def _rand(rng, *shape, scale=1.0):
+    return scale * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+def _relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# ------------------------------------------------------------------ GEMM kernel
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(37, 53, 29), (128, 64, 100), (1, 5, 7), (200, 130, 257)])
+def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
+    lrcc = _lrcc()
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = _rand(rng, *((k, m) if ta else (m, k)))
+    B = _rand(rng, *((n, k) if tb else (k, n)))
+    C0 = _rand(rng, m, n)
+    al, be = 0.7 - 0.3j, 0.25 + 0.5j
+    ref = al * ((A.T if ta else A) @ (B.T if tb else B)) + be * C0
+    dev = torch.device("cuda:0")
+    Ad = torch.tensor(A, dtype=dtype, device=dev)
+    Bd = torch.tensor(B, dtype=dtype, device=dev)
+    Cd = torch.tensor(C0, dtype=dtype, device=dev)
+    lrcc.gemm(Ad, Bd, Cd, transa=bool(ta), transb=bool(tb), alpha=al, beta=be)
+    torch.cuda.synchronize()
+    got = Cd.cpu().numpy().astype(np.complex128)
+    # normwise bound: |A||B| k eps
+    scale = np.sqrt(k) * np.abs(A).max() * np.abs(B).max() + np.abs(C0).max()
+    eps = 1e-15 if dtype == torch.complex128 else 2e-7
+    assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k)
+
+
+# ------------------------------------------------------------------ helpers
+def _ctx(inp, precision="fp64", tol=1e-11, **kw):
+    lrcc = _lrcc()
+    c = lrcc.Context(precision=precision, tol=tol, **kw)
+    c.load_df(inp.o, inp.v, inp.B)
+    c.load_fock(inp.fock)
+    c.load_dipoles(inp.mu)
+    return c
+
+
+def _oracle_problem(inp):
+    from oracle.response import Problem
+    return Problem.from_arrays(inp.B, inp.fock, inp.mu, inp.o)
+
+
+CASES = [("c1", 4, 16, 32, 8.0, 0), ("ragged", 3, 17, 11, 8.0, 5)]
+
+
+# ------------------------------------------------------------------ sigma parity
+@pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
+def test_residual_and_sigmas_match_oracle(name, o, v, naux, scale, seed):
+    """Omega(t), A X and lambda A at random (non-converged) complex t."""
+    from oracle.response import left_sigma, right_sigma
+    inp = make_inputs(o, v, naux, seed=seed)
+    inp.B = inp.B * scale
+    c = _ctx(inp)
+    P = _oracle_problem(inp)
+    rng = np.random.default_rng(seed + 100)
+    n = P.lay.n
+    assert c.n == n
+    t = _rand(rng, n, scale=0.05)
+    R = c.sigma("residual", t)
+    ref = P.omega(torch.as_tensor(t)).numpy()
+    assert _relerr(R, ref) < 1e-12
+    c.set_amplitudes(_lrcc().AMP_T, t)
+    X = _rand(rng, 3, n)
+    shifts = np.array([0.0, -0.2, 0.3])
+    for side, fn in (("right", right_sigma), ("left", left_sigma)):
+        got = c.sigma(side, X, shifts=shifts)
+        for r in range(3):
+            ref = fn(P, torch.as_tensor(t), torch.as_tensor(X[r])).resolve_conj().numpy() + shifts[r] * X[r]
+            assert _relerr(got[r], ref) < 1e-12, (side, r)
+    # the FP32 (3M MFMA) products agree to single precision
+    got32 = c.sigma("right", X, precision="mixed")
+    ref64 = c.sigma("right", X)
+    assert _relerr(got32, ref64) < 1e-5
+
+
+# ------------------------------------------------------------------ full pipeline
+@pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
+def test_polarizability_fp64_matches_oracle(name, o, v, naux, scale, seed):
+    from oracle.response import lr_ccsd
+    inp = make_inputs(o, v, naux, seed=seed)
+    inp.B = inp.B * scale
+    omegas = [0.0, 0.11]
+    ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
+    c = _ctx(inp, tol=1e-11)
+    e, st = c.solve_ground()
+    assert st["converged"] == 1
+    assert abs(e - ref.ecorr) < 1e-10 * abs(ref.ecorr)
+    assert _relerr(c.get_amplitudes(_lrcc().AMP_T), ref.t.numpy()) < 1e-9
+    c.solve_lambda()
+    assert _relerr(c.get_amplitudes(_lrcc().AMP_LAMBDA), ref.lam.numpy()) < 1e-9
+    per = c.solve_response(omegas)
+    assert all(s["converged"] for s in per)
+    al = c.alpha(len(omegas))
+    assert _relerr(al, ref.alpha) < 1e-8
+    # X and Y of one right-hand side
+    X = c.get_amplitudes(_lrcc().AMP_X, 1 * 3 + 2)
+    assert _relerr(X, ref.X[(1, 2)].numpy()) < 1e-8
+    Y = c.get_amplitudes(_lrcc().AMP_Y, 1 * 3 + 2)
+    assert _relerr(Y, ref.Y[(1, 2)].numpy()) < 1e-8
+
+
+def test_polarizability_mixed_precision_close_to_fp64():
+    inp = make_inputs(4, 16, 32, seed=0)
+    inp.B = inp.B * 8.0
+    omegas = [0.0, 0.2]
+    res = {}
+    for prec in ("fp64", "mixed"):
+        c = _ctx(inp, precision=prec, tol=1e-10)
+        c.solve_ground()
+        c.solve_lambda()
+        c.solve_response(omegas)
+        res[prec] = c.alpha(len(omegas))
+    assert _relerr(res["mixed"], res["fp64"]) < 1e-6
