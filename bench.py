@@ -1,0 +1,193 @@
+"""Benchmark: LR-CCSD Jacobian-product throughput on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic system:
+integral blocks from density-fitting factors, ground-state T, Lambda, the
+batched X(w)/Y(w) solves for 3 dipole directions x n_w frequencies, and the
+polarizability tensor.  `value` is Jacobian-vector products (sigma
+evaluations, right or left, per right-hand side) completed per second over
+the timed steps, for the mixed-precision batched solver (FP32 3M products on
+MFMA, FP64 residuals/updates).  The same pass in plain FP64 is timed once
+beside it, and the alpha tensors of the two are compared.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LR sigma evals/s (3 dirs×nω) + ladder TFLOP/s; FP32-3M vs FP64 at fixed α err"
+PEAK = {"fp32": 157.3, "fp64": 78.6}  # dense MFMA TFLOP/s (MI355X)
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name") or line.startswith("Socket(s)") or line.startswith("Thread(s) per core"):
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
+def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0):
+    """One pass of the hot path; returns counts, alpha and phase times."""
+    ph = {}
+    t = time.perf_counter()
+    c = lrcc.Context(precision=precision, tol=tol, rhs_chunk=chunk)
+    c.set_timing(timing)
+    c.load_df(inp.o, inp.v, inp.B)
+    c.load_fock(inp.fock)
+    c.load_dipoles(inp.mu)
+    ph["integrals"] = time.perf_counter() - t
+    t = time.perf_counter()
+    e, st0 = c.solve_ground()
+    ph["ground"] = time.perf_counter() - t
+    t = time.perf_counter()
+    st1 = c.solve_lambda()
+    ph["lambda"] = time.perf_counter() - t
+    t = time.perf_counter()
+    per = c.solve_response(inp.omegas)
+    ph["response"] = time.perf_counter() - t
+    resp_sig = sum(s["sigma_evals"] for s in per)
+    sig = st0["sigma_evals"] + st1["sigma_evals"] + resp_sig
+    alpha = c.alpha(len(inp.omegas))
+    ladder = c.kernel_time(0) if timing else None
+    allg = c.kernel_time(1) if timing else None
+    c.close()
+    return dict(ecorr=e, sigma_evals=sig, resp_sigma_evals=resp_sig, alpha=alpha, ladder=ladder, gemm=allg,
+                iters=[s["iterations"] for s in per], phases=ph)
+
+
+def cpu_baseline(inp, budget_s=25.0):
+    """The oracle, as it stands, timed on the host: right-sigma (A X)
+    evaluations at the workload's shapes, one right-hand side at a time."""
+    import numpy as np
+    import torch
+
+    from oracle.response import Problem, right_sigma, solve_ground
+    P = Problem.from_arrays(inp.B, inp.fock, inp.mu, inp.o)
+    rng = np.random.default_rng(7)
+    n = P.lay.n
+    t = torch.as_tensor(0.01 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))
+    X = torch.as_tensor(rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    P.g("vvvv")  # integral build is not timed
+    right_sigma(P, t, X)  # warm
+    k, t0 = 0, time.perf_counter()
+    while True:
+        right_sigma(P, t, X)
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "sigma evals/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{k} right-sigma (A X) evaluations of the FP64 oracle at o={inp.o}, v={inp.v}, one RHS each, "
+                      f"integral build excluded ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--fp64", default="both", choices=["none", "plain", "batched", "both"],
+                    help="FP64 comparison passes: plain (one RHS per product) and/or batched")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    # residual tolerances that meet each path's alpha target (mixed: 1e-6
+    # relative on alpha; FP64: 1e-10 on residuals, 1e-8 on alpha)
+    ap.add_argument("--tol", type=float, default=1e-6, help="mixed-precision residual tolerance")
+    ap.add_argument("--tol64", type=float, default=1e-10, help="FP64 residual tolerance")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2503_23144_amd import lrcc
+    from paper_2503_23144_amd.synth import CONFIGS, config_inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    inp = config_inputs(args.workload)
+    cfg = CONFIGS[args.workload]
+    print(f"[bench] workload {args.workload}: o={inp.o} v={inp.v} naux={inp.naux} "
+          f"nw={len(inp.omegas)} gap={inp.gap:.3f}", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        r = run_pass(lrcc, inp, "mixed", args.tol)
+        print(f"[bench] warmup {w}: sigma evals {r['sigma_evals']}", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sig = 0
+    last = None
+    for s in range(args.steps):
+        last = run_pass(lrcc, inp, "mixed", args.tol, timing=True)
+        sig += last["sigma_evals"]
+        print(f"[bench] step {s}: sigma evals {last['sigma_evals']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = sig / dt
+
+    ladder_ms, ladder_n, ladder_fl = last["ladder"]
+    gemm_ms, gemm_n, gemm_fl = last["gemm"]
+    ladder_avg_s = ladder_ms / 1e3 / max(ladder_n, 1)
+    ladder_tf = ladder_fl / max(ladder_ms / 1e3, 1e-30) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "sigma evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 products (3M, FP32 MFMA) + c128 residuals", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: o={cfg['o']} v={cfg['v']} naux={cfg['naux']}, 3 dipole directions "
+                               f"x {len(cfg['omegas'])} omegas in [{min(cfg['omegas']):.2f},{max(cfg['omegas']):.2f}] Ha, "
+                               "full pass (integrals, T, Lambda, X, Y, alpha)",
+                   "precision": "mixed", "tol_residual": args.tol, "tol_residual_fp64": args.tol64},
+        "ladder_tflops": ladder_tf,
+        "gemm_all_tflops": gemm_fl / max(gemm_ms / 1e3, 1e-30) / 1e12, "gemm_all_ms": gemm_ms, "gemm_launches": gemm_n,
+        "roofline": {"bound": "mfma", "achieved": ladder_tf, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                     "frac": ladder_tf / PEAK["fp32"], "traffic": None,
+                     "kernel": "zgemm_kernel<float, false, true, 1> (packed vvvv ladder, 3M)",
+                     "avg_launch_ms": 1e3 * ladder_avg_s, "launches": ladder_n},
+    }
+    out["phases_s"] = last["phases"]
+    out["response_sigma_evals_per_s"] = last["resp_sigma_evals"] / last["phases"]["response"]
+    if args.fp64 != "none":
+        # plain FP64 solver: one right-hand side per Jacobian product; and FP64 batched
+        runs = [r for r in (("fp64_plain", 1), ("fp64_batched", 0)) if args.fp64 in ("both", r[0][5:])]
+        for name, chunk in runs:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r64 = run_pass(lrcc, inp, "fp64", args.tol64, timing=True, chunk=chunk)
+            torch.cuda.synchronize()
+            d64 = time.perf_counter() - t1
+            err = float(np.abs(last["alpha"] - r64["alpha"]).max() / np.abs(r64["alpha"]).max())
+            l64 = r64["ladder"]
+            out[name] = {"sigma_evals_per_s": r64["sigma_evals"] / d64, "seconds": d64,
+                         "response_sigma_evals_per_s": r64["resp_sigma_evals"] / r64["phases"]["response"],
+                         "phases_s": r64["phases"],
+                         "ladder_tflops": l64[2] / max(l64[0] / 1e3, 1e-30) / 1e12,
+                         "alpha_rel_diff_mixed_vs_this": err}
+            print(f"[bench] {name}: {d64:.1f} s", file=sys.stderr, flush=True)
+        for name, _ in runs:
+            out[f"mixed_over_{name}_sigma_rate"] = value / out[name]["sigma_evals_per_s"]
+            out[f"mixed_over_{name}_time"] = out[name]["seconds"] / (dt / args.steps)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inp)
+        out["cpu_baseline"]["host"] = host_info()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

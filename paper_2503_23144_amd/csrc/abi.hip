@@ -221,9 +221,10 @@ int lrcc_sigma(lrcc_ctx* ctx, int side, int nvec, const double* shifts, const vo
       if (precision == LRCC_FP64) {
         c.sigma64(sd, nvec, din.p, dout.p);
       } else {
+        // FP32 coupling products plus the FP64 diagonal D X
         s32.ensure(nvec * c.n * 8);
         c.sigma32(sd, nvec, din.p, s32.p);
-        lrcc::launch_s2d(nvec * c.n, s32.p, dout.p, c.st);
+        lrcc::launch_residual<float>(nvec, c.n, s32.p, nullptr, din.p, nullptr, 0, dout.p, c.st, c.D.as<double>());
       }
       if (shifts) {
         shd.ensure(nvec * 8);

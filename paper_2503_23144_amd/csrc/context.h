@@ -107,11 +107,15 @@ struct Context {
   void sigma32(Side side, int nb, const void* in64, void* out32);  // FP64 in, FP32 out
   void xi_vectors(void* out);                                       // [ncomp][n]
   void hvp(int nb, const int* comp, const void* Xdt, void* out);    // eta^B + F X (Xdt may be null)
+  void fx32(int nb, const void* X64, void* out32);                  // F X with FP32 products
+  void residual32(const void* tvec, void* R);                       // Omega(t) = D t (FP64) + coupling (FP32)
+  int gradL32_ready = 0;
 
   // generic batched linear solve: for r < nb, (op + s_r) x_r = -b_r
   void solve_linear(Side side, int nb, const double* shifts, const void* b, void* x, int prec, double tol,
                     std::vector<SolveStats>& st_out);
 
+  int rhs_chunk_for(int nrhs, int prec);
   int64_t sigma_count = 0;
   void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
   void require_sizes() const;

@@ -69,7 +69,9 @@ __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& t
   tn = id / nbm;
 }
 
-template <typename T, bool TA, bool TB>
+// KIND only separates kernel symbols (0: general contraction, 1: the packed
+// vvvv ladder), so that profiles attribute time to the ladder.
+template <typename T, bool TA, bool TB, int KIND>
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
@@ -234,30 +236,34 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st) {
+                 hipStream_t st, int kind) {
   if (m <= 0 || n <= 0) return;
   using V2 = typename cpx<T>::type;
   int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
   LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
   dim3 grid((unsigned)nb), block(NT);
-#define GO(TA_, TB_)                                                                                       \
-  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_>), grid, block, 0, st, m, n, k, (T)are, (T)aim, (const V2*)A, \
+#define GO(TA_, TB_, K_)                                                                                     \
+  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, K_>), grid, block, 0, st, m, n, k, (T)are, (T)aim, (const V2*)A, \
                      lda, (const V2*)B, ldb, (T)bre, (T)bim, (V2*)C, ldc)
-  if (!ta && !tb)
-    GO(false, false);
+  if (kind == 1 && !ta && tb)
+    GO(false, true, 1);
+  else if (kind == 1 && !ta && !tb)
+    GO(false, false, 1);
+  else if (!ta && !tb)
+    GO(false, false, 0);
   else if (!ta && tb)
-    GO(false, true);
+    GO(false, true, 0);
   else if (ta && !tb)
-    GO(true, false);
+    GO(true, false, 0);
   else
-    GO(true, true);
+    GO(true, true, 0);
 #undef GO
   HIP_CHECK(hipGetLastError());
 }
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
-                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t);
+                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int);
 template void launch_gemm<float>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
-                                 const void*, int64_t, double, double, void*, int64_t, hipStream_t);
+                                 const void*, int64_t, double, double, void*, int64_t, hipStream_t, int);
 
 }  // namespace lrcc

@@ -67,16 +67,20 @@ void launch_gram(int64_t nvec, int m, int64_t n, const void* h, int64_t hs, cons
 
 // Dense complex GEMM C = alpha op(A) op(B) + beta C (no conjugation).
 // FP64: 4 real MFMA products per complex product; FP32: 3 (Gauss).
+// kind 1 marks the packed-vvvv ladder (a separate kernel symbol).
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st);
+                 hipStream_t st, int kind = 0);
 
 // Solver kernels (FP64 vectors, nvec right-hand sides of length n).
-// R = s_r * X + b_r + sig (sig in Ts), optionally returning R.
+// R = sig + (D + s_r) X + b_r  (sig in Ts; D, shift, X, b may be null = 0).
 template <typename Ts>
 void launch_residual(int64_t nvec, int64_t n, const void* sig, const double* shift_dev, const void* X,
-                     const void* b, int64_t bstride, void* R, hipStream_t st);
+                     const void* b, int64_t bstride, void* R, hipStream_t st, const double* D = nullptr);
+// p[i*(n+1)] = 0 for i < n (diagonal of an n x n complex matrix)
+template <typename T>
+void launch_zero_diag(void* p, int64_t n, hipStream_t st);
 // Xn = X - R / (D + s_r);  E = Xn - X  (either output may be null)
 void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X,
                    const void* R, void* Xn, void* E, hipStream_t st);

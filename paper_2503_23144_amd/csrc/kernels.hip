@@ -329,15 +329,17 @@ void launch_gram(int64_t nvec, int m, int64_t n, const void* h, int64_t hs, cons
 template <typename Ts>
 __global__ void __launch_bounds__(256) residual_kernel(int64_t n, const typename cplx2<Ts>::type* sig,
                                                        const double* __restrict__ shift, const double2* X,
-                                                       const double2* b, int64_t bstride, double2* R) {
+                                                       const double2* b, int64_t bstride, double2* R,
+                                                       const double* __restrict__ D) {
   int64_t r = blockIdx.y;
   double s = shift ? shift[r] : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     int64_t k = r * n + i;
-    double re = (double)sig[k].x, im = (double)sig[k].y;
+    double re = sig ? (double)sig[k].x : 0.0, im = sig ? (double)sig[k].y : 0.0;
     if (X) {
-      re += s * X[k].x;
-      im += s * X[k].y;
+      double f = s + (D ? D[i] : 0.0);
+      re += f * X[k].x;
+      im += f * X[k].y;
     }
     if (b) {
       re += b[r * bstride + i].x;
@@ -349,12 +351,25 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, const typename
 
 template <typename Ts>
 void launch_residual(int64_t nvec, int64_t n, const void* sig, const double* shift_dev, const void* X,
-                     const void* b, int64_t bstride, void* R, hipStream_t st) {
+                     const void* b, int64_t bstride, void* R, hipStream_t st, const double* D) {
   if (nvec <= 0) return;
   unsigned gx = nblocks(n, 256, 4096);
   using C = typename cplx2<Ts>::type;
   hipLaunchKernelGGL(residual_kernel<Ts>, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, (const C*)sig, shift_dev,
-                     (const double2*)X, (const double2*)b, bstride, (double2*)R);
+                     (const double2*)X, (const double2*)b, bstride, (double2*)R, D);
+  LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void zero_diag_kernel(typename cplx2<T>::type* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i * (n + 1)] = {T(0), T(0)};
+}
+
+template <typename T>
+void launch_zero_diag(void* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(zero_diag_kernel<T>, dim3(nblocks(n)), dim3(256), 0, st, (typename cplx2<T>::type*)p, n);
   LAUNCH_CHECK();
 }
 
@@ -536,7 +551,8 @@ void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int6
   template void launch_batched_dot<T>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, bool,    \
                                       void*, void*, hipStream_t);                                            \
   template void launch_residual<T>(int64_t, int64_t, const void*, const double*, const void*, const void*,   \
-                                   int64_t, void*, hipStream_t);                                             \
+                                   int64_t, void*, hipStream_t, const double*);                              \
+  template void launch_zero_diag<T>(void*, int64_t, hipStream_t);                                            \
   template void launch_pack_vvvv<T>(int64_t, int64_t, int64_t, int64_t, const void*, void*, hipStream_t);
 INST(double)
 INST(float)

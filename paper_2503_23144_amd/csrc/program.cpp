@@ -517,6 +517,16 @@ void build_programs(CcPrograms& P) {
     P.h_out1 = tan.at(P.g_gt1);
     P.h_out2p = tan.at(P.g_gt2p);
     P.hvp = prune(m, hops, {P.h_out1, P.h_out2p});
+
+    std::map<int, int> tt;
+    P.f_dt1 = m.add("F(t1)", "ov", Role::Tangent, true);
+    P.f_dt2p = m.add("F(t2p)", "OV", Role::Tangent, true);
+    tt[P.t1] = P.f_dt1;
+    tt[P.t2p] = P.f_dt2p;
+    OpList fops = jvp(m, comb, tt, {P.g_gt1, P.g_gt2p}, "F");
+    P.f_out1 = tt.at(P.g_gt1);
+    P.f_out2p = tt.at(P.g_gt2p);
+    P.hvpt = prune(m, fops, {P.f_out1, P.f_out2p});
   }
 }
 

@@ -107,6 +107,7 @@ struct CcPrograms {
   OpList xi;        // dO along f -> mu                          (tangent in f, batched)
   OpList gradL;     // d/dt (E + lambda.Omega)                   (adjoint, unbatched)
   OpList hvp;       // tangent of gradL along (dt, df)           (batched)
+  OpList hvpt;      // tangent of gradL along dt only: F dt      (batched)
   // tensor ids
   int t1, t2p, foo, fov, fvo, fvv, O1, O2p, E, one;
   int r_dt1, r_dt2p, r_dO1, r_dO2p;           // right
@@ -115,6 +116,7 @@ struct CcPrograms {
   int x_df[4], x_dO1, x_dO2p;                 // xi (df in foo, fov, fvo, fvv order)
   int g_lam1, g_lam2p, g_gt1, g_gt2p;         // gradL
   int h_dt1, h_dt2p, h_df[4], h_out1, h_out2p;  // hvp
+  int f_dt1, f_dt2p, f_out1, f_out2p;           // hvpt
 };
 void build_programs(CcPrograms& P);
 

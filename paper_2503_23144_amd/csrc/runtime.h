@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -50,7 +51,12 @@ class Executor {
   int max_batch() const { return max_nb_; }
   // Copy host/device data into an owned tensor (converting FP64 -> T).
   void upload(int id, const void* src_fp64, int nb = 1);
-  void run(const OpList& ops, int nb);
+  // Run a program at batch nb.  Batched tensors written by the program
+  // (except those listed in `keep`) are transient: they live in a pool whose
+  // buffers are reused once a tensor's last reader has run.
+  void run(const OpList& ops, int nb, const std::vector<int>& keep = {});
+  // Bytes of pooled transients plus kept batched tensors per right-hand side.
+  int64_t transient_bytes(const OpList& ops, int nb, const std::vector<int>& keep);
   void release_batched();
   size_t bytes_allocated() const;
 
@@ -74,6 +80,16 @@ class Executor {
   void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
             int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
             int64_t capC, bool ladder);
+
+  struct Plan {
+    std::vector<std::pair<int, int>> slot;  // (tensor, pool slot) of each transient
+    std::vector<int64_t> slot_elems;
+  };
+  const Plan& plan_for(const OpList& ops, int nb, const std::vector<int>& keep);
+  std::map<std::pair<const OpList*, int>, Plan> plans_;
+  std::vector<void*> pool_;
+  std::vector<int64_t> pool_cap_;
+  std::vector<char> pooled_;
 
   const Module& m_;
   Dims d_;

@@ -36,6 +36,7 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   buf_.assign(n, nullptr);
   cap_.assign(n, 0);
   bound_.assign(n, 0);
+  pooled_.assign(n, 0);
   scr_.assign(4, nullptr);
   scr_cap_.assign(4, 0);
   HIP_CHECK(hipMalloc(&dot_out_, 64));
@@ -45,8 +46,10 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
 template <typename T>
 Executor<T>::~Executor() {
   for (size_t k = 0; k < buf_.size(); ++k)
-    if (buf_[k] && !bound_[k]) (void)hipFree(buf_[k]);
+    if (buf_[k] && !bound_[k] && !pooled_[k]) (void)hipFree(buf_[k]);
   for (void* p : scr_)
+    if (p) (void)hipFree(p);
+  for (void* p : pool_)
     if (p) (void)hipFree(p);
   (void)hipFree(dot_out_);
   (void)hipFree(dot_work_);
@@ -67,7 +70,7 @@ int64_t Executor<T>::elems(int id, int nb) const {
 
 template <typename T>
 void* Executor<T>::ptr(int id) {
-  if (bound_[id]) return buf_[id];
+  if (bound_[id] || pooled_[id]) return buf_[id];
   int64_t need = elems(id, max_nb_);
   if (cap_[id] < need) {
     if (buf_[id]) {
@@ -83,6 +86,7 @@ void* Executor<T>::ptr(int id) {
 
 template <typename T>
 void Executor<T>::bind(int id, void* p) {
+  LRCC_REQUIRE(!pooled_[id], LRCC_E_INTERNAL, "cannot bind a pooled transient");
   if (buf_[id] && !bound_[id]) {
     HIP_CHECK(hipStreamSynchronize(st_));
     HIP_CHECK(hipFree(buf_[id]));
@@ -111,19 +115,33 @@ template <typename T>
 void Executor<T>::release_batched() {
   HIP_CHECK(hipStreamSynchronize(st_));
   for (size_t k = 0; k < buf_.size(); ++k)
-    if (m_[k].batched && buf_[k] && !bound_[k]) {
+    if (m_[k].batched && buf_[k] && !bound_[k] && !pooled_[k]) {
       HIP_CHECK(hipFree(buf_[k]));
       buf_[k] = nullptr;
       cap_[k] = 0;
     }
+  for (size_t s = 0; s < pool_.size(); ++s)
+    if (pool_[s]) {
+      HIP_CHECK(hipFree(pool_[s]));
+      pool_[s] = nullptr;
+      pool_cap_[s] = 0;
+    }
+  for (size_t k = 0; k < buf_.size(); ++k)
+    if (pooled_[k]) {
+      buf_[k] = nullptr;
+      cap_[k] = 0;
+      pooled_[k] = 0;
+    }
+  plans_.clear();
 }
 
 template <typename T>
 size_t Executor<T>::bytes_allocated() const {
   size_t s = 0;
   for (size_t k = 0; k < buf_.size(); ++k)
-    if (!bound_[k]) s += cap_[k] * sizeof(T) * 2;
+    if (!bound_[k] && !pooled_[k]) s += cap_[k] * sizeof(T) * 2;
   for (size_t c : scr_cap_) s += c;
+  for (int64_t c : pool_cap_) s += c * sizeof(T) * 2;
   return s;
 }
 
@@ -268,7 +286,7 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
     e0 = get_event();
     HIP_CHECK(hipEventRecord(e0, st_));
   }
-  launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_);
+  launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0);
   if (timing_) {
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));
@@ -521,9 +539,89 @@ void Executor<T>::unpack(const Op& op, int nb) {
 }
 
 template <typename T>
-void Executor<T>::run(const OpList& ops, int nb) {
+const typename Executor<T>::Plan& Executor<T>::plan_for(const OpList& ops, int nb, const std::vector<int>& keep) {
+  auto key = std::make_pair(&ops, nb);
+  auto it = plans_.find(key);
+  if (it != plans_.end()) return it->second;
+  const int nt = (int)m_.tensors.size();
+  std::vector<int> first(nt, -1), last(nt, -1);
+  std::vector<char> is_keep(nt, 0);
+  for (int k : keep) is_keep[k] = 1;
+  for (int k = 0; k < (int)ops.size(); ++k) {
+    const Op& op = ops[k];
+    if (first[op.out] < 0) first[op.out] = k;
+    last[op.out] = std::max(last[op.out], k);
+    if (op.a >= 0) last[op.a] = std::max(last[op.a], k);
+    if (op.b >= 0) last[op.b] = std::max(last[op.b], k);
+  }
+  Plan pl;
+  std::vector<int> slot_of(nt, -1);
+  std::vector<char> busy;
+  for (int k = 0; k < (int)ops.size(); ++k) {
+    int t = ops[k].out;
+    if (first[t] == k && m_[t].batched && !is_keep[t] && !bound_[t]) {
+      int64_t need = elems(t, nb);
+      int best = -1;
+      for (int s = 0; s < (int)pl.slot_elems.size(); ++s)
+        if (!busy[s] && (best < 0 || std::abs(pl.slot_elems[s] - need) < std::abs(pl.slot_elems[best] - need)))
+          best = s;
+      if (best < 0) {
+        best = (int)pl.slot_elems.size();
+        pl.slot_elems.push_back(0);
+        busy.push_back(0);
+      }
+      pl.slot_elems[best] = std::max(pl.slot_elems[best], need);
+      busy[best] = 1;
+      slot_of[t] = best;
+      pl.slot.push_back({t, best});
+    }
+    // release transients whose last use is this op
+    const int used[3] = {ops[k].out, ops[k].a, ops[k].b};
+    for (int u : used)
+      if (u >= 0 && slot_of[u] >= 0 && last[u] == k) busy[slot_of[u]] = 0;
+  }
+  return plans_.emplace(key, std::move(pl)).first->second;
+}
+
+template <typename T>
+int64_t Executor<T>::transient_bytes(const OpList& ops, int nb, const std::vector<int>& keep) {
+  const Plan& pl = plan_for(ops, nb, keep);
+  int64_t e = 0;
+  for (int64_t x : pl.slot_elems) e += x;
+  for (int k : keep)
+    if (m_[k].batched) e += elems(k, nb);
+  return e * 2 * (int64_t)sizeof(T);
+}
+
+template <typename T>
+void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
   LRCC_REQUIRE(nb >= 1 && nb <= max_nb_, LRCC_E_INTERNAL, "batch exceeds executor maximum");
   g_nb = nb;
+  const Plan& pl = plan_for(ops, nb, keep);
+  if (pool_.size() < pl.slot_elems.size()) {
+    pool_.resize(pl.slot_elems.size(), nullptr);
+    pool_cap_.resize(pl.slot_elems.size(), 0);
+  }
+  for (size_t s = 0; s < pl.slot_elems.size(); ++s)
+    if (pool_cap_[s] < pl.slot_elems[s]) {
+      if (pool_[s]) {
+        HIP_CHECK(hipStreamSynchronize(st_));
+        HIP_CHECK(hipFree(pool_[s]));
+        pool_[s] = nullptr;
+      }
+      HIP_CHECK(hipMalloc(&pool_[s], pl.slot_elems[s] * sizeof(T) * 2));
+      pool_cap_[s] = pl.slot_elems[s];
+    }
+  for (auto& ts : pl.slot) {
+    int t = ts.first;
+    if (buf_[t] && !bound_[t] && !pooled_[t]) {  // drop a private buffer from earlier runs
+      HIP_CHECK(hipStreamSynchronize(st_));
+      HIP_CHECK(hipFree(buf_[t]));
+    }
+    buf_[t] = pool_[ts.second];
+    cap_[t] = pool_cap_[ts.second];
+    pooled_[t] = 1;
+  }
   for (const Op& op : ops) {
     switch (op.kind) {
       case OpKind::Contract: contract(op, nb); break;

@@ -96,6 +96,10 @@ static void ensure_x32(Context& c) {
     if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))
       launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
   }
+  if (c.have_fock) {
+    launch_zero_diag<float>(c.x32->ptr(c.P.foo), c.o, c.st);
+    launch_zero_diag<float>(c.x32->ptr(c.P.fvv), c.v, c.st);
+  }
   c.sync();
 }
 
@@ -105,6 +109,10 @@ void Context::upload_fock_blocks() {
   for (int k = 0; k < 4; ++k) {
     launch_gather_block(1, nmo, p0[k], np[k], r0[k], nr[k], fock.p, x64->ptr(ids[k]), st);
     if (x32) launch_d2s(np[k] * nr[k], x64->ptr(ids[k]), x32->ptr(ids[k]), st);
+  }
+  if (x32) {  // the FP32 program carries only the off-diagonal part of f
+    launch_zero_diag<float>(x32->ptr(P.foo), o, st);
+    launch_zero_diag<float>(x32->ptr(P.fvv), v, st);
   }
 }
 
@@ -193,6 +201,7 @@ void Context::ensure_primal(int prec) {
     x32->bind(P.t2p, (char*)t32.p + n1 * 8);
     x32->run(P.residual, 1);
     primal32 = 1;
+    gradL32_ready = 0;
   }
 }
 
@@ -204,7 +213,7 @@ void Context::sigma64(Side side, int nb, const void* in, void* out) {
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, double>(nb, n1, in, n, x64->ptr(a1), n1, st);
   launch_copy_rows<double, double>(nb, n2, (const char*)in + n1 * 16, n, x64->ptr(a2), n2, st);
-  x64->run(r ? P.right : P.left, nb);
+  x64->run(r ? P.right : P.left, nb, {o1, o2});
   launch_copy_rows<double, double>(nb, n1, x64->ptr(o1), n1, out, n, st);
   launch_copy_rows<double, double>(nb, n2, x64->ptr(o2), n2, (char*)out + n1 * 16, n, st);
   sigma_count += nb;
@@ -218,7 +227,7 @@ void Context::sigma32(Side side, int nb, const void* in64, void* out32) {
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, float>(nb, n1, in64, n, x32->ptr(a1), n1, st);
   launch_copy_rows<double, float>(nb, n2, (const char*)in64 + n1 * 16, n, x32->ptr(a2), n2, st);
-  x32->run(r ? P.right : P.left, nb);
+  x32->run(r ? P.right : P.left, nb, {o1, o2});
   launch_copy_rows<float, float>(nb, n1, x32->ptr(o1), n1, out32, n, st);
   launch_copy_rows<float, float>(nb, n2, x32->ptr(o2), n2, (char*)out32 + n1 * 8, n, st);
   sigma_count += nb;
@@ -241,7 +250,7 @@ void Context::xi_vectors(void* out) {
   std::vector<int> comp(ncomp);
   for (int c = 0; c < ncomp; ++c) comp[c] = c;
   gather_mu_blocks(*this, ncomp, comp.data(), P.x_df);
-  x64->run(P.xi, ncomp);
+  x64->run(P.xi, ncomp, {P.x_dO1, P.x_dO2p});
   launch_copy_rows<double, double>(ncomp, n1, x64->ptr(P.x_dO1), n1, out, n, st);
   launch_copy_rows<double, double>(ncomp, n2, x64->ptr(P.x_dO2p), n2, (char*)out + n1 * 16, n, st);
 }
@@ -264,7 +273,7 @@ void Context::hvp(int nb, const int* comp, const void* Xdt, void* out) {
     launch_fill_zero<double>(x64->ptr(P.h_dt2p), nb * n2, st);
   }
   gather_mu_blocks(*this, nb, comp, P.h_df);
-  x64->run(P.hvp, nb);
+  x64->run(P.hvp, nb, {P.h_out1, P.h_out2p});
   launch_copy_rows<double, double>(nb, n1, x64->ptr(P.h_out1), n1, out, n, st);
   launch_copy_rows<double, double>(nb, n2, x64->ptr(P.h_out2p), n2, (char*)out + n1 * 16, n, st);
 }
@@ -279,6 +288,42 @@ static void vec_norms(Context& c, int nb, const void* v, std::vector<double>& ou
   c.sync();
   out.resize(nb);
   for (int r = 0; r < nb; ++r) out[r] = std::sqrt(std::max(0.0, h[r].real()));
+}
+
+void Context::residual32(const void* tvec, void* R) {
+  ensure_x32(*this);
+  t32.ensure(n * 8);
+  work.ensure(n * 16);
+  launch_d2s(n, tvec, t32.p, st);
+  x32->bind(P.t1, t32.p);
+  x32->bind(P.t2p, (char*)t32.p + n1 * 8);
+  x32->bind(P.O1, work.p);
+  x32->bind(P.O2p, (char*)work.p + n1 * 8);
+  x32->run(P.residual, 1);
+  x32->unbind(P.O1);
+  x32->unbind(P.O2p);
+  primal32 = 0;
+  gradL32_ready = 0;
+  launch_residual<float>(1, n, work.p, nullptr, tvec, nullptr, 0, R, st, D.as<double>());
+}
+
+void Context::fx32(int nb, const void* X64, void* out32) {
+  ensure_primal(32);
+  LRCC_REQUIRE(have_lam, LRCC_E_STATE, "no Lambda amplitudes (call lrcc_solve_lambda first)");
+  if (!gradL32_ready) {
+    lam32.ensure(n * 8);
+    launch_d2s(n, lam.p, lam32.p, st);
+    x32->bind(P.g_lam1, lam32.p);
+    x32->bind(P.g_lam2p, (char*)lam32.p + n1 * 8);
+    x32->run(P.gradL, 1);
+    gradL32_ready = 1;
+  }
+  x32->set_max_batch(nb);
+  launch_copy_rows<double, float>(nb, n1, X64, n, x32->ptr(P.f_dt1), n1, st);
+  launch_copy_rows<double, float>(nb, n2, (const char*)X64 + n1 * 16, n, x32->ptr(P.f_dt2p), n2, st);
+  x32->run(P.hvpt, nb, {P.f_out1, P.f_out2p});
+  launch_copy_rows<float, float>(nb, n1, x32->ptr(P.f_out1), n1, out32, n, st);
+  launch_copy_rows<float, float>(nb, n2, x32->ptr(P.f_out2p), n2, (char*)out32 + n1 * 8, n, st);
 }
 
 // ---------------------------------------------------------------- DIIS
@@ -327,6 +372,8 @@ static bool diis_coeffs(const std::vector<cplx>& G, int m, int cnt, const std::v
 
 struct SlotMeta {
   int rhs = -1;
+  int best_it = 0;
+  double best = 1e300;
   int cnt = 0;    // entries stored
   int next = 0;   // ring position of the next entry
   int iters = 0;
@@ -344,7 +391,8 @@ struct SlotMeta {
 using ResidFn = std::function<void(int, const double*, const void*, const void*, void*)>;
 
 static void diis_solve(Context& c, int nb, const double* shifts_host, const void* b, void* x, double tol, int maxit,
-                       const ResidFn& resid, std::vector<SolveStats>& stats, int sig_per_eval) {
+                       const ResidFn& resid, std::vector<SolveStats>& stats, int sig_per_eval,
+                       int stall = 0, double ref = -1.0) {
   const int64_t n = c.n;
   const int m = std::max(0, c.cfg.diis_size);
   const size_t vb = n * 16;
@@ -381,7 +429,7 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
   }
   for (int s = 0; s < nb; ++s) {
     meta[s].rhs = s;
-    meta[s].bnorm = b ? std::sqrt(std::max(0.0, hd[s].real())) : -1.0;
+    meta[s].bnorm = b ? std::sqrt(std::max(0.0, hd[s].real())) : ref;
     if (b && meta[s].bnorm == 0) meta[s].bnorm = 1e-300;
     meta[s].G.assign(std::max(m, 1) * std::max(m, 1), 0.0);
   }
@@ -428,9 +476,16 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
       for (int s = 0; s < std::min(na, 4); ++s) fprintf(stderr, " %.3e", meta[s].rn / meta[s].bnorm);
       fprintf(stderr, "\n");
     }
+    for (int s = 0; s < na; ++s)
+      if (meta[s].rn < 0.7 * meta[s].best) {
+        meta[s].best = meta[s].rn;
+        meta[s].best_it = it;
+      }
     for (int s = 0; s < na;) {
-      if (meta[s].rn <= tol * meta[s].bnorm) {
-        finalize(s, true);
+      bool conv = meta[s].rn <= tol * meta[s].bnorm;
+      bool stalled = stall > 0 && it - meta[s].best_it >= stall;
+      if (conv || stalled) {
+        finalize(s, conv);
         move_slot(na - 1, s);
         --na;
       } else {
@@ -489,9 +544,31 @@ void Context::solve_ground(double ecorr_out[2], SolveStats& so) {
   have_t = have_lam = have_alpha = false;
   primal64 = primal32 = gradL_ready = 0;
   std::vector<SolveStats> ss;
-  diis_solve(*this, 1, nullptr, nullptr, t.p, cfg.tol_residual, cfg.maxit,
-             [&](int, const double*, const void* X, const void*, void* R) { residual64(X, R, nullptr); }, ss, 0);
+  if (cfg.precision == LRCC_MIXED) {
+    // FP32 coupling terms with the FP64 diagonal until the iteration stalls
+    // or converges, then FP64 residuals finish (and certify) the solve.  The
+    // reference norm is that of the driving terms, ||Omega(0)||.
+    std::vector<double> r0;
+    work.ensure(n * 16);
+    DevBuf R0;
+    R0.ensure(n * 16);
+    residual64(t.p, R0.p, nullptr);
+    vec_norms(*this, 1, R0.p, r0);
+    double ref = std::max(r0[0], 1e-300);
+    std::vector<SolveStats> s32;
+    diis_solve(*this, 1, nullptr, nullptr, t.p, cfg.tol_residual, cfg.maxit,
+               [&](int, const double*, const void* X, const void*, void* R) { residual32(X, R); }, s32, 0, 4, ref);
+    diis_solve(*this, 1, nullptr, nullptr, t.p, cfg.tol_residual, cfg.maxit,
+               [&](int, const double*, const void* X, const void*, void* R) { residual64(X, R, nullptr); }, ss, 0,
+               0, ref);
+    ss[0].iterations += s32[0].iterations;
+  } else {
+    diis_solve(*this, 1, nullptr, nullptr, t.p, cfg.tol_residual, cfg.maxit,
+               [&](int, const double*, const void* X, const void*, void* R) { residual64(X, R, nullptr); }, ss, 0);
+  }
   so = ss[0];
+  primal32 = 0;
+  gradL32_ready = 0;
   // evaluate once more at the solution: every stored intermediate then belongs to it
   have_t = true;
   work.ensure(n * 16);
@@ -522,91 +599,69 @@ void Context::solve_linear(Side side, int nb, const double* shifts, const void* 
                out, 1);
     return;
   }
-  // mixed precision with iterative refinement
+  // Mixed precision.  The FP32 program carries f without its diagonal, so
+  // it computes the coupling part (A - D) X; the residual kernel adds
+  // (D + s) X and b in FP64.  FP32 rounding therefore perturbs only the small
+  // coupling term and the FP32 iteration converges well below the FP32
+  // epsilon.  An FP64 product then certifies every right-hand side (defect
+  // correction); any that fall short continue with FP64 products.
   sig.ensure(nb * n * 8);
-  DevBuf Xa, Ba, R64, d, s64, shd;
-  Xa.ensure(nb * vb);
-  Ba.ensure(nb * vb);
-  R64.ensure(nb * vb);
-  d.ensure(nb * vb);
+  std::vector<SolveStats> s32;
+  diis_solve(*this, nb, shifts, b, x, tol, cfg.maxit,
+             [&](int na, const double* sh, const void* X, const void* Bw, void* R) {
+               sigma32(side, na, X, sig.p);
+               launch_residual<float>(na, n, sig.p, sh, X, Bw, n, R, st, D.as<double>());
+             },
+             s32, 1, 4);
+  out = s32;
+  DevBuf s64, R64, shd;
   s64.ensure(nb * vb);
+  R64.ensure(nb * vb);
   shd.ensure(nb * 8);
-  out.assign(nb, SolveStats());
-  std::vector<double> bn;
-  {
-    DevBuf dd, w;
-    dd.ensure(nb * 16);
-    w.ensure((size_t)nb * 1024 * 16);
-    launch_batched_dot<double>(nb, n, b, n, b, n, true, dd.p, w.p, st);
-    std::vector<cplx> h(nb);
-    HIP_CHECK(hipMemcpyAsync(h.data(), dd.p, nb * 16, hipMemcpyDeviceToHost, st));
-    sync();
-    for (int r = 0; r < nb; ++r) bn.push_back(std::max(1e-300, std::sqrt(std::max(0.0, h[r].real()))));
+  std::vector<double> sh(nb, 0.0);
+  if (shifts) sh.assign(shifts, shifts + nb);
+  HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nb * 8, hipMemcpyHostToDevice, st));
+  sigma64(side, nb, x, s64.p);
+  launch_residual<double>(nb, n, s64.p, shd.as<double>(), x, b, n, R64.p, st);
+  std::vector<double> rn, bn;
+  vec_norms(*this, nb, R64.p, rn);
+  vec_norms(*this, nb, b, bn);
+  std::vector<int> redo;
+  for (int r = 0; r < nb; ++r) {
+    out[r].sigma_evals += 1;
+    out[r].residual = rn[r] / std::max(bn[r], 1e-300);
+    out[r].converged = out[r].residual <= tol ? 1 : 0;
+    if (!out[r].converged) redo.push_back(r);
   }
-  std::vector<int> act(nb);
-  for (int r = 0; r < nb; ++r) act[r] = r;
-  const double tol_in = std::max(1e-5, tol);
-  double t0 = now_s();
-  const int max_outer = 12;
-  for (int outer = 0; outer < max_outer && !act.empty(); ++outer) {
-    int na = (int)act.size();
-    std::vector<double> sh(na);
-    for (int k = 0; k < na; ++k) {
-      sh[k] = shifts ? shifts[act[k]] : 0.0;
-      HIP_CHECK(hipMemcpyAsync((char*)Xa.p + k * vb, (char*)x + act[k] * vb, vb, hipMemcpyDeviceToDevice, st));
-      HIP_CHECK(hipMemcpyAsync((char*)Ba.p + k * vb, (const char*)b + act[k] * vb, vb, hipMemcpyDeviceToDevice, st));
-    }
-    HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), na * 8, hipMemcpyHostToDevice, st));
-    sigma64(side, na, Xa.p, s64.p);
-    launch_residual<double>(na, n, s64.p, shd.as<double>(), Xa.p, Ba.p, n, R64.p, st);
-    std::vector<double> rn;
-    vec_norms(*this, na, R64.p, rn);
-    std::vector<int> keep;
-    std::vector<int> keep_slot;
-    for (int k = 0; k < na; ++k) {
-      SolveStats& so = out[act[k]];
-      so.sigma_evals += 1;
-      so.residual = rn[k] / bn[act[k]];
-      so.seconds = now_s() - t0;
-      if (rn[k] <= tol * bn[act[k]]) {
-        so.converged = 1;
-      } else {
-        keep.push_back(act[k]);
-        keep_slot.push_back(k);
-      }
-    }
-    if (keep.empty()) break;
-    if (outer == max_outer - 1) break;
-    // compact the unconverged right-hand sides
-    int nk = (int)keep.size();
-    std::vector<double> shk(nk);
-    for (int q = 0; q < nk; ++q) {
-      int k = keep_slot[q];
-      shk[q] = sh[k];
-      if (q != k) {
-        HIP_CHECK(hipMemcpyAsync((char*)R64.p + q * vb, (char*)R64.p + k * vb, vb, hipMemcpyDeviceToDevice, st));
-        HIP_CHECK(hipMemcpyAsync((char*)Xa.p + q * vb, (char*)Xa.p + k * vb, vb, hipMemcpyDeviceToDevice, st));
-      }
-    }
-    HIP_CHECK(hipMemcpyAsync(shd.p, shk.data(), nk * 8, hipMemcpyHostToDevice, st));
-    // correction equation (A + s) d = -R64 with FP32 products
-    launch_jacobi(nk, n, D.as<double>(), shd.as<double>(), nullptr, R64.p, d.p, nullptr, st);
-    std::vector<SolveStats> inner;
-    diis_solve(*this, nk, shk.data(), R64.p, d.p, tol_in, cfg.maxit,
-               [&](int na2, const double* sh2, const void* X, const void* Bw, void* R) {
-                 sigma32(side, na2, X, sig.p);
-                 launch_residual<float>(na2, n, sig.p, sh2, X, Bw, n, R, st);
-               },
-               inner, 1);
-    // x += d
-    for (int q = 0; q < nk; ++q) {
-      launch_residual<double>(1, n, (char*)d.p + q * vb, nullptr, nullptr, (char*)Xa.p + q * vb, n,
-                              (char*)Xa.p + q * vb, st);
-      HIP_CHECK(hipMemcpyAsync((char*)x + keep[q] * vb, (char*)Xa.p + q * vb, vb, hipMemcpyDeviceToDevice, st));
-      out[keep[q]].iterations += inner[q].iterations;
-      out[keep[q]].sigma_evals += inner[q].sigma_evals;
-    }
-    act = keep;
+  if (redo.empty()) return;
+  // finish the remaining right-hand sides with FP64 products
+  const int nr = (int)redo.size();
+  DevBuf Xr, Br;
+  Xr.ensure(nr * vb);
+  Br.ensure(nr * vb);
+  std::vector<double> shr(nr);
+  for (int q = 0; q < nr; ++q) {
+    HIP_CHECK(hipMemcpyAsync((char*)Xr.p + q * vb, (char*)x + redo[q] * vb, vb, hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipMemcpyAsync((char*)Br.p + q * vb, (const char*)b + redo[q] * vb, vb, hipMemcpyDeviceToDevice, st));
+    shr[q] = sh[redo[q]];
+  }
+  std::vector<SolveStats> s2;
+  DevBuf sg;
+  sg.ensure(nr * vb);
+  diis_solve(*this, nr, shr.data(), Br.p, Xr.p, tol, cfg.maxit,
+             [&](int na, const double* shv, const void* X, const void* Bw, void* R) {
+               sigma64(side, na, X, sg.p);
+               launch_residual<double>(na, n, sg.p, shv, X, Bw, n, R, st);
+             },
+             s2, 1);
+  for (int q = 0; q < nr; ++q) {
+    HIP_CHECK(hipMemcpyAsync((char*)x + redo[q] * vb, (char*)Xr.p + q * vb, vb, hipMemcpyDeviceToDevice, st));
+    SolveStats& o = out[redo[q]];
+    o.iterations += s2[q].iterations;
+    o.sigma_evals += s2[q].sigma_evals;
+    o.converged = s2[q].converged;
+    o.residual = s2[q].residual;
+    o.seconds += s2[q].seconds;
   }
   sync();
 }
@@ -624,12 +679,34 @@ void Context::solve_lambda(SolveStats& so) {
   lam.ensure(vb);
   launch_jacobi(1, n, D.as<double>(), nullptr, nullptr, e0.p, lam.p, nullptr, st);
   std::vector<SolveStats> ss;
-  solve_linear(Side::Left, 1, nullptr, e0.p, lam.p, 64, cfg.tol_residual, ss);
+  solve_linear(Side::Left, 1, nullptr, e0.p, lam.p, cfg.precision == LRCC_MIXED ? 32 : 64, cfg.tol_residual, ss);
   so = ss[0];
   have_lam = true;
   gradL_ready = 0;
+  gradL32_ready = 0;
   have_alpha = false;
   LRCC_REQUIRE(so.converged, LRCC_E_NOCONV, "Lambda amplitudes did not converge");
+}
+
+// Right-hand sides per batched solve: the configured chunk, or as many as
+// fit in 70% of the free device memory (transient tensors of the Jacobian
+// programs at the working precision(s) plus the DIIS history per RHS).
+int Context::rhs_chunk_for(int nrhs, int prec) {
+  if (cfg.rhs_chunk > 0) return std::min(cfg.rhs_chunk, nrhs);
+  int64_t per = 0;
+  per += std::max(x64->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
+                  x64->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
+  per = std::max(per, x64->transient_bytes(P.hvp, 1, {P.h_out1, P.h_out2p}));
+  if (prec == 32) {
+    ensure_x32(*this);
+    per += std::max(x32->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
+                    x32->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
+  }
+  per += (int64_t)(2 * std::max(cfg.diis_size, 0) + 12) * n * 16;
+  size_t fr = 0, tot = 0;
+  HIP_CHECK(hipMemGetInfo(&fr, &tot));
+  int64_t c = (int64_t)(0.7 * (double)fr) / std::max<int64_t>(per, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, c));
 }
 
 void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& per) {
@@ -659,7 +736,8 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
   X.ensure(nrhs * vb);
   Y.ensure(nrhs * vb);
   per.assign(2 * nrhs, SolveStats());
-  const int chunk = cfg.rhs_chunk > 0 ? std::min(cfg.rhs_chunk, nrhs) : nrhs;
+  const int chunk = rhs_chunk_for(nrhs, prec);
+  if (cfg.verbose >= 1) fprintf(stderr, "[lrcc] response: %d right-hand sides in chunks of %d\n", nrhs, chunk);
   DevBuf bc, shd;
   bc.ensure(chunk * vb);
   shd.ensure(chunk * 8);
@@ -677,8 +755,17 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
       if (side == 0) {
         for (int q = 0; q < nc; ++q)
           HIP_CHECK(hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
-      } else {
+      } else if (prec == 64) {
         hvp(nc, cp.data(), (char*)X.p + c0 * vb, bc.p);  // eta^B + F X^B
+      } else {
+        // F X^B with FP32 products (F does not involve the Fock diagonal),
+        // plus eta^B (FP64)
+        DevBuf f32;
+        f32.ensure(nc * n * 8);
+        fx32(nc, (char*)X.p + c0 * vb, f32.p);
+        for (int q = 0; q < nc; ++q)
+          launch_residual<float>(1, n, (char*)f32.p + (size_t)q * n * 8, nullptr, nullptr, (char*)eta.p + cp[q] * vb, 0,
+                                 (char*)bc.p + q * vb, st);
       }
       HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
       launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);

@@ -24,6 +24,10 @@ SIDE_RESIDUAL, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 AMP_T, AMP_LAMBDA, AMP_X, AMP_Y = 0, 1, 2, 3
 PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL = range(7)
 
+# torch ships its own libamdhip64.so.7; load it first so that torch (device
+# memory, streams) and this library share one HIP runtime in the process.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2503_23144_amd.build`")
 lib = ctypes.CDLL(LIB_PATH)

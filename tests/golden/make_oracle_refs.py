@@ -1,0 +1,73 @@
+"""Write stored oracle values for the larger parity cases.
+
+Calls only oracle/ (and the seeded input generator).  The HIP path never
+writes anything here.
+
+    python tests/golden/make_oracle_refs.py c2      # -> tests/golden/oracle_c2.npz
+    python tests/golden/make_oracle_refs.py c3      # -> tests/golden/oracle_c3.npz
+
+c2: o=10, v=60, naux=120, seed 0, all three dipole directions at w = 0.05:
+    E_corr, alpha, and right/left sigma products at seeded (t, X).
+c3: o=20, v=150, naux=300, seed 0, all three directions at w = 0.3 (the
+    largest frequency of that workload): E_corr and alpha.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle.response import (Problem, alpha_from, eta, F_times, left_sigma, right_sigma,  # noqa: E402
+                             solve_ground, solve_lambda, solve_x, solve_y, xi)
+from paper_2503_23144_amd.synth import config_inputs  # noqa: E402
+
+
+def sampled_sigmas(P, seed=11):
+    rng = np.random.default_rng(seed)
+    n = P.lay.n
+    t = 0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    X = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    tt, XX = torch.as_tensor(t), torch.as_tensor(X)
+    return dict(sig_t=t, sig_X=X, sig_residual=P.omega(tt).numpy(),
+                sig_right=right_sigma(P, tt, XX).resolve_conj().numpy(),
+                sig_left=left_sigma(P, tt, XX).resolve_conj().numpy())
+
+
+def main(name):
+    inp = config_inputs(name)
+    omegas = {"c2": [0.05], "c3": [0.3]}[name]
+    t0 = time.time()
+    P = Problem.from_arrays(inp.B, inp.fock, inp.mu, inp.o)
+    out = {}
+    if name == "c2":
+        out.update(sampled_sigmas(P))
+        print(f"sigmas done {time.time() - t0:.0f}s", flush=True)
+    t, E, it = solve_ground(P, tol=1e-12)
+    print(f"T done ({it} it) {time.time() - t0:.0f}s E={complex(E)}", flush=True)
+    lam, it = solve_lambda(P, t, tol=1e-12)
+    print(f"Lambda done ({it} it) {time.time() - t0:.0f}s", flush=True)
+    xis = [xi(P, t, c) for c in range(3)]
+    etas = [eta(P, t, lam, c) for c in range(3)]
+    alpha = []
+    for w in omegas:
+        Xs, Ys = [], []
+        for c in range(3):
+            X, itx = solve_x(P, t, xis[c], w, tol=1e-12)
+            Y, ity = solve_y(P, t, lam, etas[c] + F_times(P, t, lam, X), w, tol=1e-12)
+            Xs.append(X)
+            Ys.append(Y)
+            print(f"w={w} comp {c}: X {itx} it, Y {ity} it, {time.time() - t0:.0f}s", flush=True)
+        alpha.append(alpha_from(xis, etas, Xs, Ys))
+    out.update(ecorr=np.array(complex(E)), omegas=np.array(omegas), alpha=np.array(alpha))
+    path = os.path.join(HERE, f"oracle_{name}.npz")
+    np.savez(path, **out)
+    print(f"wrote {path} in {time.time() - t0:.0f}s", flush=True)
+
+
+if __name__ == "__main__":
+    for nm in sys.argv[1:] or ["c2"]:
+        main(nm)
