@@ -77,7 +77,8 @@ typedef struct lrcc_config {
   int maxit;             /* iteration limit per solve (default 100) */
   int diis_size;         /* DIIS subspace per right-hand side (default 8, 0 = plain Jacobi) */
   int rhs_chunk;         /* right-hand sides per batched Jacobian product (0 = all) */
-  int refine_every;      /* mixed mode: iterations between FP64 residual refinements (default 4) */
+  int autotune;          /* 1: time the candidate GEMM tiles of each new shape once and keep the
+                            fastest (process-wide; cache file from LRCC_AUTOTUNE_CACHE); default 1 */
   int verbose;           /* 0 silent, 1 per-solve summary, 2 per-iteration lines on stderr */
 } lrcc_config;
 
@@ -161,8 +162,9 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
               const double beta[2], void *C, int64_t ldc, void *stream);
 
 /* Text of the derived operation lists (host-only, no GPU needed):
-   which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L,
-   5 dE/dt, 6 grad L.
+   which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L
+   along (X, mu), 5 dE/dt, 6 grad L, 7 F X (tangent of grad L along X),
+   8 FNS++ projections of the perturbation over the MP2 doubles.
    Writes at most `cap` bytes including the NUL; returns the full length. */
 int64_t lrcc_program_text(int which, char *buf, int64_t cap);
 

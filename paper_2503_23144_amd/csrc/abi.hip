@@ -67,7 +67,7 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->maxit = 100;
   cfg->diis_size = 8;
   cfg->rhs_chunk = 0;
-  cfg->refine_every = 4;
+  cfg->autotune = 1;
   cfg->verbose = 0;
 }
 
@@ -85,6 +85,8 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
     HIP_CHECK(hipGetDeviceCount(&ndev));
     LRCC_REQUIRE(c.device >= 0 && c.device < ndev, LRCC_E_INVALID, "no such HIP device");
     std::unique_ptr<lrcc_ctx> ctx(new lrcc_ctx);
+    HIP_CHECK(hipSetDevice(c.device));
+    lrcc::set_gemm_autotune(c.autotune != 0);
     ctx->impl.reset(new Context(c));
     *out = ctx.release();
     g_create_error.clear();
@@ -321,8 +323,9 @@ int64_t lrcc_program_text(int which, char* buf, int64_t cap) {
       lrcc::build_programs(p);
       return p;
     }();
-    const lrcc::OpList* lists[] = {&P.residual, &P.right, &P.left, &P.xi, &P.hvp, &P.eta0, &P.gradL};
-    if (which < 0 || which > 6) return -1;
+    const lrcc::OpList* lists[] = {&P.residual, &P.right, &P.left, &P.xi, &P.hvp,
+                                   &P.eta0,     &P.gradL, &P.hvpt, &P.fnspp};
+    if (which < 0 || which > 8) return -1;
     std::string s = lrcc::serialize(P.m, *lists[which]);
     if (buf && cap > 0) {
       int64_t k = std::min<int64_t>(cap - 1, (int64_t)s.size());
@@ -361,10 +364,6 @@ namespace lrcc {
 void Context::collect_times() {
   if (x64) x64->collect_times(kt);
   if (x32) x32->collect_times(kt);
-}
-
-void Context::fnspp_truncate(const double*, int, double, int, int*, double*) {
-  throw Error(LRCC_E_INTERNAL, "FNS++ truncation is not available in this build");
 }
 
 }  // namespace lrcc

@@ -1,0 +1,290 @@
+// Perturbation-sensitive frozen natural spinors (FNS++), Section II.C.
+//
+//  1. MP2 doubles t_ij^ab = <ab||ij> / (e_i + e_j - e_a - e_b)         (Eq. 39)
+//  2. Hbar_ii = F_ii + 1/2 sum t_in^ef <in||ef>,
+//     Hbar_aa = F_aa - 1/2 sum t_mn^fa <mn||fa>                          (Eqs. 49-50)
+//  3. per direction A: Abar_i^a, Abar_ij^ac (Eq. 48, singles projection
+//     A_ai + sum_me A_me t_im^ae), divided by the Hbar denominators + w
+//     (Eqs. 46-47, with +w as printed)
+//  4. D_ab = <1/2 sum_ijc t(A)_ij^ac conj t(A)_ij^bc + sum_i t(A)_i^a conj t(A)_i^b>
+//     averaged over directions and the frequency grid              (Eq. 45)
+//  5. D V = V n, keep |n| > thresh or the `keep` largest             (Eq. 41)
+//  6. F~ = V~^H F_vv V~, F~ Z~ = Z~ e~, U = V~ Z~                      (Eqs. 42-44)
+//  7. B, F and mu are rotated with C = diag(1_occ, U) on the device and the
+//     integral blocks are rebuilt in the truncated space.
+// The two Hermitian eigenproblems use rocSOLVER (zheevd).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "context.h"
+#include "kernels.h"
+
+namespace lrcc {
+
+namespace {
+
+// t[i][j][a][b] = g[a][b][i][j] / (e_i + e_j - e_a - e_b)   (g = <ab||ij>)
+__global__ void mp2_kernel(int64_t o, int64_t v, const double2* __restrict__ g, const double* __restrict__ eps,
+                           double2* __restrict__ t) {
+  int64_t n = o * o * v * v;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t b = k % v, r = k / v;
+    int64_t a = r % v;
+    r /= v;
+    int64_t j = r % o, i = r / o;
+    double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    double2 x = g[((a * v + b) * o + i) * o + j];
+    t[k] = (i == j || a == b) ? double2{0.0, 0.0} : double2{x.x / d, x.y / d};
+  }
+}
+
+// tA1 = s1 / (Haa[a] - Hii[i] + w), tA2 = s2 / (Haa[a] + Haa[c] - Hii[i] - Hii[j] + w)
+__global__ void fnspp_divide_kernel(int64_t o, int64_t v, const double* __restrict__ Hii,
+                                    const double* __restrict__ Haa, double w, const double2* __restrict__ s1,
+                                    const double2* __restrict__ s2, double2* __restrict__ t1,
+                                    double2* __restrict__ t2) {
+  int64_t n1 = o * v, n2 = o * o * v * v;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n1 + n2;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < n1) {
+      int64_t i = k / v, a = k % v;
+      double d = Haa[a] - Hii[i] + w;
+      t1[k] = {s1[k].x / d, s1[k].y / d};
+    } else {
+      int64_t q = k - n1;
+      int64_t c = q % v, r = q / v;
+      int64_t a = r % v;
+      r /= v;
+      int64_t j = r % o, i = r / o;
+      double d = Haa[a] + Haa[c] - Hii[i] - Hii[j] + w;
+      t2[q] = (i == j || a == c) ? double2{0.0, 0.0} : double2{s2[q].x / d, s2[q].y / d};
+    }
+  }
+}
+
+__global__ void conj_kernel(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = {x[k].x, -x[k].y};
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1 << 20); }
+
+void conj_copy(int64_t n, const void* x, void* y, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(conj_kernel, dim3(grid_of(n)), dim3(256), 0, st, n, (const double2*)x, (double2*)y);
+  HIP_CHECK(hipGetLastError());
+}
+
+// Row-major permute of a 2-D or grouped tensor via the generic kernel.
+void permute(const void* in, void* out, std::initializer_list<int64_t> dims, std::initializer_list<int64_t> istr,
+             hipStream_t st, double bre = 0.0) {
+  PermDesc d{};
+  d.rank = (int)dims.size();
+  int k = 0;
+  for (int64_t x : dims) d.dims[k++] = x;
+  k = 0;
+  for (int64_t x : istr) d.istride[k++] = x;
+  launch_permute<double>(in, out, d, 1.0, 0.0, bre, 0.0, st);
+}
+
+struct Solver {
+  rocblas_handle h = nullptr;
+  explicit Solver(hipStream_t st) {
+    LRCC_REQUIRE(rocblas_create_handle(&h) == rocblas_status_success, LRCC_E_INTERNAL, "rocblas_create_handle");
+    rocblas_set_stream(h, st);
+  }
+  ~Solver() {
+    if (h) rocblas_destroy_handle(h);
+  }
+  // Eigen-decomposition of a Hermitian n x n matrix held row-major on the
+  // device.  Returns eigenvalues (ascending) and, in V (row-major, host),
+  // the eigenvectors as columns: H V = V diag(w).
+  void eigh(int n, const void* Hdev, std::vector<double>& w, std::vector<cplx>& V, hipStream_t st) {
+    DevBuf A, Dv, Ev, info;
+    A.ensure((size_t)n * n * 16);
+    Dv.ensure(n * 8);
+    Ev.ensure(n * 8);
+    info.ensure(16);
+    // a row-major Hermitian H read column-major is conj(H); its eigenvectors
+    // are the conjugates of those of H
+    HIP_CHECK(hipMemcpyAsync(A.p, Hdev, (size_t)n * n * 16, hipMemcpyDeviceToDevice, st));
+    rocblas_status s = rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n,
+                                        (rocblas_double_complex*)A.p, n, Dv.as<double>(), Ev.as<double>(),
+                                        (rocblas_int*)info.p);
+    LRCC_REQUIRE(s == rocblas_status_success, LRCC_E_INTERNAL, "rocsolver_zheevd failed");
+    int inf = 0;
+    w.resize(n);
+    std::vector<cplx> R((size_t)n * n);
+    HIP_CHECK(hipMemcpyAsync(&inf, info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(w.data(), Dv.p, n * 8, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(R.data(), A.p, (size_t)n * n * 16, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    LRCC_REQUIRE(inf == 0, LRCC_E_NOCONV, "Hermitian eigensolver did not converge");
+    // column k of the column-major result is R[k*n + i]: eigenvector of conj(H)
+    V.assign((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k)
+      for (int i = 0; i < n; ++i) V[(size_t)i * n + k] = std::conj(R[(size_t)k * n + i]);
+  }
+};
+
+// X'[Q] = C^H X[Q] C for nq matrices X[Q] (nmo x nmo) with C (nmo x m), all
+// row-major on the device.  Y[Q][p][q'] = sum_q X[Q][p][q] C[q][q'] is one
+// GEMM over Q*nmo rows; then X'[Q][p'][q'] = sum_p conj(C)[p][p'] Y[Q][p][q'].
+void rotate(int64_t nq, int64_t nmo, int64_t m, const void* X, const void* C, void* out, hipStream_t st) {
+  DevBuf Y, Yt, Cc, Z;
+  Y.ensure((size_t)nq * nmo * m * 16);
+  Yt.ensure((size_t)nq * nmo * m * 16);
+  Cc.ensure((size_t)nmo * m * 16);
+  Z.ensure((size_t)nq * m * m * 16);
+  launch_gemm<double>(false, false, nq * nmo, m, nmo, 1.0, 0.0, X, nmo, C, m, 0.0, 0.0, Y.p, m, st);
+  // Yt[p][Q][q'] = Y[Q][p][q']
+  permute(Y.p, Yt.p, {nmo, nq, m}, {m, nmo * m, 1}, st);
+  conj_copy(nmo * m, C, Cc.p, st);
+  // Z[p'][Q][q'] = sum_p conj(C)[p][p'] Yt[p][Q][q']
+  launch_gemm<double>(true, false, m, nq * m, nmo, 1.0, 0.0, Cc.p, m, Yt.p, nq * m, 0.0, 0.0, Z.p, nq * m, st);
+  permute(Z.p, out, {nq, m, m}, {m, nq * m, 1}, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out) {
+  require_sizes();
+  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+  LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
+  LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
+  LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
+  const int64_t vv = v, oo = o;
+  const size_t n2f = (size_t)oo * oo * vv * vv;
+  DevBuf epsd, t2, Hd;
+  epsd.ensure(nmo * 8);
+  HIP_CHECK(hipMemcpy(epsd.p, eps.data(), nmo * 8, hipMemcpyHostToDevice));
+  // 1. MP2 doubles into the projection program's input
+  void* tm2 = x64->ptr(P.n_t2);
+  hipLaunchKernelGGL(mp2_kernel, dim3(grid_of(n2f)), dim3(256), 0, st, oo, vv,
+                     (const double2*)x64->ptr(P.m.find("gvvoo")), epsd.as<double>(), (double2*)tm2);
+  HIP_CHECK(hipGetLastError());
+  // 2. Hbar diagonals: per-i and per-a bilinear sums of t2 with <ij||ab>
+  const void* goovv = x64->ptr(P.m.find("goovv"));
+  DevBuf dots, wk, tA, gA;
+  dots.ensure(std::max(oo, vv) * 16);
+  wk.ensure((size_t)std::max(oo, vv) * 1024 * 16);
+  std::vector<cplx> hd(std::max(oo, vv));
+  launch_batched_dot<double>(oo, oo * vv * vv, tm2, oo * vv * vv, goovv, oo * vv * vv, false, dots.p, wk.p, st);
+  HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, oo * 16, hipMemcpyDeviceToHost, st));
+  sync();
+  std::vector<double> Hii(oo), Haa(vv);
+  for (int64_t i = 0; i < oo; ++i) Hii[i] = eps[i] + 0.5 * hd[i].real();
+  tA.ensure(n2f * 16);
+  gA.ensure(n2f * 16);
+  // [m][n][f][a] -> [a][m][n][f]
+  permute(tm2, tA.p, {vv, oo, oo, vv}, {1, oo * vv * vv, vv * vv, vv}, st);
+  permute(goovv, gA.p, {vv, oo, oo, vv}, {1, oo * vv * vv, vv * vv, vv}, st);
+  launch_batched_dot<double>(vv, oo * oo * vv, tA.p, oo * oo * vv, gA.p, oo * oo * vv, false, dots.p, wk.p, st);
+  HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, vv * 16, hipMemcpyDeviceToHost, st));
+  sync();
+  for (int64_t a = 0; a < vv; ++a) Haa[a] = eps[o + a] - 0.5 * hd[a].real();
+  Hd.ensure((oo + vv) * 8);
+  HIP_CHECK(hipMemcpy(Hd.p, Hii.data(), oo * 8, hipMemcpyHostToDevice));
+  HIP_CHECK(hipMemcpy((char*)Hd.p + oo * 8, Haa.data(), vv * 8, hipMemcpyHostToDevice));
+  // 3-4. projections per direction, first-order amplitudes per frequency,
+  // and the averaged Gram density
+  DevBuf Dm, t1A, t2A, P2, P2c, P1, P1c;
+  Dm.ensure(vv * vv * 16);
+  launch_fill_zero<double>(Dm.p, vv * vv, st);
+  t1A.ensure(oo * vv * 16);
+  t2A.ensure(n2f * 16);
+  P2.ensure(n2f * 16);
+  P2c.ensure(n2f * 16);
+  P1.ensure(oo * vv * 16);
+  P1c.ensure(oo * vv * 16);
+  const int64_t p0[4] = {0, 0, o, o}, np[4] = {o, o, v, v}, r0[4] = {0, o, 0, o}, nr[4] = {o, v, o, v};
+  const double scale = 1.0 / (double)(nw * ncomp);
+  for (int c = 0; c < ncomp; ++c) {
+    for (int k = 0; k < 4; ++k)
+      launch_gather_block(1, nmo, p0[k], np[k], r0[k], nr[k], (const char*)mu.p + c * nmo * nmo * 16,
+                          x64->ptr(P.n_A[k]), st);
+    x64->run(P.fnspp, 1);
+    for (int k = 0; k < nw; ++k) {
+      hipLaunchKernelGGL(fnspp_divide_kernel, dim3(grid_of(oo * vv + n2f)), dim3(256), 0, st, oo, vv,
+                         Hd.as<double>(), Hd.as<double>() + oo, om[k], (const double2*)x64->ptr(P.n_s1),
+                         (const double2*)x64->ptr(P.n_s2), (double2*)t1A.p, (double2*)t2A.p);
+      HIP_CHECK(hipGetLastError());
+      // D[a][b] += s/2 sum_{ijc} t2A[ijac] conj t2A[ijbc]
+      permute(t2A.p, P2.p, {vv, oo, oo, vv}, {vv, oo * vv * vv, vv * vv, 1}, st);  // [a][i][j][c]
+      conj_copy(n2f, P2.p, P2c.p, st);
+      launch_gemm<double>(false, true, vv, vv, oo * oo * vv, 0.5 * scale, 0.0, P2.p, oo * oo * vv, P2c.p,
+                          oo * oo * vv, 1.0, 0.0, Dm.p, vv, st);
+      // D[a][b] += s sum_i t1A[ia] conj t1A[ib]
+      permute(t1A.p, P1.p, {vv, oo}, {1, vv}, st);  // [a][i]
+      conj_copy(oo * vv, P1.p, P1c.p, st);
+      launch_gemm<double>(false, true, vv, vv, oo, scale, 0.0, P1.p, oo, P1c.p, oo, 1.0, 0.0, Dm.p, vv, st);
+    }
+  }
+  // 5. natural spinors, ordered by |n|
+  Solver sol(st);
+  std::vector<double> nocc;
+  std::vector<cplx> Vn;
+  sol.eigh((int)vv, Dm.p, nocc, Vn, st);
+  std::vector<int> order(vv);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::abs(nocc[a]) > std::abs(nocc[b]); });
+  int nk = keep;
+  if (nk == 0)
+    for (int k = 0; k < vv; ++k)
+      if (std::abs(nocc[order[k]]) > thresh) ++nk;
+  LRCC_REQUIRE(nk >= 2, LRCC_E_INVALID, "fewer than two natural spinors kept");
+  if (occ_out)
+    for (int k = 0; k < vv; ++k) occ_out[k] = nocc[order[k]];
+  std::vector<cplx> Vt((size_t)vv * nk);
+  for (int64_t a = 0; a < vv; ++a)
+    for (int k = 0; k < nk; ++k) Vt[a * nk + k] = Vn[(size_t)a * vv + order[k]];
+  // 6. semicanonical: F~ = V~^H F_vv V~ (F_vv on the device), F~ Z = Z e~, U = V~ Z
+  DevBuf Vd, Vc, Fv, Y, Ft, Ud, Zd;
+  Vd.ensure(vv * nk * 16);
+  Vc.ensure(vv * nk * 16);
+  Fv.ensure(vv * vv * 16);
+  Y.ensure(vv * nk * 16);
+  Ft.ensure((size_t)nk * nk * 16);
+  Ud.ensure(vv * nk * 16);
+  Zd.ensure((size_t)nk * nk * 16);
+  HIP_CHECK(hipMemcpy(Vd.p, Vt.data(), vv * nk * 16, hipMemcpyHostToDevice));
+  launch_gather_block(1, nmo, o, v, o, v, fock.p, Fv.p, st);
+  launch_gemm<double>(false, false, vv, nk, vv, 1.0, 0.0, Fv.p, vv, Vd.p, nk, 0.0, 0.0, Y.p, nk, st);
+  conj_copy(vv * nk, Vd.p, Vc.p, st);
+  launch_gemm<double>(true, false, nk, nk, vv, 1.0, 0.0, Vc.p, nk, Y.p, nk, 0.0, 0.0, Ft.p, nk, st);
+  std::vector<double> et;
+  std::vector<cplx> Z;
+  sol.eigh(nk, Ft.p, et, Z, st);
+  HIP_CHECK(hipMemcpy(Zd.p, Z.data(), (size_t)nk * nk * 16, hipMemcpyHostToDevice));
+  launch_gemm<double>(false, false, vv, nk, nk, 1.0, 0.0, Vd.p, nk, Zd.p, nk, 0.0, 0.0, Ud.p, nk, st);
+  // 7. C = diag(1_occ, U) and the rotated inputs
+  const int64_t m = o + nk;
+  std::vector<cplx> Uh((size_t)vv * nk), C((size_t)nmo * m, 0.0);
+  HIP_CHECK(hipMemcpy(Uh.data(), Ud.p, vv * nk * 16, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < o; ++i) C[i * m + i] = 1.0;
+  for (int64_t a = 0; a < vv; ++a)
+    for (int k = 0; k < nk; ++k) C[(o + a) * m + o + k] = Uh[a * nk + k];
+  DevBuf Cd, Bn, Fn, Mn;
+  Cd.ensure((size_t)nmo * m * 16);
+  HIP_CHECK(hipMemcpy(Cd.p, C.data(), (size_t)nmo * m * 16, hipMemcpyHostToDevice));
+  Bn.ensure((size_t)naux * m * m * 16);
+  Fn.ensure((size_t)m * m * 16);
+  Mn.ensure((size_t)ncomp * m * m * 16);
+  rotate(naux, nmo, m, B.p, Cd.p, Bn.p, st);
+  rotate(1, nmo, m, fock.p, Cd.p, Fn.p, st);
+  rotate(ncomp, nmo, m, mu.p, Cd.p, Mn.p, st);
+  const int nc = ncomp;
+  const int64_t na = naux;
+  load_df((int)o, nk, (int)na, Bn.p, LRCC_DEVICE);
+  load_fock(Fn.p, LRCC_DEVICE);
+  load_dipoles(nc, Mn.p, LRCC_DEVICE);
+  if (nvir_out) *nvir_out = nk;
+}
+
+}  // namespace lrcc

@@ -10,14 +10,23 @@
 //       (Br+Bi) are formed once per element when a tile is staged to LDS.
 //
 // Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, 2 x 2) owns a
-// BM x BN tile of C; each wavefront owns (BM/2) x (BN/2) made of 16 x 16
-// MFMA blocks.  K advances in BK-deep slabs staged in LDS as real planes
-// laid out [k][row] so that the MFMA operand read (lane l takes row l%16 at
-// k = l/16) is a contiguous 16-element run per k.  The next slab is
-// prefetched to registers while the current one is consumed.  Blocks are
-// remapped so that consecutive workgroups on one XCD walk the M tiles of the
-// same N column (reuse of the B slab in that XCD's L2).
+// BM x BN tile of C (128 x 128 FP32 / 128 x 64 FP64 for large problems,
+// 64 x 64 otherwise); each wavefront owns (BM/2) x (BN/2) made of 16 x 16
+// MFMA blocks.  K advances in 16-deep slabs staged in LDS as real planes
+// whose layout follows the operand's global layout (16-byte staging writes)
+// with padding that keeps the MFMA operand reads (lane l takes row l%16 at
+// k = l/16) free of bank conflicts.  The next slab is prefetched to
+// registers while the current one is consumed.  Blocks are remapped so that
+// consecutive workgroups on one XCD walk the M tiles of the same N column
+// (reuse of the B slab in that XCD's L2).
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 
 #include "common.h"
 #include "kernels.h"
@@ -50,10 +59,9 @@ struct cpx<float> {
 __device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int WM = BM / 2, WN = BN / 2;      // wavefront tile
-constexpr int TI = WM / 16, TJ = WN / 16;    // MFMA blocks per wavefront
-constexpr int LOADS = BM * BK / NT;          // complex elements per thread per operand slab
+constexpr int BK = 16, NT = 256;
+constexpr int PADK = 4;   // row layout [row][k]: row stride BK + PADK words (reads conflict-free)
+constexpr int PADR = 16;  // k-major layout [k][row]: row stride BM + PADR (lane groups on distinct banks)
 
 // Map a linear workgroup id to (tile_m, tile_n).  Hardware dispatches
 // consecutive ids round-robin over the 8 XCDs; regroup so that each XCD sees
@@ -69,9 +77,22 @@ __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& t
   tn = id / nbm;
 }
 
+// LDS tile of one operand, one real plane per component.  The layout follows
+// the operand's global layout so that each thread stores its four
+// consecutive elements with one 16-byte write:
+//   KMAJ (global contiguous along rows):  [k][row + PADR]
+//   row layout (global contiguous along k): [row][k + PADK]
+template <typename T, int ROWS, bool KMAJ>
+struct Tile {
+  static constexpr int LD = KMAJ ? ROWS + PADR : BK + PADK;
+  static constexpr int SIZE = KMAJ ? BK * LD : ROWS * LD;
+  static __device__ inline int at(int row, int k) { return KMAJ ? k * LD + row : row * LD + k; }
+};
+
 // KIND only separates kernel symbols (0: general contraction, 1: the packed
-// vvvv ladder), so that profiles attribute time to the ladder.
-template <typename T, bool TA, bool TB, int KIND>
+// vvvv ladder), so that profiles attribute time to the ladder.  The workgroup
+// (4 wavefronts, WGM x (4/WGM)) owns a BM x BN tile of C.
+template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM>
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
@@ -79,8 +100,14 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   using V2 = typename cpx<T>::type;
   using ACC = typename cpx<T>::acc;
   constexpr int NP = cpx<T>::planes;
-  __shared__ T As[NP][BK][BM];
-  __shared__ T Bs[NP][BK][BN];
+  constexpr int WGN = 4 / WGM;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TI = WM / 16, TJ = WN / 16;
+  constexpr int GA = BM * BK / 4 / NT, GB = BN * BK / 4 / NT;  // 4-element groups per thread
+  using TA_ = Tile<T, BM, TA>;   // A stored [k][m] when transposed
+  using TB_ = Tile<T, BN, !TB>;  // B stored [k][n] when not transposed
+  __shared__ T As[NP][TA_::SIZE];
+  __shared__ T Bs[NP][TB_::SIZE];
 
   const int64_t nbm = (M + BM - 1) / BM, nbn = (N + BN - 1) / BN;
   int64_t tm, tn;
@@ -88,53 +115,74 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
   const int r16 = lane & 15, kq = lane >> 4;
 
-  // per-thread load coordinates (tile-local)
-  int la_r[LOADS], la_k[LOADS], lb_c[LOADS], lb_k[LOADS];
+  // tile coordinates of each 4-element group (along the contiguous dim)
+  int ar_[GA], ak_[GA], bc_[GB], bk_[GB];
 #pragma unroll
-  for (int q = 0; q < LOADS; ++q) {
-    if (!TA) {  // A[m][k]: thread walks 4 consecutive k
-      la_r[q] = tid >> 2;
-      la_k[q] = (tid & 3) * 4 + q;
-    } else {  // A stored [k][m]: 4 consecutive m
-      la_k[q] = tid >> 4;
-      la_r[q] = (tid & 15) * 4 + q;
+  for (int q = 0; q < GA; ++q) {
+    int g = tid + NT * q;
+    if (!TA) {
+      ar_[q] = g / (BK / 4);
+      ak_[q] = (g % (BK / 4)) * 4;
+    } else {
+      ak_[q] = g / (BM / 4);
+      ar_[q] = (g % (BM / 4)) * 4;
     }
-    if (!TB) {  // B[k][n]: 4 consecutive n
-      lb_k[q] = tid >> 4;
-      lb_c[q] = (tid & 15) * 4 + q;
-    } else {  // B stored [n][k]: 4 consecutive k
-      lb_c[q] = tid >> 2;
-      lb_k[q] = (tid & 3) * 4 + q;
+  }
+#pragma unroll
+  for (int q = 0; q < GB; ++q) {
+    int g = tid + NT * q;
+    if (TB) {
+      bc_[q] = g / (BK / 4);
+      bk_[q] = (g % (BK / 4)) * 4;
+    } else {
+      bk_[q] = g / (BN / 4);
+      bc_[q] = (g % (BN / 4)) * 4;
     }
   }
 
-  V2 ra[LOADS], rb[LOADS];
+  V2 ra[GA][4], rb[GB][4];
   auto load_slab = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      int64_t gm = m0 + la_r[q], gk = k0 + la_k[q];
-      V2 z = {T(0), T(0)};
-      if (gm < M && gk < K) z = TA ? A[gk * lda + gm] : A[gm * lda + gk];
-      ra[q] = z;
-      int64_t gn = n0 + lb_c[q], gk2 = k0 + lb_k[q];
-      V2 w = {T(0), T(0)};
-      if (gn < N && gk2 < K) w = TB ? B[gn * ldb + gk2] : B[gk2 * ldb + gn];
-      rb[q] = w;
-    }
+    for (int q = 0; q < GA; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t gm = m0 + ar_[q] + (TA ? e : 0), gk = k0 + ak_[q] + (TA ? 0 : e);
+        V2 z = {T(0), T(0)};
+        if (gm < M && gk < K) z = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+        ra[q][e] = z;
+      }
+#pragma unroll
+    for (int q = 0; q < GB; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t gn = n0 + bc_[q] + (TB ? 0 : e), gk = k0 + bk_[q] + (TB ? e : 0);
+        V2 w = {T(0), T(0)};
+        if (gn < N && gk < K) w = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
+        rb[q][e] = w;
+      }
   };
   auto store_slab = [&]() {
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
-      As[0][la_k[q]][la_r[q]] = ra[q].x;
-      As[1][la_k[q]][la_r[q]] = ra[q].y;
-      Bs[0][lb_k[q]][lb_c[q]] = rb[q].x;
-      Bs[1][lb_k[q]][lb_c[q]] = rb[q].y;
-      if constexpr (NP == 3) {
-        As[2][la_k[q]][la_r[q]] = ra[q].x + ra[q].y;
-        Bs[2][lb_k[q]][lb_c[q]] = rb[q].x + rb[q].y;
+    for (int q = 0; q < GA; ++q) {
+      int base = TA_::at(ar_[q], ak_[q]);  // the 4 elements are contiguous in LDS
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        As[0][base + e] = ra[q][e].x;
+        As[1][base + e] = ra[q][e].y;
+        if constexpr (NP == 3) As[2][base + e] = ra[q][e].x + ra[q][e].y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      int base = TB_::at(bc_[q], bk_[q]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        Bs[0][base + e] = rb[q][e].x;
+        Bs[1][base + e] = rb[q][e].y;
+        if constexpr (NP == 3) Bs[2][base + e] = rb[q][e].x + rb[q][e].y;
       }
     }
   };
@@ -161,13 +209,15 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
       T ar[TI], ai[TI], br[TJ], bi[TJ];
 #pragma unroll
       for (int i = 0; i < TI; ++i) {
-        ar[i] = As[0][k][wm + i * 16 + r16];
-        ai[i] = As[1][k][wm + i * 16 + r16];
+        int x = TA_::at(wm + i * 16 + r16, k);
+        ar[i] = As[0][x];
+        ai[i] = As[1][x];
       }
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
-        br[j] = Bs[0][k][wn + j * 16 + r16];
-        bi[j] = Bs[1][k][wn + j * 16 + r16];
+        int x = TB_::at(wn + j * 16 + r16, k);
+        br[j] = Bs[0][x];
+        bi[j] = Bs[1][x];
       }
       if constexpr (NP == 2) {
 #pragma unroll
@@ -182,9 +232,9 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
       } else {
         T as[TI], bs[TJ];
 #pragma unroll
-        for (int i = 0; i < TI; ++i) as[i] = As[2][k][wm + i * 16 + r16];
+        for (int i = 0; i < TI; ++i) as[i] = As[2][TA_::at(wm + i * 16 + r16, k)];
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) bs[j] = Bs[2][k][wn + j * 16 + r16];
+        for (int j = 0; j < TJ; ++j) bs[j] = Bs[2][TB_::at(wn + j * 16 + r16, k)];
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -233,32 +283,162 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
       }
 }
 
+template <typename T, int KIND, int BM, int BN, int WGM>
+static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A, int64_t lda,
+               const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc, hipStream_t st) {
+  using V2 = typename cpx<T>::type;
+  int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
+  LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
+#define GO_(TA_, TB_)                                                                                      \
+  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM>), dim3((unsigned)nb), dim3(NT), 0, st, m, n, k, \
+                     (T)are, (T)aim, (const V2*)A, lda, (const V2*)B, ldb, (T)bre, (T)bim, (V2*)C, ldc)
+  if (!ta && !tb)
+    GO_(false, false);
+  else if (!ta && tb)
+    GO_(false, true);
+  else if (ta && !tb)
+    GO_(true, false);
+  else
+    GO_(true, true);
+#undef GO_
+  HIP_CHECK(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- tile choice
+// Candidate workgroup tiles: 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 (FP32).
+// The autotuner times every candidate once per GEMM shape (into a scratch
+// output, so accumulating calls are not disturbed) and keeps the fastest;
+// without it a size heuristic decides.  Results can persist in a text cache
+// named by LRCC_AUTOTUNE_CACHE ("gfx950 prec ta tb kind m n k tile" lines).
+
+template <typename T, int KIND>
+static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
+                     const void* A, int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C,
+                     int64_t ldc, hipStream_t st) {
+  if (cfgid == 2 && sizeof(T) == 4)
+    go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+  else if (cfgid >= 1)
+    go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+  else
+    go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+}
+
+namespace {
+struct TuneKey {
+  int prec, ta, tb, kind;
+  int64_t m, n, k;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(prec, ta, tb, kind, m, n, k) < std::tie(o.prec, o.ta, o.tb, o.kind, o.m, o.n, o.k);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_autotune = false;
+bool g_cache_loaded = false;
+
+std::string cache_path() {
+  const char* p = std::getenv("LRCC_AUTOTUNE_CACHE");
+  return p ? std::string(p) : std::string();
+}
+
+void load_cache() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  std::string path = cache_path();
+  if (path.empty()) return;
+  std::ifstream in(path);
+  std::string arch;
+  TuneKey key;
+  int cfg;
+  while (in >> arch >> key.prec >> key.ta >> key.tb >> key.kind >> key.m >> key.n >> key.k >> cfg)
+    if (arch == "gfx950") g_tune[key] = cfg;
+}
+
+void save_entry(const TuneKey& key, int cfg) {
+  std::string path = cache_path();
+  if (path.empty()) return;
+  std::ofstream out(path, std::ios::app);
+  out << "gfx950 " << key.prec << " " << key.ta << " " << key.tb << " " << key.kind << " " << key.m << " " << key.n
+      << " " << key.k << " " << cfg << "\n";
+}
+}  // namespace
+
+void set_gemm_autotune(bool on) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_autotune = on;
+}
+
+int gemm_tuned_shapes() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return (int)g_tune.size();
+}
+
+template <typename T>
+static int heuristic_tile(int64_t m, int64_t n) {
+  // the large tile only when it still gives every CU several workgroups
+  const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
+  if (sizeof(T) == 4 && big_tiles >= 2048) return 2;
+  return 0;
+}
+
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
                  hipStream_t st, int kind) {
   if (m <= 0 || n <= 0) return;
-  using V2 = typename cpx<T>::type;
-  int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
-  LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
-  dim3 grid((unsigned)nb), block(NT);
-#define GO(TA_, TB_, K_)                                                                                     \
-  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, K_>), grid, block, 0, st, m, n, k, (T)are, (T)aim, (const V2*)A, \
-                     lda, (const V2*)B, ldb, (T)bre, (T)bim, (V2*)C, ldc)
-  if (kind == 1 && !ta && tb)
-    GO(false, true, 1);
-  else if (kind == 1 && !ta && !tb)
-    GO(false, false, 1);
-  else if (!ta && !tb)
-    GO(false, false, 0);
-  else if (!ta && tb)
-    GO(false, true, 0);
-  else if (ta && !tb)
-    GO(true, false, 0);
-  else
-    GO(true, true, 0);
-#undef GO
-  HIP_CHECK(hipGetLastError());
+  auto run = [&](int cfg, void* Cout, double br, double bi) {
+    if (kind == 1)
+      dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+    else
+      dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+  };
+  int cfg = heuristic_tile<T>(m, n);
+  bool tune = false;
+  TuneKey key{sizeof(T) == 8 ? 64 : 32, ta, tb, kind, m, n, k};
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_autotune) {
+      load_cache();
+      auto it = g_tune.find(key);
+      if (it != g_tune.end())
+        cfg = it->second;
+      else
+        tune = true;
+    }
+  }
+  const bool small = (double)m * n * k < 1e8;  // not worth timing
+  if (tune && !small) {
+    const int ncand = sizeof(T) == 4 ? 3 : 2;
+    void* scratch = nullptr;
+    HIP_CHECK(hipMalloc(&scratch, (size_t)m * ldc * 2 * sizeof(T)));
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int c = 0; c < ncand; ++c) {
+      float ms = 0;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_CHECK(hipEventRecord(e0, st));
+        run(c, scratch, 0.0, 0.0);
+        HIP_CHECK(hipEventRecord(e1, st));
+        HIP_CHECK(hipEventSynchronize(e1));
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best) {
+        best = ms;
+        cfg = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_CHECK(hipFree(scratch));
+  }
+  if (tune) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = cfg;
+    if (!small) save_entry(key, cfg);
+  }
+  run(cfg, C, bre, bim);
 }
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,

@@ -73,6 +73,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
                  hipStream_t st, int kind = 0);
 
+// Per-shape tile autotuning of launch_gemm (process-wide).
+void set_gemm_autotune(bool on);
+int gemm_tuned_shapes();
+
 // Solver kernels (FP64 vectors, nvec right-hand sides of length n).
 // R = sig + (D + s_r) X + b_r  (sig in Ts; D, shift, X, b may be null = 0).
 template <typename Ts>

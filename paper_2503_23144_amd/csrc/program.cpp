@@ -432,9 +432,31 @@ E[] += 0.25 * goovv[ijab] * t2[ijab]
 E[] += 0.5 * Xjb[jb] * t1[jb]
 )";
 
+// Abar_i^a = A_ai + sum_me A_me t_im^ae;
+// Abar_ij^ac = P(a,c) sum_e t_ij^ec A_ae - P(i,j) sum_m t_mj^ac A_mi.
+const char* kFnsppProgram = R"(
+input  tm2[ijab] Aoo[ij] Aov[ia] Avo[ai] Avv[ab]
+s1[ia]    = Avo[ai]
+s1[ia]   += tm2[imae] * Aov[me]
+Tca[ijca] = tm2[ijec] * Avv[ae]
+s2[ijac]  = Tca[ijca]
+s2[ijac] += -1 * Tca[ijac]
+Tmi[ijac] = Aoo[mi] * tm2[mjac]
+s2[ijac] += -1 * Tmi[ijac]
+s2[ijac] += Tmi[jiac]
+)";
+
 void build_programs(CcPrograms& P) {
   Module& m = P.m;
   P.residual = parse_program(m, kCcsdProgram);
+  P.fnspp = parse_program(m, kFnsppProgram);
+  P.n_t2 = m.find("tm2");
+  P.n_A[0] = m.find("Aoo");
+  P.n_A[1] = m.find("Aov");
+  P.n_A[2] = m.find("Avo");
+  P.n_A[3] = m.find("Avv");
+  P.n_s1 = m.find("s1");
+  P.n_s2 = m.find("s2");
   P.t1 = m.find("t1");
   P.t2p = m.find("t2p");
   P.foo = m.find("foo");

@@ -97,6 +97,10 @@ std::string serialize(const Module& m, const OpList& prog);
 // The CCSD residual and energy as a program over the module's tensors.
 extern const char* kCcsdProgram;
 
+// Singles and doubles projections of the perturbation operator over the MP2
+// doubles (the numerators of the FNS++ first-order amplitudes).
+extern const char* kFnsppProgram;
+
 // All programs the solvers run, derived from kCcsdProgram.
 struct CcPrograms {
   Module m;
@@ -117,6 +121,8 @@ struct CcPrograms {
   int g_lam1, g_lam2p, g_gt1, g_gt2p;         // gradL
   int h_dt1, h_dt2p, h_df[4], h_out1, h_out2p;  // hvp
   int f_dt1, f_dt2p, f_out1, f_out2p;           // hvpt
+  OpList fnspp;                                 // Abar_i^a, Abar_ij^ac from (t2 MP2, A)
+  int n_t2, n_A[4], n_s1, n_s2;
 };
 void build_programs(CcPrograms& P);
 

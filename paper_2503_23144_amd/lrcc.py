@@ -22,7 +22,7 @@ HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 SIDE_RESIDUAL, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 AMP_T, AMP_LAMBDA, AMP_X, AMP_Y = 0, 1, 2, 3
-PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL = range(7)
+PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL, PROG_FX, PROG_FNSPP = range(9)
 
 # torch ships its own libamdhip64.so.7; load it first so that torch (device
 # memory, streams) and this library share one HIP runtime in the process.
@@ -42,7 +42,7 @@ class LrccError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
-                ("rhs_chunk", ctypes.c_int), ("refine_every", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -140,7 +140,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0):
+                 verbose=0, autotune=True):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -153,6 +153,7 @@ class Context:
         cfg.maxit = maxit
         cfg.diis_size = diis
         cfg.rhs_chunk = rhs_chunk
+        cfg.autotune = int(autotune)
         cfg.verbose = verbose
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))

@@ -95,3 +95,13 @@ def random_unitary(n: int, rng: np.random.Generator) -> np.ndarray:
 
 def random_vector(n: int, rng: np.random.Generator, scale: float = 1.0) -> np.ndarray:
     return scale * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+
+
+def probe_vectors(n: int, seed: int = 11):
+    """Seeded (t, X) for spot checks of Jacobian products: t ~ 0.05 N(0,1)
+    complex amplitudes, X ~ N(0,1) complex."""
+    rng = np.random.default_rng(seed)
+    t = 0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    X = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    idx = np.sort(rng.choice(n, size=min(n, 4096), replace=False))
+    return t, X, idx

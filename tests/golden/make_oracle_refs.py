@@ -23,18 +23,21 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle.response import (Problem, alpha_from, eta, F_times, left_sigma, right_sigma,  # noqa: E402
                              solve_ground, solve_lambda, solve_x, solve_y, xi)
-from paper_2503_23144_amd.synth import config_inputs  # noqa: E402
+from paper_2503_23144_amd.synth import config_inputs, probe_vectors  # noqa: E402
 
 
 def sampled_sigmas(P, seed=11):
-    rng = np.random.default_rng(seed)
-    n = P.lay.n
-    t = 0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
-    X = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    """Omega(t), A X and X A at the seeded probe vectors; 4096 sampled
+    entries of each, plus their full norms."""
+    t, X, idx = probe_vectors(P.lay.n, seed)
     tt, XX = torch.as_tensor(t), torch.as_tensor(X)
-    return dict(sig_t=t, sig_X=X, sig_residual=P.omega(tt).numpy(),
-                sig_right=right_sigma(P, tt, XX).resolve_conj().numpy(),
-                sig_left=left_sigma(P, tt, XX).resolve_conj().numpy())
+    out = dict(sig_seed=np.array(seed), sig_idx=idx)
+    for name, val in (("residual", P.omega(tt)), ("right", right_sigma(P, tt, XX)),
+                      ("left", left_sigma(P, tt, XX))):
+        v = val.resolve_conj().numpy()
+        out["sig_" + name] = v[idx]
+        out["sig_" + name + "_norm"] = np.array(np.linalg.norm(v))
+    return out
 
 
 def main(name):

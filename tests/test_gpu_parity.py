@@ -30,7 +30,7 @@ def _relerr(a, b):
 # ------------------------------------------------------------------ GEMM kernel
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("m,n,k", [(37, 53, 29), (128, 64, 100), (1, 5, 7), (200, 130, 257)])
+@pytest.mark.parametrize("m,n,k", [(37, 53, 29), (128, 64, 100), (1, 5, 7), (200, 130, 257), (260, 300, 45), (513, 257, 130)])
 def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
     lrcc = _lrcc()
     rng = np.random.default_rng(m * 7 + n * 3 + k)
@@ -138,3 +138,68 @@ def test_polarizability_mixed_precision_close_to_fp64():
         c.solve_response(omegas)
         res[prec] = c.alpha(len(omegas))
     assert _relerr(res["mixed"], res["fp64"]) < 1e-6
+
+
+# ------------------------------------------------------------------ FNS++ (A2)
+def test_fnspp_truncation_matches_oracle():
+    from oracle.fnspp import fnspp_transform
+    from oracle.response import lr_ccsd
+    o, v = 3, 10
+    inp = make_inputs(o, v, 12, seed=31)
+    inp.B = inp.B * 8.0
+    omegas = [0.05, 0.12]
+    keep = 6
+    U, n_ref, (Bn, fn, mun) = fnspp_transform(inp.B, inp.fock, inp.mu, o, omegas, keep=keep)
+    c = _ctx(inp)
+    nk, occ = c.fnspp_truncate(omegas, keep=keep)
+    assert nk == keep
+    assert _relerr(occ, n_ref) < 1e-10
+    assert c.n == o * keep + (o * (o - 1) // 2) * (keep * (keep - 1) // 2)
+    ref = lr_ccsd(Bn, fn, mun, o, [0.1], tol=1e-13)
+    e, _ = c.solve_ground()
+    assert abs(e - ref.ecorr) < 1e-10 * abs(ref.ecorr)
+    c.solve_lambda()
+    c.solve_response([0.1])
+    assert _relerr(c.alpha(1), ref.alpha) < 1e-8
+
+
+def test_fnspp_without_truncation_keeps_alpha():
+    inp = make_inputs(3, 8, 10, seed=32)
+    inp.B = inp.B * 8.0
+    res = []
+    for trunc in (False, True):
+        c = _ctx(inp)
+        if trunc:
+            nk, _ = c.fnspp_truncate([0.05], keep=8)
+            assert nk == 8
+        c.solve_ground()
+        c.solve_lambda()
+        c.solve_response([0.05])
+        res.append(c.alpha(1))
+    assert _relerr(res[1], res[0]) < 1e-9
+
+
+# ------------------------------------------------------------------ stored oracle values, o=10 v=60
+def test_c2_matches_stored_oracle():
+    import os
+    from paper_2503_23144_amd.synth import config_inputs, probe_vectors
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c2.npz"))
+    inp = config_inputs("c2")
+    c = _ctx(inp, tol=1e-11)
+    # Jacobian products at the seeded probe (t, X), compared on the stored entries
+    t, X, idx = probe_vectors(c.n, int(ref["sig_seed"]))
+    assert np.array_equal(idx, ref["sig_idx"])
+    R = c.sigma("residual", t)
+    assert _relerr(R[idx], ref["sig_residual"]) < 1e-12
+    assert abs(np.linalg.norm(R) / float(ref["sig_residual_norm"]) - 1) < 1e-12
+    c.set_amplitudes(_lrcc().AMP_T, t)
+    for side in ("right", "left"):
+        got = c.sigma(side, X[None])[0]
+        assert _relerr(got[idx], ref["sig_" + side]) < 1e-12
+        assert abs(np.linalg.norm(got) / float(ref["sig_" + side + "_norm"]) - 1) < 1e-12
+    e, _ = c.solve_ground()
+    assert abs(e - complex(ref["ecorr"])) < 1e-9 * abs(complex(ref["ecorr"]))
+    c.solve_lambda()
+    c.solve_response(ref["omegas"])
+    al = c.alpha(len(ref["omegas"]))
+    assert _relerr(al, ref["alpha"]) < 1e-8

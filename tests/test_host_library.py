@@ -37,6 +37,7 @@ def test_default_config():
     c = lrcc.Config()
     lrcc.lib.lrcc_default_config(ctypes.byref(c))
     assert c.precision == lrcc.FP64 and c.tol_residual == 1e-10 and c.diis_size == 8 and c.maxit == 100
+    assert c.autotune == 1
 
 
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device error path")
@@ -54,7 +55,7 @@ def test_create_without_device_fails_cleanly():
 
 def test_program_text_is_well_formed():
     lrcc = _lrcc()
-    for which in range(7):
+    for which in range(9):
         tensors, ops = parse(lrcc.program_text(which))
         assert ops, which
         for op in ops:
@@ -140,3 +141,32 @@ def test_derived_operation_lists_match_oracle(o, v, naux, seed):
     for r, g in enumerate(_cat(env, I, "H(G(t1))", "H(G(t2p))", nb)):
         ref = (F_times(P, t, lam, X[r]) + eta(P, t, lam, comps[r])).resolve_conj().numpy()
         assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
+
+    _, fx = parse(lrcc.program_text(lrcc.PROG_FX))
+    env[I.id("F(t1)")], env[I.id("F(t2p)")] = _batch(P.lay, X)
+    I.run(fx, env)
+    for r, g in enumerate(_cat(env, I, "F(G(t1))", "F(G(t2p))", nb)):
+        ref = F_times(P, t, lam, X[r]).resolve_conj().numpy()
+        assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_fnspp_projection_list_matches_oracle():
+    """The FNS++ numerators (Eq. 48 and the singles projection), before the
+    denominators of Eqs. 46-47 are applied."""
+    from oracle.fnspp import mp2_and_hbar, perturbed_amplitudes
+    lrcc = _lrcc()
+    o, v = 3, 6
+    inp = make_inputs(o, v, 8, seed=3)
+    B = inp.B * 8
+    t2, Hii, Haa = mp2_and_hbar(B, inp.fock, o)
+    # with a zero frequency and unit denominators the oracle returns the numerators
+    one_i, one_a = torch.zeros_like(Hii), torch.full_like(Haa, 0.5)
+    tA1, tA2 = perturbed_amplitudes(t2, one_i, one_a, inp.mu[1], o, 0.0)
+    tens, ops = parse(lrcc.program_text(lrcc.PROG_FNSPP))
+    I = Interp(tens, o, v, 1)
+    blk = fock_blocks(inp.mu[1], o)
+    env = {I.id("tm2"): t2.numpy(), I.id("Aoo"): blk["foo"], I.id("Aov"): blk["fov"], I.id("Avo"): blk["fvo"],
+           I.id("Avv"): blk["fvv"]}
+    I.run(ops, env)
+    assert np.abs(env[I.id("s1")] - 0.5 * tA1.numpy()).max() < 1e-14
+    assert np.abs(env[I.id("s2")] - tA2.numpy()).max() < 1e-14
