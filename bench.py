@@ -62,8 +62,8 @@ def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0):
     resp_sig = sum(s["sigma_evals"] for s in per)
     sig = st0["sigma_evals"] + st1["sigma_evals"] + resp_sig
     alpha = c.alpha(len(inp.omegas))
-    ladder = c.kernel_time(0) if timing else None
-    allg = c.kernel_time(1) if timing else None
+    ladder = c.kernel_time(0 if precision == "mixed" else 1) if timing else None
+    allg = c.kernel_time(2) if timing else None
     c.close()
     return dict(ecorr=e, sigma_evals=sig, resp_sigma_evals=resp_sig, alpha=alpha, ladder=ladder, gemm=allg,
                 iters=[s["iterations"] for s in per], phases=ph)

@@ -170,7 +170,8 @@ int64_t lrcc_program_text(int which, char *buf, int64_t cap);
 
 /* Time spent in kernels of one class during the last solve or sigma call,
    measured with HIP events on the context's stream (milliseconds, launches).
-   cls: 0 = ladder GEMM (packed vvvv), 1 = all GEMMs, 2 = everything. */
+   cls: 0 = FP32 (3M) packed-vvvv ladder GEMMs, 1 = FP64 (4M) ladder GEMMs,
+   2 = all GEMMs.  flops: executed real flops (6 MNK for 3M, 8 MNK for 4M). */
 int lrcc_kernel_time(lrcc_ctx *ctx, int cls, double *ms, int64_t *launches, double *flops);
 /* Enable (1) or disable (0) the per-launch event timing above. */
 int lrcc_set_timing(lrcc_ctx *ctx, int on);

@@ -90,7 +90,8 @@ struct Tile {
 };
 
 // KIND only separates kernel symbols (0: general contraction, 1: the packed
-// vvvv ladder), so that profiles attribute time to the ladder.  The workgroup
+// vvvv ladder, +2: autotuner probes of either), so that profiles attribute
+// time to the ladder and never mix probes into it.  The workgroup
 // (4 wavefronts, WGM x (4/WGM)) owns a BM x BN tile of C.
 template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM>
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
@@ -386,11 +387,17 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
                  hipStream_t st, int kind) {
   if (m <= 0 || n <= 0) return;
-  auto run = [&](int cfg, void* Cout, double br, double bi) {
-    if (kind == 1)
+  auto run = [&](int cfg, void* Cout, double br, double bi, bool probe) {
+    if (probe) {
+      if (kind == 1)
+        dispatch<T, 3>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+      else
+        dispatch<T, 2>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+    } else if (kind == 1) {
       dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
-    else
+    } else {
       dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+    }
   };
   int cfg = heuristic_tile<T>(m, n);
   bool tune = false;
@@ -419,7 +426,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
       float ms = 0;
       for (int rep = 0; rep < 2; ++rep) {
         HIP_CHECK(hipEventRecord(e0, st));
-        run(c, scratch, 0.0, 0.0);
+        run(c, scratch, 0.0, 0.0, true);
         HIP_CHECK(hipEventRecord(e1, st));
         HIP_CHECK(hipEventSynchronize(e1));
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
@@ -438,7 +445,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     g_tune[key] = cfg;
     if (!small) save_entry(key, cfg);
   }
-  run(cfg, C, bre, bim);
+  run(cfg, C, bre, bim, false);
 }
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,

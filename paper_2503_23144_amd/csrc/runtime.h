@@ -27,10 +27,12 @@ struct Dims {
   int64_t of(char cls) const { return cls == 'o' ? o : cls == 'v' ? v : cls == 'O' ? O : V; }
 };
 
+// HIP-event totals per class: 0 = FP32 (3M) ladder GEMM, 1 = FP64 (4M)
+// ladder GEMM, 2 = every GEMM (executed real flops: 6 MNK for 3M, 8 MNK for 4M).
 struct KernelTimes {
-  double ms[3] = {0, 0, 0};     // ladder GEMM, all GEMM, everything
+  double ms[3] = {0, 0, 0};
   int64_t launches[3] = {0, 0, 0};
-  double flops[3] = {0, 0, 0};  // executed real flops (ladder, all GEMM)
+  double flops[3] = {0, 0, 0};
   void clear() { *this = KernelTimes(); }
 };
 

@@ -212,8 +212,8 @@ void Executor<T>::collect_times(KernelTimes& kt) {
   for (auto& p : pending_) {
     float ms = 0;
     HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
-    for (int c = p.cls; c < 3; ++c) {
-      if (c == 0 && p.cls != 0) continue;
+    for (int c : {p.cls, 2}) {
+      if (c < 0) continue;
       kt.ms[c] += ms;
       kt.launches[c] += 1;
       kt.flops[c] += p.flops;
@@ -291,7 +291,7 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));
     double fl = (sizeof(T) == 8 ? 8.0 : 6.0) * (double)M * (double)N * (double)K;
-    pending_.push_back({e0, e1, ladder ? 0 : 1, fl});
+    pending_.push_back({e0, e1, ladder ? (sizeof(T) == 4 ? 0 : 1) : -1, fl});
   }
 }
 

@@ -261,3 +261,26 @@ class Context:
         ms, ln, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self._check(lib.lrcc_kernel_time(self._h, cls, ctypes.byref(ms), ctypes.byref(ln), ctypes.byref(fl)))
         return ms.value, ln.value, fl.value
+
+
+class RightSigma(torch.autograd.Function):
+    """y = A x + s x: the CC Jacobian (Eq. 30) at the context's T applied to
+    complex128 amplitude vectors x [nvec, n] (device or host).  The backward
+    pass is the library's left product (the exact transpose): for a
+    holomorphic map PyTorch expects grad_x = conj(A^T conj(grad_y))."""
+
+    @staticmethod
+    def forward(ctx, x, context, shifts=None, precision="fp64"):
+        ctx.context, ctx.shifts, ctx.precision = context, shifts, precision
+        return context.sigma("right", x.detach().contiguous(), shifts=shifts, precision=precision)
+
+    @staticmethod
+    def backward(ctx, g):
+        gl = ctx.context.sigma("left", g.conj().resolve_conj().contiguous(), shifts=ctx.shifts,
+                               precision=ctx.precision)
+        return gl.conj().resolve_conj(), None, None, None
+
+
+def right_sigma(x, context, shifts=None, precision="fp64"):
+    """Differentiable A x (see RightSigma)."""
+    return RightSigma.apply(x, context, shifts, precision)

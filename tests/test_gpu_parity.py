@@ -203,3 +203,39 @@ def test_c2_matches_stored_oracle():
     c.solve_response(ref["omegas"])
     al = c.alpha(len(ref["omegas"]))
     assert _relerr(al, ref["alpha"]) < 1e-8
+
+
+# ------------------------------------------------------------------ adjoint / autograd
+def test_autograd_wrapper_gradcheck_and_dot_product():
+    lrcc = _lrcc()
+    inp = make_inputs(3, 6, 8, seed=41)
+    inp.B = inp.B * 8.0
+    c = _ctx(inp)
+    c.solve_ground()
+    n = c.n
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(5)
+    x = torch.tensor(_rand(rng, 2, n), dtype=torch.complex128, device=dev, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda z: lrcc.right_sigma(z, c, shifts=np.array([0.1, -0.2])), (x,),
+                                    eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
+    # bilinear dot-product test u.(A v) = (u A).v on the device
+    u = torch.tensor(_rand(rng, 1, n), dtype=torch.complex128, device=dev)
+    v = torch.tensor(_rand(rng, 1, n), dtype=torch.complex128, device=dev)
+    Av = c.sigma("right", v)
+    uA = c.sigma("left", u)
+    lhs = complex(torch.sum(u * Av))
+    rhs = complex(torch.sum(uA * v))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_right_sigma_matches_central_finite_difference_c2():
+    """A X = (Omega(t + h X) - Omega(t - h X)) / 2h with h = 1e-6 at o=10, v=60."""
+    from paper_2503_23144_amd.synth import config_inputs, probe_vectors
+    inp = config_inputs("c2")
+    c = _ctx(inp)
+    t, X, _ = probe_vectors(c.n, 11)
+    h = 1e-6
+    fd = (c.sigma("residual", t + h * X) - c.sigma("residual", t - h * X)) / (2 * h)
+    c.set_amplitudes(_lrcc().AMP_T, t)
+    AX = c.sigma("right", X[None])[0]
+    assert _relerr(fd, AX) < 1e-7
