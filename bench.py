@@ -69,6 +69,46 @@ def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0):
                 iters=[s["iterations"] for s in per], phases=ph)
 
 
+def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
+    """The particle-particle ladder sum_{e<f} <ab||ef> tau_ij^ef of one batched
+    sigma at o=40, v=400: C[(r,i<j)][a<b] = taup[(r,i<j)][e<f] W[a<b][e<f]
+    with the packed vvvv matrix W (79800 x 79800) resident in HBM, as complex
+    FP32 (3M) and complex FP64 (4M).  Operand values do not change the work;
+    they are seeded random numbers here."""
+    import torch
+    dev = torch.device("cuda:0")
+    po, pv = o * (o - 1) // 2, v * (v - 1) // 2
+    M, N, K = nrhs * po, pv, pv
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    out = {"o": o, "v": v, "rhs": nrhs, "m": M, "n": N, "k": K}
+    for name, dt, mult, peak in (("fp32_3m", torch.complex64, 6, PEAK["fp32"]),
+                                 ("fp64_4m", torch.complex128, 8, PEAK["fp64"])):
+        W = torch.randn(N, K, dtype=dt, device=dev, generator=g)
+        A = torch.randn(M, K, dtype=dt, device=dev, generator=g)
+        C = torch.empty(M, N, dtype=dt, device=dev)
+        lrcc.gemm(A, W, C, transb=True)  # warm-up (and tile autotuning)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lrcc.gemm(A, W, C, transb=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        t = sorted(ts)[len(ts) // 2]
+        tf = mult * M * N * K / t / 1e12
+        out[name] = {"ms": 1e3 * t, "tflops": tf, "peak": peak, "frac": tf / peak,
+                     "w_gib": W.numel() * W.element_size() / 2**30}
+        print(f"[bench] ladder o={o} v={v} {name}: {1e3 * t:.1f} ms, {tf:.1f} TFLOP/s ({100 * tf / peak:.1f}% of peak)",
+              file=sys.stderr, flush=True)
+        del W, A, C
+        torch.cuda.empty_cache()
+    out["fp32_3m_over_fp64_4m_time"] = out["fp64_4m"]["ms"] / out["fp32_3m"]["ms"]
+    return out
+
+
 def cpu_baseline(inp, budget_s=25.0):
     """The oracle, as it stands, timed on the host: right-sigma (A X)
     evaluations at the workload's shapes, one right-hand side at a time."""
@@ -104,6 +144,7 @@ def main():
     ap.add_argument("--fp64", default="both", choices=["none", "plain", "batched", "both"],
                     help="FP64 comparison passes: plain (one RHS per product) and/or batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-ladder-scale", action="store_true", help="skip the o=40, v=400 ladder measurement")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
     # relative on alpha; FP64: 1e-10 on residuals, 1e-8 on alpha)
     ap.add_argument("--tol", type=float, default=1e-6, help="mixed-precision residual tolerance")
@@ -183,6 +224,8 @@ def main():
         for name, _ in runs:
             out[f"mixed_over_{name}_sigma_rate"] = value / out[name]["sigma_evals_per_s"]
             out[f"mixed_over_{name}_time"] = out[name]["seconds"] / (dt / args.steps)
+    if not args.no_ladder_scale:
+        out["ladder_o40_v400"] = ladder_at_scale(lrcc)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inp)
         out["cpu_baseline"]["host"] = host_info()

@@ -7,16 +7,20 @@
 // FP32: 3 real products (Gauss / Karatsuba) on v_mfma_f32_16x16x4_f32 with
 //       FP32 accumulation:  P1 = ArBr, P2 = AiBi, P3 = (Ar+Ai)(Br+Bi),
 //       Re = P1 - P2, Im = P3 - P1 - P2.  The pre-added planes (Ar+Ai),
-//       (Br+Bi) are formed once per element when a tile is staged to LDS.
+//       (Br+Bi) are formed in registers from the staged planes.
 //
 // Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, 2 x 2) owns a
 // BM x BN tile of C (128 x 128 FP32 / 128 x 64 FP64 for large problems,
 // 64 x 64 otherwise); each wavefront owns (BM/2) x (BN/2) made of 16 x 16
-// MFMA blocks.  K advances in 16-deep slabs staged in LDS as real planes
-// whose layout follows the operand's global layout (16-byte staging writes)
-// with padding that keeps the MFMA operand reads (lane l takes row l%16 at
-// k = l/16) free of bank conflicts.  The next slab is prefetched to
-// registers while the current one is consumed.  Blocks are remapped so that
+// MFMA blocks.  K advances in 16-deep slabs staged in LDS as two real
+// planes (re, im; the Gauss sums are formed in registers) whose layout
+// follows the operand's global layout, with padding that keeps the MFMA
+// operand reads (lane l takes row l%16 at k = l/16) free of bank conflicts.
+// Global loads are lane-contiguous along the operand's contiguous dimension
+// and unconditional (clamped addresses; the K tail is zeroed in LDS).  The next slab is
+// fetched into registers while the current one is consumed; where LDS allows
+// two workgroups per CU it is double-buffered (one barrier per slab).  MFMA
+// operand fragments are read from LDS one 4-deep step ahead.  Blocks are remapped so that
 // consecutive workgroups on one XCD walk the M tiles of the same N column
 // (reuse of the B slab in that XCD's L2).
 #include <hip/hip_runtime.h>
@@ -45,14 +49,14 @@ template <>
 struct cpx<double> {
   using type = double2;
   using acc = d4;
-  static constexpr int planes = 2;
+  static constexpr bool gauss = false;  // 4 real products
   static __device__ constexpr int row(int g, int r) { return g + 4 * r; }
 };
 template <>
 struct cpx<float> {
   using type = float2;
   using acc = f4;
-  static constexpr int planes = 3;
+  static constexpr bool gauss = true;  // 3 real products
   static __device__ constexpr int row(int g, int r) { return 4 * g + r; }
 };
 
@@ -77,9 +81,20 @@ __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& t
   tn = id / nbm;
 }
 
+// Register staging of one operand tile: IN elements along the dimension
+// that is contiguous in global memory, PER elements per thread, STEP rows of
+// the other dimension per pass of the 256 threads.
+template <int ROWS, bool KMAJ>
+struct Stage {
+  static constexpr int IN = KMAJ ? ROWS : BK;
+  static constexpr int PER = ROWS * BK / NT;
+  static constexpr int STEP = NT / IN;
+  static_assert(NT % IN == 0 && (ROWS * BK) % NT == 0, "tile does not split over the workgroup");
+};
+
 // LDS tile of one operand, one real plane per component.  The layout follows
-// the operand's global layout so that each thread stores its four
-// consecutive elements with one 16-byte write:
+// the operand's global layout, so lane-consecutive staging writes hit
+// consecutive banks:
 //   KMAJ (global contiguous along rows):  [k][row + PADR]
 //   row layout (global contiguous along k): [row][k + PADK]
 template <typename T, int ROWS, bool KMAJ>
@@ -100,15 +115,20 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
                                                   T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc) {
   using V2 = typename cpx<T>::type;
   using ACC = typename cpx<T>::acc;
-  constexpr int NP = cpx<T>::planes;
+  constexpr bool G3 = cpx<T>::gauss;
+  constexpr int NA = G3 ? 3 : 2;  // accumulators per block
   constexpr int WGN = 4 / WGM;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TI = WM / 16, TJ = WN / 16;
-  constexpr int GA = BM * BK / 4 / NT, GB = BN * BK / 4 / NT;  // 4-element groups per thread
   using TA_ = Tile<T, BM, TA>;   // A stored [k][m] when transposed
   using TB_ = Tile<T, BN, !TB>;  // B stored [k][n] when not transposed
-  __shared__ T As[NP][TA_::SIZE];
-  __shared__ T Bs[NP][TB_::SIZE];
+  // two real planes (re, im) per stage; the Gauss sums are formed in
+  // registers.  Double-buffer when two stages still leave room for two
+  // workgroups per CU (160 KB LDS), else stage once with two barriers.
+  constexpr int STAGE_BYTES = 2 * (TA_::SIZE + TB_::SIZE) * (int)sizeof(T);
+  constexpr int ST = 2 * STAGE_BYTES <= 81920 ? 2 : 1;
+  __shared__ T As[ST][2][TA_::SIZE];
+  __shared__ T Bs[ST][2][TB_::SIZE];
 
   const int64_t nbm = (M + BM - 1) / BM, nbn = (N + BN - 1) / BN;
   int64_t tm, tn;
@@ -119,138 +139,145 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
   const int r16 = lane & 15, kq = lane >> 4;
 
-  // tile coordinates of each 4-element group (along the contiguous dim)
-  int ar_[GA], ak_[GA], bc_[GB], bk_[GB];
-#pragma unroll
-  for (int q = 0; q < GA; ++q) {
-    int g = tid + NT * q;
-    if (!TA) {
-      ar_[q] = g / (BK / 4);
-      ak_[q] = (g % (BK / 4)) * 4;
-    } else {
-      ak_[q] = g / (BM / 4);
-      ar_[q] = (g % (BM / 4)) * 4;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < GB; ++q) {
-    int g = tid + NT * q;
-    if (TB) {
-      bc_[q] = g / (BK / 4);
-      bk_[q] = (g % (BK / 4)) * 4;
-    } else {
-      bk_[q] = g / (BN / 4);
-      bc_[q] = (g % (BN / 4)) * 4;
-    }
-  }
-
-  V2 ra[GA][4], rb[GB][4];
+  // Global -> register staging.  Consecutive lanes take consecutive
+  // elements along the operand's contiguous dimension (IN), so one load
+  // instruction of a wavefront covers whole cache lines.  Every load is
+  // unconditional at a clamped in-range address: rows of A beyond M and
+  // columns of B beyond N only feed outputs that are never stored, and in the
+  // last, partial K slab the A tile's k >= K entries are zeroed in LDS, which
+  // cancels whatever B holds there.
+  using LA = Stage<BM, TA>;
+  using LB = Stage<BN, !TB>;
+  const int a_in = tid % LA::IN, a_out = tid / LA::IN;
+  const int b_in = tid % LB::IN, b_out = tid / LB::IN;
+  V2 ra[LA::PER], rb[LB::PER];
   auto load_slab = [&](int64_t k0) {
 #pragma unroll
-    for (int q = 0; q < GA; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t gm = m0 + ar_[q] + (TA ? e : 0), gk = k0 + ak_[q] + (TA ? 0 : e);
-        V2 z = {T(0), T(0)};
-        if (gm < M && gk < K) z = TA ? A[gk * lda + gm] : A[gm * lda + gk];
-        ra[q][e] = z;
-      }
-#pragma unroll
-    for (int q = 0; q < GB; ++q)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t gn = n0 + bc_[q] + (TB ? 0 : e), gk = k0 + bk_[q] + (TB ? e : 0);
-        V2 w = {T(0), T(0)};
-        if (gn < N && gk < K) w = TB ? B[gn * ldb + gk] : B[gk * ldb + gn];
-        rb[q][e] = w;
-      }
-  };
-  auto store_slab = [&]() {
-#pragma unroll
-    for (int q = 0; q < GA; ++q) {
-      int base = TA_::at(ar_[q], ak_[q]);  // the 4 elements are contiguous in LDS
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[0][base + e] = ra[q][e].x;
-        As[1][base + e] = ra[q][e].y;
-        if constexpr (NP == 3) As[2][base + e] = ra[q][e].x + ra[q][e].y;
-      }
+    for (int q = 0; q < LA::PER; ++q) {
+      const int o = a_out + LA::STEP * q;
+      const int64_t gm = m0 + (TA ? a_in : o), gk = k0 + (TA ? o : a_in);
+      const int64_t cm = gm < M ? gm : M - 1, ck = gk < K ? gk : K - 1;
+      ra[q] = TA ? A[ck * lda + cm] : A[cm * lda + ck];
     }
 #pragma unroll
-    for (int q = 0; q < GB; ++q) {
-      int base = TB_::at(bc_[q], bk_[q]);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        Bs[0][base + e] = rb[q][e].x;
-        Bs[1][base + e] = rb[q][e].y;
-        if constexpr (NP == 3) Bs[2][base + e] = rb[q][e].x + rb[q][e].y;
+    for (int q = 0; q < LB::PER; ++q) {
+      const int o = b_out + LB::STEP * q;
+      const int64_t gn = n0 + (TB ? o : b_in), gk = k0 + (TB ? b_in : o);
+      const int64_t cn = gn < N ? gn : N - 1, ck = gk < K ? gk : K - 1;
+      rb[q] = TB ? B[cn * ldb + ck] : B[ck * ldb + cn];
+    }
+  };
+  auto zero_a_tail = [&](int s, int64_t k0) {
+    const int kv = (int)(K - k0);  // valid depth of this slab, < BK
+    for (int e = tid; e < BM * BK; e += NT) {
+      const int row = e / BK, k = e % BK;
+      if (k >= kv) {
+        As[s][0][TA_::at(row, k)] = T(0);
+        As[s][1][TA_::at(row, k)] = T(0);
       }
+    }
+  };
+  auto store_slab = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < LA::PER; ++q) {
+      const int o = a_out + LA::STEP * q;
+      const int x = TA ? TA_::at(a_in, o) : TA_::at(o, a_in);
+      As[s][0][x] = ra[q].x;
+      As[s][1][x] = ra[q].y;
+    }
+#pragma unroll
+    for (int q = 0; q < LB::PER; ++q) {
+      const int o = b_out + LB::STEP * q;
+      const int x = TB ? TB_::at(o, b_in) : TB_::at(b_in, o);
+      Bs[s][0][x] = rb[q].x;
+      Bs[s][1][x] = rb[q].y;
     }
   };
 
-  ACC acc[NP][TI][TJ];
+  ACC acc[NA][TI][TJ];
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+  for (int p = 0; p < NA; ++p)
 #pragma unroll
     for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int j = 0; j < TJ; ++j) acc[p][i][j] = ACC{0, 0, 0, 0};
 
+  // MFMA operand fragments, double-buffered across the 4-deep k steps so the
+  // LDS reads of step ks+1 are in flight during the products of step ks
+  T ar[2][TI], ai[2][TI], br[2][TJ], bi[2][TJ];
+  auto read_frag = [&](int f, int s, int ks) {
+    const int k = ks * 4 + kq;
+#pragma unroll
+    for (int i = 0; i < TI; ++i) {
+      const int x = TA_::at(wm + i * 16 + r16, k);
+      ar[f][i] = As[s][0][x];
+      ai[f][i] = As[s][1][x];
+    }
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int x = TB_::at(wn + j * 16 + r16, k);
+      br[f][j] = Bs[s][0][x];
+      bi[f][j] = Bs[s][1][x];
+    }
+  };
+  auto products = [&](int f) {
+    if constexpr (!G3) {
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          acc[0][i][j] = mfma(ar[f][i], br[f][j], acc[0][i][j]);
+          acc[0][i][j] = mfma(-ai[f][i], bi[f][j], acc[0][i][j]);
+          acc[1][i][j] = mfma(ar[f][i], bi[f][j], acc[1][i][j]);
+          acc[1][i][j] = mfma(ai[f][i], br[f][j], acc[1][i][j]);
+        }
+    } else {
+      T as[TI], bs[TJ];
+#pragma unroll
+      for (int i = 0; i < TI; ++i) as[i] = ar[f][i] + ai[f][i];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) bs[j] = br[f][j] + bi[f][j];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) {
+          acc[0][i][j] = mfma(ar[f][i], br[f][j], acc[0][i][j]);
+          acc[1][i][j] = mfma(ai[f][i], bi[f][j], acc[1][i][j]);
+          acc[2][i][j] = mfma(as[i], bs[j], acc[2][i][j]);
+        }
+    }
+  };
+
   const int64_t nk = (K + BK - 1) / BK;
   if (nk > 0) {
     load_slab(0);
-    store_slab();
+    store_slab(0);
+    if (BK > K) {
+      __syncthreads();  // the tail entries are written by other threads
+      zero_a_tail(0, 0);
+    }
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = ST == 2 ? (int)(kt & 1) : 0;
     if (kt + 1 < nk) load_slab((kt + 1) * BK);
+    read_frag(0, cur, 0);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      const int k = ks * 4 + kq;
-      T ar[TI], ai[TI], br[TJ], bi[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i) {
-        int x = TA_::at(wm + i * 16 + r16, k);
-        ar[i] = As[0][x];
-        ai[i] = As[1][x];
-      }
-#pragma unroll
-      for (int j = 0; j < TJ; ++j) {
-        int x = TB_::at(wn + j * 16 + r16, k);
-        br[j] = Bs[0][x];
-        bi[j] = Bs[1][x];
-      }
-      if constexpr (NP == 2) {
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) {
-            acc[0][i][j] = mfma(ar[i], br[j], acc[0][i][j]);
-            acc[0][i][j] = mfma(-ai[i], bi[j], acc[0][i][j]);
-            acc[1][i][j] = mfma(ar[i], bi[j], acc[1][i][j]);
-            acc[1][i][j] = mfma(ai[i], br[j], acc[1][i][j]);
-          }
-      } else {
-        T as[TI], bs[TJ];
-#pragma unroll
-        for (int i = 0; i < TI; ++i) as[i] = As[2][TA_::at(wm + i * 16 + r16, k)];
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) bs[j] = Bs[2][TB_::at(wn + j * 16 + r16, k)];
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) {
-            acc[0][i][j] = mfma(ar[i], br[j], acc[0][i][j]);
-            acc[1][i][j] = mfma(ai[i], bi[j], acc[1][i][j]);
-            acc[2][i][j] = mfma(as[i], bs[j], acc[2][i][j]);
-          }
+      if (ks + 1 < BK / 4) read_frag((ks + 1) & 1, cur, ks + 1);
+      products(ks & 1);
+    }
+    if (kt + 1 < nk) {
+      // with two stages the other one was last read before the previous
+      // barrier; with one, wait until every wavefront is done reading it
+      if constexpr (ST == 1) __syncthreads();
+      store_slab(ST == 2 ? cur ^ 1 : 0);
+      if ((kt + 2) * BK > K) {
+        __syncthreads();  // the tail entries are written by other threads
+        zero_a_tail(ST == 2 ? cur ^ 1 : 0, (kt + 1) * BK);
       }
     }
     __syncthreads();
-    if (kt + 1 < nk) {
-      store_slab();
-      __syncthreads();
-    }
   }
 
   // epilogue: register r of a lane holds row cpx<T>::row(lane/16, r), column lane%16
@@ -265,7 +292,7 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
         int64_t gn = n0 + wn + j * 16 + r16;
         if (gm >= M || gn >= N) continue;
         T re, im;
-        if constexpr (NP == 2) {
+        if constexpr (!G3) {
           re = acc[0][i][j][r];
           im = acc[1][i][j][r];
         } else {
@@ -316,9 +343,10 @@ template <typename T, int KIND>
 static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
                      const void* A, int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C,
                      int64_t ldc, hipStream_t st) {
-  if (cfgid == 2 && sizeof(T) == 4)
-    go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
-  else if (cfgid >= 1)
+  if constexpr (sizeof(T) == 4) {  // the FP64 128 x 128 tile does not fit the register file
+    if (cfgid == 2) return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+  }
+  if (cfgid >= 1)
     go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
   else
     go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);

@@ -52,6 +52,30 @@ def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
     assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_ragged_depth_repeated(dtype, ta, tb):
+    """Depths that end in a partial 16-deep slab, each launched repeatedly
+    (the partial slab's zero fill is ordered against the staging writes of
+    other wavefronts; a missing barrier shows up as run-to-run differences)."""
+    lrcc = _lrcc()
+    dev = torch.device("cuda:0")
+    for m, n, k in [(70, 90, 1), (37, 53, 29), (130, 129, 17), (300, 260, 45), (64, 64, 15)]:
+        rng = np.random.default_rng(m + n + k)
+        A = _rand(rng, *((k, m) if ta else (m, k)))
+        B = _rand(rng, *((n, k) if tb else (k, n)))
+        ref = (A.T if ta else A) @ (B.T if tb else B)
+        Ad = torch.tensor(A, dtype=dtype, device=dev)
+        Bd = torch.tensor(B, dtype=dtype, device=dev)
+        eps = 1e-15 if dtype == torch.complex128 else 2e-7
+        tol = 20 * eps * np.sqrt(k) * np.abs(A).max() * np.abs(B).max() * np.sqrt(k)
+        for _ in range(12):
+            Cd = torch.zeros(m, n, dtype=dtype, device=dev)
+            lrcc.gemm(Ad, Bd, Cd, transa=bool(ta), transb=bool(tb))
+            torch.cuda.synchronize()
+            assert np.abs(Cd.cpu().numpy().astype(np.complex128) - ref).max() <= tol, (m, n, k)
+
+
 # ------------------------------------------------------------------ helpers
 def _ctx(inp, precision="fp64", tol=1e-11, **kw):
     lrcc = _lrcc()
