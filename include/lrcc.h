@@ -80,6 +80,8 @@ typedef struct lrcc_config {
   int autotune;          /* 1: time the candidate GEMM tiles of each new shape once and keep the
                             fastest (process-wide; cache file from LRCC_AUTOTUNE_CACHE); default 1 */
   int verbose;           /* 0 silent, 1 per-solve summary, 2 per-iteration lines on stderr */
+  int graphs;            /* 1: replay the Jacobian-product programs as HIP graphs (captured on the
+                            second identical call, replayed from the third); default 1 */
 } lrcc_config;
 
 typedef struct lrcc_stats {
@@ -173,8 +175,14 @@ int64_t lrcc_program_text(int which, char *buf, int64_t cap);
    cls: 0 = FP32 (3M) packed-vvvv ladder GEMMs, 1 = FP64 (4M) ladder GEMMs,
    2 = all GEMMs.  flops: executed real flops (6 MNK for 3M, 8 MNK for 4M). */
 int lrcc_kernel_time(lrcc_ctx *ctx, int cls, double *ms, int64_t *launches, double *flops);
-/* Enable (1) or disable (0) the per-launch event timing above. */
+/* Enable (1) or disable (0) the per-launch event timing above.  With graph
+   replay on (lrcc_config.graphs), GEMMs inside a replayed graph are not
+   timed; the ladder GEMMs are then launched between graph segments so that
+   classes 0 and 1 stay complete. */
 int lrcc_set_timing(lrcc_ctx *ctx, int on);
+/* Program runs captured into HIP graphs and graph replays so far (FP64 and
+   FP32 executors together).  Either pointer may be NULL. */
+int lrcc_graph_stats(lrcc_ctx *ctx, int64_t *captures, int64_t *replays);
 
 /* Build identification string. */
 const char *lrcc_build_info(void);

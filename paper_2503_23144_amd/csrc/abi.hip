@@ -69,6 +69,7 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->rhs_chunk = 0;
   cfg->autotune = 1;
   cfg->verbose = 0;
+  cfg->graphs = 1;
 }
 
 int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
@@ -352,6 +353,16 @@ int lrcc_set_timing(lrcc_ctx* ctx, int on) {
     c.timing = on != 0;
     if (c.x64) c.x64->set_timing(c.timing);
     if (c.x32) c.x32->set_timing(c.timing);
+  });
+}
+
+int lrcc_graph_stats(lrcc_ctx* ctx, int64_t* captures, int64_t* replays) {
+  return guard(ctx, [&](Context& c) {
+    int64_t cap = 0, rep = 0;
+    if (c.x64) cap += c.x64->graph_captures(), rep += c.x64->graph_replays();
+    if (c.x32) cap += c.x32->graph_captures(), rep += c.x32->graph_replays();
+    if (captures) *captures = cap;
+    if (replays) *replays = rep;
   });
 }
 

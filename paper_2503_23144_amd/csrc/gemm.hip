@@ -429,6 +429,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   };
   int cfg = heuristic_tile<T>(m, n);
   bool tune = false;
+  // no timing runs while the stream is being captured into a graph
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (st && hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+  const bool capturing = cap != hipStreamCaptureStatusNone;
   TuneKey key{sizeof(T) == 8 ? 64 : 32, ta, tb, kind, m, n, k};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -438,7 +442,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
       if (it != g_tune.end())
         cfg = it->second;
       else
-        tune = true;
+        tune = !capturing;
     }
   }
   const bool small = (double)m * n * k < 1e8;  // not worth timing

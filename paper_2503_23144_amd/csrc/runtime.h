@@ -67,7 +67,61 @@ class Executor {
   void collect_times(KernelTimes& kt);  // synchronizes; accumulates and clears pending events
   int ladder_const = -1;                // tensor id whose contractions count as the ladder
 
+  // HIP graph replay.  With graphs on, a run whose program, batch and every
+  // buffer address match an earlier (eager) run is captured into HIP graphs
+  // on the second occurrence and replayed from the third on.  Graph runs
+  // execute on a private stream joined to the caller's stream by events.
+  // With timing on, the ladder GEMMs stay outside the graphs (launched
+  // between graph segments) so HIP events can time them; the other GEMMs
+  // inside graphs are then not timed.
+  void set_graphs(bool on);
+  int64_t graph_replays() const { return replays_; }
+  int64_t graph_captures() const { return captures_; }
+
  private:
+  struct GemmArgs {
+    bool ta, tb;
+    int64_t M, N, K;
+    double are, aim;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    double bre;
+    void* C;
+    int64_t ldc;
+    bool ladder;
+  };
+  struct RunKey {
+    const OpList* ops;
+    int nb;
+    bool timing;
+    std::vector<int> keep;
+    std::vector<void*> addr;  // every tensor and scratch buffer
+    bool operator<(const RunKey& o) const;
+  };
+  struct Recorded {
+    int state = 0;                     // 0: seen once (eager), 1: captured
+    std::vector<hipGraphExec_t> seg;   // graph segments, timed GEMMs between them
+    std::vector<GemmArgs> timed;
+  };
+  void prepare(const OpList& ops, int nb, const std::vector<int>& keep);
+  void run_ops(const OpList& ops, int nb);
+  RunKey make_key(const OpList& ops, int nb, const std::vector<int>& keep) const;
+  void capture(Recorded& r, const OpList& ops, int nb);
+  void replay(const Recorded& r);
+  void end_segment();
+  void launch_timed(const GemmArgs& g);
+  void clear_graphs();
+  void on_realloc();  // every allocation change invalidates recorded graphs
+  std::map<RunKey, Recorded> graphs_;
+  bool graphs_on_ = false;
+  bool capturing_ = false;
+  Recorded* rec_ = nullptr;
+  hipStream_t gst_ = nullptr;  // private stream of graph runs
+  hipEvent_t fork_ = nullptr, join_ = nullptr;
+  int64_t replays_ = 0, captures_ = 0;
+
   void contract(const Op& op, int nb);
   void add(const Op& op, int nb);
   void pack(const Op& op, int nb);

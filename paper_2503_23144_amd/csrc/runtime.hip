@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -45,6 +46,10 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
 
 template <typename T>
 Executor<T>::~Executor() {
+  try {
+    clear_graphs();
+  } catch (...) {
+  }
   for (size_t k = 0; k < buf_.size(); ++k)
     if (buf_[k] && !bound_[k] && !pooled_[k]) (void)hipFree(buf_[k]);
   for (void* p : scr_)
@@ -53,6 +58,9 @@ Executor<T>::~Executor() {
     if (p) (void)hipFree(p);
   (void)hipFree(dot_out_);
   (void)hipFree(dot_work_);
+  if (gst_) (void)hipStreamDestroy(gst_);
+  if (fork_) (void)hipEventDestroy(fork_);
+  if (join_) (void)hipEventDestroy(join_);
   for (auto& p : pending_) {
     event_pool_.push_back(p.a);
     event_pool_.push_back(p.b);
@@ -73,6 +81,7 @@ void* Executor<T>::ptr(int id) {
   if (bound_[id] || pooled_[id]) return buf_[id];
   int64_t need = elems(id, max_nb_);
   if (cap_[id] < need) {
+    on_realloc();
     if (buf_[id]) {
       HIP_CHECK(hipStreamSynchronize(st_));
       HIP_CHECK(hipFree(buf_[id]));
@@ -88,6 +97,7 @@ template <typename T>
 void Executor<T>::bind(int id, void* p) {
   LRCC_REQUIRE(!pooled_[id], LRCC_E_INTERNAL, "cannot bind a pooled transient");
   if (buf_[id] && !bound_[id]) {
+    on_realloc();
     HIP_CHECK(hipStreamSynchronize(st_));
     HIP_CHECK(hipFree(buf_[id]));
   }
@@ -113,6 +123,7 @@ void Executor<T>::set_max_batch(int nb) {
 
 template <typename T>
 void Executor<T>::release_batched() {
+  on_realloc();
   HIP_CHECK(hipStreamSynchronize(st_));
   for (size_t k = 0; k < buf_.size(); ++k)
     if (m_[k].batched && buf_[k] && !bound_[k] && !pooled_[k]) {
@@ -161,6 +172,7 @@ void Executor<T>::upload(int id, const void* src, int nb) {
 template <typename T>
 void* Executor<T>::scratch(int slot, size_t bytes) {
   if (scr_cap_[slot] < bytes) {
+    on_realloc();
     if (scr_[slot]) {
       HIP_CHECK(hipStreamSynchronize(st_));
       HIP_CHECK(hipFree(scr_[slot]));
@@ -281,17 +293,35 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
                      ldb >= (tb ? K : N) && ldc >= N,
                  LRCC_E_INTERNAL, "gemm operands exceed their buffers");
   }
+  const GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder};
+  if (capturing_) {
+    if (timing_ && ladder) {  // leave the graph: the ladder is timed between segments
+      end_segment();
+      rec_->timed.push_back(g);
+      launch_timed(g);
+      HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    } else {
+      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0);
+    }
+    return;
+  }
+  launch_timed(g);
+}
+
+template <typename T>
+void Executor<T>::launch_timed(const GemmArgs& g) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timing_) {
     e0 = get_event();
     HIP_CHECK(hipEventRecord(e0, st_));
   }
-  launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0);
+  launch_gemm<T>(g.ta, g.tb, g.M, g.N, g.K, g.are, g.aim, g.A, g.lda, g.B, g.ldb, g.bre, 0.0, g.C, g.ldc, st_,
+                 g.ladder ? 1 : 0);
   if (timing_) {
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));
-    double fl = (sizeof(T) == 8 ? 8.0 : 6.0) * (double)M * (double)N * (double)K;
-    pending_.push_back({e0, e1, ladder ? (sizeof(T) == 4 ? 0 : 1) : -1, fl});
+    double fl = (sizeof(T) == 8 ? 8.0 : 6.0) * (double)g.M * (double)g.N * (double)g.K;
+    pending_.push_back({e0, e1, g.ladder ? (sizeof(T) == 4 ? 0 : 1) : -1, fl});
   }
 }
 
@@ -594,9 +624,7 @@ int64_t Executor<T>::transient_bytes(const OpList& ops, int nb, const std::vecto
 }
 
 template <typename T>
-void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
-  LRCC_REQUIRE(nb >= 1 && nb <= max_nb_, LRCC_E_INTERNAL, "batch exceeds executor maximum");
-  g_nb = nb;
+void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& keep) {
   const Plan& pl = plan_for(ops, nb, keep);
   if (pool_.size() < pl.slot_elems.size()) {
     pool_.resize(pl.slot_elems.size(), nullptr);
@@ -604,6 +632,7 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
   }
   for (size_t s = 0; s < pl.slot_elems.size(); ++s)
     if (pool_cap_[s] < pl.slot_elems[s]) {
+      on_realloc();
       if (pool_[s]) {
         HIP_CHECK(hipStreamSynchronize(st_));
         HIP_CHECK(hipFree(pool_[s]));
@@ -615,6 +644,7 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
   for (auto& ts : pl.slot) {
     int t = ts.first;
     if (buf_[t] && !bound_[t] && !pooled_[t]) {  // drop a private buffer from earlier runs
+      on_realloc();
       HIP_CHECK(hipStreamSynchronize(st_));
       HIP_CHECK(hipFree(buf_[t]));
     }
@@ -622,6 +652,10 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
     cap_[t] = pool_cap_[ts.second];
     pooled_[t] = 1;
   }
+}
+
+template <typename T>
+void Executor<T>::run_ops(const OpList& ops, int nb) {
   for (const Op& op : ops) {
     switch (op.kind) {
       case OpKind::Contract: contract(op, nb); break;
@@ -634,6 +668,138 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
         break;
     }
   }
+}
+
+template <typename T>
+void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
+  LRCC_REQUIRE(nb >= 1 && nb <= max_nb_, LRCC_E_INTERNAL, "batch exceeds executor maximum");
+  g_nb = nb;
+  prepare(ops, nb, keep);
+  if (!graphs_on_) {
+    run_ops(ops, nb);
+    return;
+  }
+  // fork onto the private stream (capture is not possible on the null stream)
+  HIP_CHECK(hipEventRecord(fork_, st_));
+  HIP_CHECK(hipStreamWaitEvent(gst_, fork_, 0));
+  const hipStream_t caller = st_;
+  st_ = gst_;
+  try {
+    auto it = graphs_.find(make_key(ops, nb, keep));
+    if (it == graphs_.end()) {
+      run_ops(ops, nb);  // eager: lazy allocations and GEMM tile tuning happen here
+      if (graphs_.size() >= 64) clear_graphs();
+      graphs_.emplace(make_key(ops, nb, keep), Recorded());
+    } else if (it->second.state == 0) {
+      capture(it->second, ops, nb);
+    } else {
+      replay(it->second);
+    }
+  } catch (...) {
+    st_ = caller;
+    throw;
+  }
+  st_ = caller;
+  HIP_CHECK(hipEventRecord(join_, gst_));
+  HIP_CHECK(hipStreamWaitEvent(st_, join_, 0));
+}
+
+template <typename T>
+bool Executor<T>::RunKey::operator<(const RunKey& o) const {
+  return std::tie(ops, nb, timing, keep, addr) < std::tie(o.ops, o.nb, o.timing, o.keep, o.addr);
+}
+
+template <typename T>
+typename Executor<T>::RunKey Executor<T>::make_key(const OpList& ops, int nb, const std::vector<int>& keep) const {
+  RunKey k{&ops, nb, timing_, keep, {}};
+  k.addr.reserve(buf_.size() + scr_.size() + pool_.size());
+  k.addr.insert(k.addr.end(), buf_.begin(), buf_.end());
+  k.addr.insert(k.addr.end(), scr_.begin(), scr_.end());
+  k.addr.insert(k.addr.end(), pool_.begin(), pool_.end());
+  return k;
+}
+
+template <typename T>
+void Executor<T>::capture(Recorded& r, const OpList& ops, int nb) {
+  ++captures_;
+  r.seg.clear();
+  r.timed.clear();
+  capturing_ = true;
+  rec_ = &r;
+  try {
+    HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    run_ops(ops, nb);
+    end_segment();
+  } catch (...) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(st_, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    capturing_ = false;
+    rec_ = nullptr;
+    for (hipGraphExec_t e : r.seg)
+      if (e) (void)hipGraphExecDestroy(e);
+    r.seg.clear();
+    r.timed.clear();
+    throw;
+  }
+  capturing_ = false;
+  rec_ = nullptr;
+  r.state = 1;
+}
+
+// Close the current capture, instantiate it and launch it at once (the
+// capturing run executes through its own graphs).
+template <typename T>
+void Executor<T>::end_segment() {
+  hipGraph_t g = nullptr;
+  HIP_CHECK(hipStreamEndCapture(st_, &g));
+  size_t nodes = 0;
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphGetNodes(g, nullptr, &nodes);
+  if (e == hipSuccess && nodes > 0) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIP_CHECK(e);
+  rec_->seg.push_back(ex);
+  if (ex) HIP_CHECK(hipGraphLaunch(ex, st_));
+}
+
+template <typename T>
+void Executor<T>::replay(const Recorded& r) {
+  ++replays_;
+  for (size_t k = 0; k < r.seg.size(); ++k) {
+    if (r.seg[k]) HIP_CHECK(hipGraphLaunch(r.seg[k], st_));
+    if (k < r.timed.size()) launch_timed(r.timed[k]);
+  }
+}
+
+template <typename T>
+void Executor<T>::clear_graphs() {
+  if (graphs_.empty()) return;
+  if (gst_) HIP_CHECK(hipStreamSynchronize(gst_));
+  for (auto& kv : graphs_)
+    for (hipGraphExec_t e : kv.second.seg)
+      if (e) (void)hipGraphExecDestroy(e);
+  graphs_.clear();
+}
+
+template <typename T>
+void Executor<T>::on_realloc() {
+  LRCC_REQUIRE(!capturing_, LRCC_E_INTERNAL, "allocation while capturing a graph");
+  clear_graphs();
+}
+
+template <typename T>
+void Executor<T>::set_graphs(bool on) {
+  if (on && !gst_) {
+    HIP_CHECK(hipStreamCreateWithFlags(&gst_, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
+  }
+  if (!on) clear_graphs();
+  graphs_on_ = on;
 }
 
 template class Executor<double>;

@@ -71,6 +71,7 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   x64.reset(new Executor<double>(P.m, dims, st));
   x64->ladder_const = P.m.find("W");
   x64->set_timing(timing);
+  x64->set_graphs(cfg.graphs != 0);
   build_integrals();
   have_fock = false;
   ncomp = 0;
@@ -91,6 +92,7 @@ static void ensure_x32(Context& c) {
   c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
   c.x32->ladder_const = c.P.m.find("W");
   c.x32->set_timing(c.timing);
+  c.x32->set_graphs(c.cfg.graphs != 0);
   for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
     Role r = c.P.m[(int)id].role;
     if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))

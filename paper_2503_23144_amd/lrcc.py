@@ -42,7 +42,8 @@ class LrccError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
-                ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int)]
+                ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -75,6 +76,7 @@ _sig = {
     "lrcc_program_text": (_i64, [_i, ctypes.c_char_p, _i64]),
     "lrcc_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "lrcc_set_timing": (_i, [_vp, _i]),
+    "lrcc_graph_stats": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "lrcc_build_info": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -140,7 +142,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True):
+                 verbose=0, autotune=True, graphs=True):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -155,6 +157,7 @@ class Context:
         cfg.rhs_chunk = rhs_chunk
         cfg.autotune = int(autotune)
         cfg.verbose = verbose
+        cfg.graphs = int(graphs)
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:
@@ -261,6 +264,12 @@ class Context:
         ms, ln, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self._check(lib.lrcc_kernel_time(self._h, cls, ctypes.byref(ms), ctypes.byref(ln), ctypes.byref(fl)))
         return ms.value, ln.value, fl.value
+
+    def graph_stats(self):
+        """(program runs captured into HIP graphs, graph replays)."""
+        cap, rep = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib.lrcc_graph_stats(self._h, ctypes.byref(cap), ctypes.byref(rep)))
+        return cap.value, rep.value
 
 
 class RightSigma(torch.autograd.Function):

@@ -229,6 +229,63 @@ def test_c2_matches_stored_oracle():
     assert _relerr(al, ref["alpha"]) < 1e-8
 
 
+# ------------------------------------------------------------------ HIP graph replay
+@pytest.mark.parametrize("timing", [False, True])
+def test_graph_replay_matches_eager(timing):
+    """Jacobian products replayed from captured HIP graphs equal the eager
+    launches on every replay, with other eager work and synchronizations in
+    between; with timing on the ladder GEMMs run between graph segments."""
+    lrcc = _lrcc()
+    inp = make_inputs(4, 13, 20, seed=7)
+    inp.B = inp.B * 8.0
+    ctx = {g: _ctx(inp, graphs=g) for g in (False, True)}
+    rng = np.random.default_rng(3)
+    n = ctx[True].n
+    t = _rand(rng, n, scale=0.05)
+    for c in ctx.values():
+        c.set_timing(timing)
+        c.set_amplitudes(lrcc.AMP_T, t)
+    for rep in range(6):
+        X = _rand(rng, 3, n)
+        side = "right" if rep % 2 == 0 else "left"
+        for prec in ("fp64", "mixed"):
+            ref = ctx[False].sigma(side, X, precision=prec)
+            got = ctx[True].sigma(side, X, precision=prec)
+            assert np.array_equal(got, ref), (rep, side, prec)
+        # other work between replays (the same on both contexts)
+        tr = _rand(rng, n, scale=0.05)
+        for c in ctx.values():
+            c.sigma("residual", tr)
+            c.set_amplitudes(lrcc.AMP_T, t)
+        torch.cuda.synchronize()
+    cap, rep = ctx[True].graph_stats()
+    assert cap >= 2 and rep >= 2, (cap, rep)
+    assert ctx[False].graph_stats() == (0, 0)
+    if timing:  # the ladder GEMMs are timed on replays too
+        X = _rand(rng, 3, n)
+        for prec, cls in (("fp64", 1), ("mixed", 0)):
+            for c in ctx.values():
+                c.sigma("right", X, precision=prec)
+            ms, launches, _ = ctx[True].kernel_time(cls)
+            ms0, launches0, _ = ctx[False].kernel_time(cls)
+            assert launches == launches0 > 0 and ms > 0, (prec, launches, launches0)
+
+
+def test_graph_replay_full_pipeline_matches_eager():
+    inp = make_inputs(3, 17, 11, seed=5)
+    inp.B = inp.B * 8.0
+    res = {}
+    for g in (False, True):
+        c = _ctx(inp, precision="mixed", tol=1e-9, graphs=g)
+        e, _ = c.solve_ground()
+        c.solve_lambda()
+        c.solve_response([0.0, 0.1, 0.2])
+        res[g] = (e, c.alpha(3), c.graph_stats())
+    assert res[True][0] == res[False][0]
+    assert np.array_equal(res[True][1], res[False][1])
+    assert res[True][2][1] > 10
+
+
 # ------------------------------------------------------------------ adjoint / autograd
 def test_autograd_wrapper_gradcheck_and_dot_product():
     lrcc = _lrcc()
