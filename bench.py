@@ -14,6 +14,7 @@ beside it, and the alpha tensors of the two are compared.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import subprocess
@@ -109,6 +110,77 @@ def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
     return out
 
 
+def _product_rates(lrcc, inp, nvec, graphs, stream, min_s=0.5):
+    """Right products per second on one context: (label -> rate)."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    rates = {}
+    with torch.cuda.stream(stream):
+        c = lrcc.Context(precision="mixed", graphs=graphs, stream=stream.cuda_stream)
+        c.load_df(inp.o, inp.v, inp.B)
+        c.load_fock(inp.fock)
+        c.load_dipoles(inp.mu)
+        n = c.n
+        rng = np.random.default_rng(5)
+        c.set_amplitudes(lrcc.AMP_T, 0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))
+        X = torch.tensor(rng.standard_normal((nvec, n)) + 1j * rng.standard_normal((nvec, n)),
+                         dtype=torch.complex128, device=dev)
+        out = torch.empty_like(X)
+        cases = [("fp64_plain", 1, "fp64")]
+        if graphs:
+            cases += [("fp64_batched", nvec, "fp64"), ("mixed_batched", nvec, "mixed")]
+        for label, nb, prec in cases:
+            for w in range(2):  # eager run (and tile tuning), then graph capture
+                tw = time.perf_counter()
+                c.sigma("right", X[:nb], precision=prec, out=out[:nb])
+                stream.synchronize()
+                print(f"[bench]   o={inp.o} v={inp.v} {label} warm-up {w}: {time.perf_counter() - tw:.1f} s",
+                      file=sys.stderr, flush=True)
+            k, t0 = 0, time.perf_counter()
+            while k < 3 or time.perf_counter() - t0 < min_s:
+                c.sigma("right", X[:nb], precision=prec, out=out[:nb])
+                k += 1
+                if k % 8 == 0 or nb > 1:
+                    stream.synchronize()
+            stream.synchronize()
+            rates[label] = k * nb / (time.perf_counter() - t0)
+            print(f"[bench]   o={inp.o} v={inp.v} {label}{'' if graphs else ' (no graphs)'}: {rates[label]:.4g} /s",
+                  file=sys.stderr, flush=True)
+        c.close()
+    del X, out
+    torch.cuda.empty_cache()
+    return rates
+
+
+def sigma_rates(lrcc, names=("c1", "c2", "c3", "c4"), max_batch={"c4": 16}):
+    """Jacobian products (A X) per second at each workload shape: FP64 one
+    right-hand side per product (the plain solver's product), FP64 batched,
+    and mixed-precision batched (FP32 3M coupling products + FP64 diagonal);
+    the batch is 3 dipole directions x n_w frequencies (capped at 48, and at
+    16 for o=30, v=300, per product).  Amplitudes T and X are seeded random
+    vectors resident on the device.  The plain product is also timed with
+    HIP graph replay off."""
+    import torch
+
+    from paper_2503_23144_amd.synth import CONFIGS, config_inputs
+    stream = torch.cuda.Stream()  # graphs are captured on the caller's stream unless it is the null stream
+    table = {}
+    for name in names:
+        cfg = CONFIGS[name]
+        inp = config_inputs(name)
+        nvec = min(3 * len(cfg["omegas"]), max_batch.get(name, 48))
+        row = {"o": inp.o, "v": inp.v, "batch": nvec}
+        row.update(_product_rates(lrcc, inp, nvec, True, stream))
+        row["fp64_plain_no_graphs"] = _product_rates(lrcc, inp, nvec, False, stream)["fp64_plain"]
+        row["mixed_batched_over_fp64_plain"] = row["mixed_batched"] / row["fp64_plain"]
+        row["graph_speedup_fp64_plain"] = row["fp64_plain"] / row["fp64_plain_no_graphs"]
+        print(f"[bench] sigma rates {name}: " + ", ".join(f"{k}={v:.3g}" for k, v in row.items()
+                                                          if isinstance(v, float)), file=sys.stderr, flush=True)
+        table[name] = row
+    return table
+
+
 def cpu_baseline(inp, budget_s=25.0):
     """The oracle, as it stands, timed on the host: right-sigma (A X)
     evaluations at the workload's shapes, one right-hand side at a time."""
@@ -145,6 +217,7 @@ def main():
                     help="FP64 comparison passes: plain (one RHS per product) and/or batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-ladder-scale", action="store_true", help="skip the o=40, v=400 ladder measurement")
+    ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
     # relative on alpha; FP64: 1e-10 on residuals, 1e-8 on alpha)
     ap.add_argument("--tol", type=float, default=1e-6, help="mixed-precision residual tolerance")
@@ -208,24 +281,33 @@ def main():
         # plain FP64 solver: one right-hand side per Jacobian product; and FP64 batched
         runs = [r for r in (("fp64_plain", 1), ("fp64_batched", 0)) if args.fp64 in ("both", r[0][5:])]
         for name, chunk in runs:
+            # the one-RHS-per-product solver is timed on the first two
+            # frequencies (6 right-hand sides); its rate is per product
+            sub = inp if chunk != 1 else dataclasses.replace(inp, omegas=inp.omegas[:2])
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            r64 = run_pass(lrcc, inp, "fp64", args.tol64, timing=True, chunk=chunk)
+            r64 = run_pass(lrcc, sub, "fp64", args.tol64, timing=True, chunk=chunk)
             torch.cuda.synchronize()
             d64 = time.perf_counter() - t1
-            err = float(np.abs(last["alpha"] - r64["alpha"]).max() / np.abs(r64["alpha"]).max())
+            ref_alpha = last["alpha"][: len(sub.omegas)]
+            err = float(np.abs(ref_alpha - r64["alpha"]).max() / np.abs(r64["alpha"]).max())
             l64 = r64["ladder"]
             out[name] = {"sigma_evals_per_s": r64["sigma_evals"] / d64, "seconds": d64,
                          "response_sigma_evals_per_s": r64["resp_sigma_evals"] / r64["phases"]["response"],
                          "phases_s": r64["phases"],
                          "ladder_tflops": l64[2] / max(l64[0] / 1e3, 1e-30) / 1e12,
-                         "alpha_rel_diff_mixed_vs_this": err}
+                         "alpha_rel_diff_mixed_vs_this": err,
+                         "sample": f"{3 * len(sub.omegas)} right-hand sides ({len(sub.omegas)} of "
+                                   f"{len(inp.omegas)} frequencies), one per product" if chunk == 1 else "full pass"}
             print(f"[bench] {name}: {d64:.1f} s", file=sys.stderr, flush=True)
         for name, _ in runs:
             out[f"mixed_over_{name}_sigma_rate"] = value / out[name]["sigma_evals_per_s"]
-            out[f"mixed_over_{name}_time"] = out[name]["seconds"] / (dt / args.steps)
+            if out[name]["sample"] == "full pass":
+                out[f"mixed_over_{name}_time"] = out[name]["seconds"] / (dt / args.steps)
     if not args.no_ladder_scale:
         out["ladder_o40_v400"] = ladder_at_scale(lrcc)
+    if not args.no_sigma_table:
+        out["sigma_rates"] = sigma_rates(lrcc)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inp)
         out["cpu_baseline"]["host"] = host_info()

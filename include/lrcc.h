@@ -142,7 +142,10 @@ int lrcc_get_alpha(lrcc_ctx *ctx, void *alpha, int where);
    in/out: nvec amplitude vectors; shifts (host, may be NULL = all zero).
    RESIDUAL: out = Omega(in) (nvec must be 1).  RIGHT/LEFT are taken at the
    current T (lrcc_solve_ground or lrcc_set_amplitudes(T) first).
-   precision: LRCC_FP64 or LRCC_MIXED (FP32 products). */
+   precision: LRCC_FP64 or LRCC_MIXED (FP32 products).  With where =
+   LRCC_DEVICE the call is stream-ordered and does not synchronize; device
+   vectors are read and written in place (in == out is allowed and costs a
+   copy).  With LRCC_HOST the call returns after out is written. */
 int lrcc_sigma(lrcc_ctx *ctx, int side, int nvec, const double *shifts, const void *in, void *out,
                int where, int precision);
 

@@ -209,33 +209,46 @@ int lrcc_sigma(lrcc_ctx* ctx, int side, int nvec, const double* shifts, const vo
     LRCC_REQUIRE(precision == LRCC_FP64 || precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
     LRCC_REQUIRE(c.have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
     const size_t vb = c.n * 16;
-    lrcc::DevBuf din, dout, s32, shd;
-    din.ensure(nvec * vb);
-    dout.ensure(nvec * vb);
-    HIP_CHECK(hipMemcpyAsync(din.p, in, nvec * vb, where == LRCC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                             c.st));
+    // device vectors are used in place (an aliased output goes through a copy)
+    lrcc::DevBuf din, dout;
+    const void* src = in;
+    void* dst = out;
+    if (where == LRCC_HOST || in == out) {
+      din.ensure(nvec * vb);
+      HIP_CHECK(hipMemcpyAsync(din.p, in, nvec * vb,
+                               where == LRCC_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c.st));
+      src = din.p;
+    }
+    if (where == LRCC_HOST) dst = dout.ensure(nvec * vb);
     c.kt.clear();
     if (side == LRCC_SIDE_RESIDUAL) {
       LRCC_REQUIRE(nvec == 1, LRCC_E_INVALID, "the residual takes one vector");
-      c.residual64(din.p, dout.p, nullptr);
+      c.residual64(src, dst, nullptr);
     } else {
       LRCC_REQUIRE(side == LRCC_SIDE_RIGHT || side == LRCC_SIDE_LEFT, LRCC_E_INVALID, "bad side");
       lrcc::Side sd = side == LRCC_SIDE_RIGHT ? lrcc::Side::Right : lrcc::Side::Left;
-      if (precision == LRCC_FP64) {
-        c.sigma64(sd, nvec, din.p, dout.p);
-      } else {
-        // FP32 coupling products plus the FP64 diagonal D X
-        s32.ensure(nvec * c.n * 8);
-        c.sigma32(sd, nvec, din.p, s32.p);
-        lrcc::launch_residual<float>(nvec, c.n, s32.p, nullptr, din.p, nullptr, 0, dout.p, c.st, c.D.as<double>());
+      const int prec = precision == LRCC_FP64 ? 64 : 32;
+      const int chunk = c.sigma_chunk(sd, nvec, prec);
+      for (int r0 = 0; r0 < nvec; r0 += chunk) {
+        const int nb = std::min(chunk, nvec - r0);
+        const char* s = (const char*)src + (size_t)r0 * vb;
+        char* d = (char*)dst + (size_t)r0 * vb;
+        if (prec == 64) {
+          c.sigma64(sd, nb, s, d);
+        } else {
+          // FP32 coupling products plus the FP64 diagonal D X
+          void* s32 = c.sig32.ensure(nb * c.n * 8);
+          c.sigma32(sd, nb, s, s32);
+          lrcc::launch_residual<float>(nb, c.n, s32, nullptr, s, nullptr, 0, d, c.st, c.D.as<double>());
+        }
       }
       if (shifts) {
-        shd.ensure(nvec * 8);
-        HIP_CHECK(hipMemcpyAsync(shd.p, shifts, nvec * 8, hipMemcpyHostToDevice, c.st));
-        lrcc::launch_residual<double>(nvec, c.n, dout.p, shd.as<double>(), din.p, nullptr, 0, dout.p, c.st);
+        void* shd = c.shbuf.ensure(nvec * 8);
+        HIP_CHECK(hipMemcpyAsync(shd, shifts, nvec * 8, hipMemcpyHostToDevice, c.st));
+        lrcc::launch_residual<double>(nvec, c.n, dst, (const double*)shd, src, nullptr, 0, dst, c.st);
       }
     }
-    copy_out(out, dout.p, nvec * vb, where, c.st);
+    if (where == LRCC_HOST) copy_out(out, dst, nvec * vb, where, c.st);
     c.collect_times();
   });
 }

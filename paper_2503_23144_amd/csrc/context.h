@@ -87,7 +87,7 @@ struct Context {
   bool timing = false;
 
   // scratch
-  DevBuf work, dotbuf;
+  DevBuf work, dotbuf, sig32, shbuf;
 
   // ---- setup
   void load_df(int nocc, int nvir, int naux_, const void* Bp, int where);
@@ -116,6 +116,7 @@ struct Context {
                     std::vector<SolveStats>& st_out);
 
   int rhs_chunk_for(int nrhs, int prec);
+  int sigma_chunk(Side side, int nvec, int prec);  // right-hand sides per product that fit free memory
   int64_t sigma_count = 0;
   void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
   void require_sizes() const;

@@ -57,8 +57,12 @@ class Executor {
   // (except those listed in `keep`) are transient: they live in a pool whose
   // buffers are reused once a tensor's last reader has run.
   void run(const OpList& ops, int nb, const std::vector<int>& keep = {});
-  // Bytes of pooled transients plus kept batched tensors per right-hand side.
+  // Device bytes a run at batch nb needs for pooled transients, kept batched
+  // tensors and the permutation scratch slots.
   int64_t transient_bytes(const OpList& ops, int nb, const std::vector<int>& keep);
+  // Bytes held now by batch-dependent storage (pool, batched tensors, scratch).
+  size_t batched_bytes() const;
+  // Free all batch-dependent storage (it is re-allocated on the next run).
   void release_batched();
   size_t bytes_allocated() const;
 
@@ -69,8 +73,8 @@ class Executor {
 
   // HIP graph replay.  With graphs on, a run whose program, batch and every
   // buffer address match an earlier (eager) run is captured into HIP graphs
-  // on the second occurrence and replayed from the third on.  Graph runs
-  // execute on a private stream joined to the caller's stream by events.
+  // on the second occurrence and replayed from the third on.  On the null
+  // stream, graph runs execute on a private stream joined to it by events.
   // With timing on, the ladder GEMMs stay outside the graphs (launched
   // between graph segments) so HIP events can time them; the other GEMMs
   // inside graphs are then not timed.

@@ -143,6 +143,12 @@ void Executor<T>::release_batched() {
       cap_[k] = 0;
       pooled_[k] = 0;
     }
+  for (size_t s = 0; s < scr_.size(); ++s)
+    if (scr_[s]) {
+      HIP_CHECK(hipFree(scr_[s]));
+      scr_[s] = nullptr;
+      scr_cap_[s] = 0;
+    }
   plans_.clear();
 }
 
@@ -616,11 +622,26 @@ const typename Executor<T>::Plan& Executor<T>::plan_for(const OpList& ops, int n
 template <typename T>
 int64_t Executor<T>::transient_bytes(const OpList& ops, int nb, const std::vector<int>& keep) {
   const Plan& pl = plan_for(ops, nb, keep);
-  int64_t e = 0;
+  int64_t e = 0, big = 0;
   for (int64_t x : pl.slot_elems) e += x;
   for (int k : keep)
     if (m_[k].batched) e += elems(k, nb);
+  // the three permutation scratch slots hold at most one batched operand each
+  for (const Op& op : ops)
+    for (int u : {op.out, op.a, op.b})
+      if (u >= 0 && m_[u].batched) big = std::max(big, elems(u, nb));
+  e += 3 * big;
   return e * 2 * (int64_t)sizeof(T);
+}
+
+template <typename T>
+size_t Executor<T>::batched_bytes() const {
+  size_t s = 0;
+  for (size_t k = 0; k < buf_.size(); ++k)
+    if (m_[k].batched && !bound_[k] && !pooled_[k]) s += cap_[k] * sizeof(T) * 2;
+  for (int64_t c : pool_cap_) s += c * sizeof(T) * 2;
+  for (size_t c : scr_cap_) s += c;
+  return s;
 }
 
 template <typename T>
@@ -679,11 +700,14 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
     run_ops(ops, nb);
     return;
   }
-  // fork onto the private stream (capture is not possible on the null stream)
-  HIP_CHECK(hipEventRecord(fork_, st_));
-  HIP_CHECK(hipStreamWaitEvent(gst_, fork_, 0));
+  // capture is not possible on the null stream: fork onto the private one
   const hipStream_t caller = st_;
-  st_ = gst_;
+  const bool fork = caller == nullptr;
+  if (fork) {
+    HIP_CHECK(hipEventRecord(fork_, caller));
+    HIP_CHECK(hipStreamWaitEvent(gst_, fork_, 0));
+    st_ = gst_;
+  }
   try {
     auto it = graphs_.find(make_key(ops, nb, keep));
     if (it == graphs_.end()) {
@@ -700,8 +724,10 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
     throw;
   }
   st_ = caller;
-  HIP_CHECK(hipEventRecord(join_, gst_));
-  HIP_CHECK(hipStreamWaitEvent(st_, join_, 0));
+  if (fork) {
+    HIP_CHECK(hipEventRecord(join_, gst_));
+    HIP_CHECK(hipStreamWaitEvent(st_, join_, 0));
+  }
 }
 
 template <typename T>
@@ -779,6 +805,7 @@ template <typename T>
 void Executor<T>::clear_graphs() {
   if (graphs_.empty()) return;
   if (gst_) HIP_CHECK(hipStreamSynchronize(gst_));
+  if (st_) HIP_CHECK(hipStreamSynchronize(st_));
   for (auto& kv : graphs_)
     for (hipGraphExec_t e : kv.second.seg)
       if (e) (void)hipGraphExecDestroy(e);

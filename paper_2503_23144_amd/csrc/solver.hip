@@ -89,6 +89,16 @@ void Context::build_integrals() {
 
 static void ensure_x32(Context& c) {
   if (c.x32) return;
+  {  // the FP32 copies of the constants; make room from FP64 batch storage if needed
+    int64_t need = 0;
+    for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
+      Role r = c.P.m[(int)id].role;
+      if (r == Role::Const || r == Role::Scalar1 || r == Role::Fock) need += c.x64->elems((int)id, 1) * 8;
+    }
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    if ((double)fr < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
+  }
   c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
   c.x32->ladder_const = c.P.m.find("W");
   c.x32->set_timing(c.timing);
@@ -693,22 +703,55 @@ void Context::solve_lambda(SolveStats& so) {
 // Right-hand sides per batched solve: the configured chunk, or as many as
 // fit in 70% of the free device memory (transient tensors of the Jacobian
 // programs at the working precision(s) plus the DIIS history per RHS).
+// Right-hand sides per batched product that fit the device.  `per` is the
+// device bytes one right-hand side needs; the batch storage already held by
+// the executors that will run (use64 / use32) counts as available.  If that
+// is not enough for all right-hand sides, the batch storage of the executor
+// that will not run is released first.
+static int fit_chunk(int nrhs, int64_t per, Executor<double>* x64, Executor<float>* x32, bool use64, bool use32) {
+  auto count = [&]() {
+    size_t fr = 0, tot = 0;
+    HIP_CHECK(hipMemGetInfo(&fr, &tot));
+    double avail = (double)fr;
+    if (use64 && x64) avail += (double)x64->batched_bytes();
+    if (use32 && x32) avail += (double)x32->batched_bytes();
+    return (int64_t)(0.85 * avail) / std::max<int64_t>(per, 1);
+  };
+  int64_t k = count();
+  if (k < nrhs && (!use64 || !use32)) {
+    if (!use64 && x64) x64->release_batched();
+    if (!use32 && x32) x32->release_batched();
+    k = count();
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, k));
+}
+
 int Context::rhs_chunk_for(int nrhs, int prec) {
   if (cfg.rhs_chunk > 0) return std::min(cfg.rhs_chunk, nrhs);
+  if (prec == 32) ensure_x32(*this);
   int64_t per = 0;
   per += std::max(x64->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
                   x64->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
   per = std::max(per, x64->transient_bytes(P.hvp, 1, {P.h_out1, P.h_out2p}));
-  if (prec == 32) {
-    ensure_x32(*this);
+  if (prec == 32)
     per += std::max(x32->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
                     x32->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
-  }
   per += (int64_t)(2 * std::max(cfg.diis_size, 0) + 12) * n * 16;
-  size_t fr = 0, tot = 0;
-  HIP_CHECK(hipMemGetInfo(&fr, &tot));
-  int64_t c = (int64_t)(0.7 * (double)fr) / std::max<int64_t>(per, 1);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, c));
+  // both executors run within one solve: their batch storage all counts
+  return fit_chunk(nrhs, per, x64.get(), x32.get(), true, prec == 32);
+}
+
+int Context::sigma_chunk(Side side, int nvec, int prec) {
+  if (cfg.rhs_chunk > 0) return std::min(cfg.rhs_chunk, nvec);
+  const bool r = side == Side::Right;
+  const std::vector<int> keep = r ? std::vector<int>{P.r_dO1, P.r_dO2p} : std::vector<int>{P.l_gt1, P.l_gt2p};
+  if (prec == 64) {
+    int64_t per = x64->transient_bytes(r ? P.right : P.left, 1, keep);
+    return fit_chunk(nvec, per, x64.get(), x32.get(), true, false);
+  }
+  ensure_x32(*this);
+  int64_t per = x32->transient_bytes(r ? P.right : P.left, 1, keep) + n * 8;
+  return fit_chunk(nvec, per, x64.get(), x32.get(), false, true);
 }
 
 void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& per) {

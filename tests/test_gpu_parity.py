@@ -229,16 +229,53 @@ def test_c2_matches_stored_oracle():
     assert _relerr(al, ref["alpha"]) < 1e-8
 
 
+# ------------------------------------------------------------------ stored oracle values, o=20 v=150
+def test_c3_matches_stored_oracle():
+    """The benchmark workload (o=20, v=150, naux=300): Omega, A X and X A at
+    the seeded probe vectors against stored oracle entries, with the probe in
+    a batch of 48 right-hand sides (the benchmark's product shape), in FP64
+    and in mixed precision; and E_corr."""
+    import os
+    from paper_2503_23144_amd.synth import config_inputs, probe_vectors
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c3.npz"))
+    inp = config_inputs("c3")
+    c = _ctx(inp, tol=1e-11)
+    t, X, idx = probe_vectors(c.n, int(ref["sig_seed"]))
+    assert np.array_equal(idx, ref["sig_idx"])
+    R = c.sigma("residual", t)
+    assert _relerr(R[idx], ref["sig_residual"]) < 1e-12
+    assert abs(np.linalg.norm(R) / float(ref["sig_residual_norm"]) - 1) < 1e-12
+    c.set_amplitudes(_lrcc().AMP_T, t)
+    rng = np.random.default_rng(99)
+    batch = np.concatenate([X[None], _rand(rng, 47, c.n)])
+    kl = ref["sig_left_idx"]
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        AX = c.sigma("right", batch, precision=prec)[0]
+        assert _relerr(AX[idx], ref["sig_right"]) < tol, prec
+        assert abs(np.linalg.norm(AX) / float(ref["sig_right_norm"]) - 1) < tol, prec
+        XA = c.sigma("left", batch, precision=prec)[0]
+        # each stored entry is X . (A e_k), summed over all n amplitudes
+        assert _relerr(XA[kl], ref["sig_left_entries"]) < 10 * tol, prec
+    del batch
+    e, st = c.solve_ground()
+    assert st["converged"] == 1
+    assert abs(e - complex(ref["ecorr"])) < 1e-9 * abs(complex(ref["ecorr"]))
+
+
 # ------------------------------------------------------------------ HIP graph replay
-@pytest.mark.parametrize("timing", [False, True])
-def test_graph_replay_matches_eager(timing):
+@pytest.mark.parametrize("timing,side_stream", [(False, False), (True, False), (False, True), (True, True)])
+def test_graph_replay_matches_eager(timing, side_stream):
     """Jacobian products replayed from captured HIP graphs equal the eager
     launches on every replay, with other eager work and synchronizations in
-    between; with timing on the ladder GEMMs run between graph segments."""
+    between; with timing on the ladder GEMMs run between graph segments.
+    On the null stream graphs run on a private stream joined by events; on
+    another stream they are captured there directly."""
     lrcc = _lrcc()
     inp = make_inputs(4, 13, 20, seed=7)
     inp.B = inp.B * 8.0
-    ctx = {g: _ctx(inp, graphs=g) for g in (False, True)}
+    st = torch.cuda.Stream() if side_stream else None
+    kw = {"stream": st.cuda_stream} if side_stream else {}
+    ctx = {g: _ctx(inp, graphs=g, **kw) for g in (False, True)}
     rng = np.random.default_rng(3)
     n = ctx[True].n
     t = _rand(rng, n, scale=0.05)
