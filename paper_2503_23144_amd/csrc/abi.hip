@@ -314,12 +314,18 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
     LRCC_REQUIRE(alpha && beta && A && B && C, LRCC_E_INVALID, "null argument");
     LRCC_REQUIRE(m >= 0 && n >= 0 && k >= 0, LRCC_E_INVALID, "negative size");
     LRCC_REQUIRE(lda >= (transa ? m : k) && ldb >= (transb ? k : n) && ldc >= n, LRCC_E_INVALID, "leading dimension");
+    // deep products with few output tiles are split over K into a temporary workspace
+    const size_t wsb = precision == LRCC_FP64 ? lrcc::gemm_workspace_bytes<double>(m, n, k)
+                                              : lrcc::gemm_workspace_bytes<float>(m, n, k);
+    lrcc::DevBuf ws;
+    if (wsb) ws.ensure(wsb);
     if (precision == LRCC_FP64)
       lrcc::launch_gemm<double>(transa != 0, transb != 0, m, n, k, alpha[0], alpha[1], A, lda, B, ldb, beta[0],
-                                beta[1], C, ldc, (hipStream_t)stream);
+                                beta[1], C, ldc, (hipStream_t)stream, 0, ws.p, wsb);
     else
       lrcc::launch_gemm<float>(transa != 0, transb != 0, m, n, k, alpha[0], alpha[1], A, lda, B, ldb, beta[0],
-                               beta[1], C, ldc, (hipStream_t)stream);
+                               beta[1], C, ldc, (hipStream_t)stream, 0, ws.p, wsb);
+    if (wsb) HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));  // before the workspace is freed
     return LRCC_OK;
   } catch (const Error& e) {
     g_create_error = e.what();

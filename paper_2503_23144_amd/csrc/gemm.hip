@@ -108,12 +108,23 @@ struct Tile {
 // vvvv ladder, +2: autotuner probes of either), so that profiles attribute
 // time to the ladder and never mix probes into it.  The workgroup
 // (4 wavefronts, WGM x (4/WGM)) owns a BM x BN tile of C.
+//
+// Split-K: blockIdx.y selects the depth range [y * kchunk, (y + 1) * kchunk)
+// and the output C + y * cstride (partial products, reduced afterwards).
 template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM>
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
-                                                  T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc) {
+                                                  T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc,
+                                                  int64_t kchunk, int64_t cstride) {
   using V2 = typename cpx<T>::type;
+  {
+    const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+    K = (K < kbeg + kchunk ? K : kbeg + kchunk) - kbeg;
+    A += TA ? kbeg * lda : kbeg;
+    B += TB ? kbeg : kbeg * ldb;
+    C += (int64_t)blockIdx.y * cstride;
+  }
   using ACC = typename cpx<T>::acc;
   constexpr bool G3 = cpx<T>::gauss;
   constexpr int NA = G3 ? 3 : 2;  // accumulators per block
@@ -311,15 +322,51 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
       }
 }
 
+// C = alpha * sum_s P[s] + beta * C over an m x n tile set (split-K reduction)
+template <typename T>
+__global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typename cpx<T>::type* __restrict__ P,
+                                     T are, T aim, T bre, T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc) {
+  const int64_t total = m * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    T sr = 0, si = 0;
+    for (int s = 0; s < splits; ++s) {
+      const typename cpx<T>::type p = P[(int64_t)s * total + e];
+      sr += p.x;
+      si += p.y;
+    }
+    T cr = are * sr - aim * si, ci = are * si + aim * sr;
+    typename cpx<T>::type* c = C + (e / n) * ldc + e % n;
+    if (bre != T(0) || bim != T(0)) {
+      const typename cpx<T>::type y = *c;
+      cr += bre * y.x - bim * y.y;
+      ci += bre * y.y + bim * y.x;
+    }
+    *c = typename cpx<T>::type{cr, ci};
+  }
+}
+
 template <typename T, int KIND, int BM, int BN, int WGM>
 static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A, int64_t lda,
-               const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc, hipStream_t st) {
+               const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc, hipStream_t st,
+               int splits = 1, void* ws = nullptr) {
   using V2 = typename cpx<T>::type;
   int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
   LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
-#define GO_(TA_, TB_)                                                                                      \
-  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM>), dim3((unsigned)nb), dim3(NT), 0, st, m, n, k, \
-                     (T)are, (T)aim, (const V2*)A, lda, (const V2*)B, ldb, (T)bre, (T)bim, (V2*)C, ldc)
+  // split-K: equal depth ranges, multiples of the slab depth, none empty
+  int64_t kchunk = k, cstride = 0;
+  void* out = C;
+  int64_t ldo = ldc;
+  double ar = are, ai = aim, br = bre, bi = bim;
+  if (splits > 1) {
+    kchunk = ((k + splits - 1) / splits + BK - 1) / BK * BK;
+    splits = (int)((k + kchunk - 1) / kchunk);
+    out = ws, ldo = n, cstride = m * n;
+    ar = 1, ai = 0, br = 0, bi = 0;
+  }
+#define GO_(TA_, TB_)                                                                                        \
+  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
+                     0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, ldo, \
+                     kchunk, cstride)
   if (!ta && !tb)
     GO_(false, false);
   else if (!ta && tb)
@@ -330,6 +377,13 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
     GO_(true, true);
 #undef GO_
   HIP_CHECK(hipGetLastError());
+  if (splits > 1) {
+    const int64_t total = m * n;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(blocks), dim3(256), 0, st, m, n, splits, (const V2*)ws, (T)are,
+                       (T)aim, (T)bre, (T)bim, (V2*)C, ldc);
+    HIP_CHECK(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------- tile choice
@@ -410,11 +464,38 @@ static int heuristic_tile(int64_t m, int64_t n) {
   return 0;
 }
 
+// Split-K for deep products with few output tiles: a 64 x 64 tile grid of
+// fewer than 256 workgroups leaves most CUs idle while each workgroup walks
+// all of K, so the depth is split until about 1024 workgroups run, keeping
+// at least 1024 of depth per split.
+int gemm_splits(int64_t m, int64_t n, int64_t k) {
+  const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
+  if (tiles >= 256 || k < 2048) return 1;
+  int64_t s = std::min<int64_t>((1024 + tiles - 1) / tiles, k / 1024);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+template <typename T>
+size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
+  const int s = gemm_splits(m, n, k);
+  return s > 1 ? (size_t)s * m * n * 2 * sizeof(T) : 0;
+}
+
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st, int kind) {
+                 hipStream_t st, int kind, void* ws, size_t ws_bytes) {
   if (m <= 0 || n <= 0) return;
+  {
+    const int splits = gemm_splits(m, n, k);
+    if (splits > 1 && ws && ws_bytes >= gemm_workspace_bytes<T>(m, n, k)) {
+      if (kind == 1)
+        go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st, splits, ws);
+      else
+        go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st, splits, ws);
+      return;
+    }
+  }
   auto run = [&](int cfg, void* Cout, double br, double bi, bool probe) {
     if (probe) {
       if (kind == 1)
@@ -481,8 +562,12 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
 }
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
-                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int);
+                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
+                                  size_t);
 template void launch_gemm<float>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
-                                 const void*, int64_t, double, double, void*, int64_t, hipStream_t, int);
+                                 const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
+                                 size_t);
+template size_t gemm_workspace_bytes<double>(int64_t, int64_t, int64_t);
+template size_t gemm_workspace_bytes<float>(int64_t, int64_t, int64_t);
 
 }  // namespace lrcc

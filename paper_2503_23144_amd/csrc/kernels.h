@@ -67,11 +67,16 @@ void launch_gram(int64_t nvec, int m, int64_t n, const void* h, int64_t hs, cons
 
 // Dense complex GEMM C = alpha op(A) op(B) + beta C (no conjugation).
 // FP64: 4 real MFMA products per complex product; FP32: 3 (Gauss).
-// kind 1 marks the packed-vvvv ladder (a separate kernel symbol).
+// kind 1 marks the packed-vvvv ladder (a separate kernel symbol).  With a
+// device workspace of gemm_workspace_bytes<T>(m, n, k) bytes, deep products
+// with few output tiles are split over K (partials reduced in fixed order).
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st, int kind = 0);
+                 hipStream_t st, int kind = 0, void* ws = nullptr, size_t ws_bytes = 0);
+int gemm_splits(int64_t m, int64_t n, int64_t k);
+template <typename T>
+size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k);
 
 // Per-shape tile autotuning of launch_gemm (process-wide).
 void set_gemm_autotune(bool on);

@@ -95,6 +95,8 @@ class Executor {
     void* C;
     int64_t ldc;
     bool ladder;
+    void* ws;  // split-K partials (scratch slot 4)
+    size_t wsb;
   };
   struct RunKey {
     const OpList* ops;

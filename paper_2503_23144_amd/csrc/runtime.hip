@@ -38,8 +38,8 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   cap_.assign(n, 0);
   bound_.assign(n, 0);
   pooled_.assign(n, 0);
-  scr_.assign(4, nullptr);
-  scr_cap_.assign(4, 0);
+  scr_.assign(5, nullptr);  // 0-2 permutations, 3 uploads, 4 split-K partials
+  scr_cap_.assign(5, 0);
   HIP_CHECK(hipMalloc(&dot_out_, 64));
   HIP_CHECK(hipMalloc(&dot_work_, 1024 * 16));
 }
@@ -299,7 +299,9 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
                      ldb >= (tb ? K : N) && ldc >= N,
                  LRCC_E_INTERNAL, "gemm operands exceed their buffers");
   }
-  const GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder};
+  const size_t wsb = gemm_workspace_bytes<T>(M, N, K);
+  void* ws = wsb ? scratch(4, wsb) : nullptr;
+  const GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder, ws, wsb};
   if (capturing_) {
     if (timing_ && ladder) {  // leave the graph: the ladder is timed between segments
       end_segment();
@@ -307,7 +309,7 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
       launch_timed(g);
       HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     } else {
-      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0);
+      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0, ws, wsb);
     }
     return;
   }
@@ -322,7 +324,7 @@ void Executor<T>::launch_timed(const GemmArgs& g) {
     HIP_CHECK(hipEventRecord(e0, st_));
   }
   launch_gemm<T>(g.ta, g.tb, g.M, g.N, g.K, g.are, g.aim, g.A, g.lda, g.B, g.ldb, g.bre, 0.0, g.C, g.ldc, st_,
-                 g.ladder ? 1 : 0);
+                 g.ladder ? 1 : 0, g.ws, g.wsb);
   if (timing_) {
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));

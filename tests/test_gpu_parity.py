@@ -54,6 +54,30 @@ def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("m,n,k", [(37, 53, 5000), (64, 64, 20011), (1, 7, 3000), (200, 10, 4100), (130, 3, 70000)])
+def test_gemm_split_depth_matches_host_matmul(dtype, ta, tb, m, n, k):
+    """Deep products with few output tiles run split over K (partial tiles
+    reduced in a second kernel); alpha and beta apply after the reduction."""
+    lrcc = _lrcc()
+    rng = np.random.default_rng(m + 2 * n + k)
+    A = _rand(rng, *((k, m) if ta else (m, k)))
+    B = _rand(rng, *((n, k) if tb else (k, n)))
+    C0 = _rand(rng, m, n)
+    al, be = 0.3 + 0.9j, -0.5 + 0.25j
+    ref = al * ((A.T if ta else A) @ (B.T if tb else B)) + be * C0
+    dev = torch.device("cuda:0")
+    Cd = torch.tensor(C0, dtype=dtype, device=dev)
+    lrcc.gemm(torch.tensor(A, dtype=dtype, device=dev), torch.tensor(B, dtype=dtype, device=dev), Cd,
+              transa=bool(ta), transb=bool(tb), alpha=al, beta=be)
+    torch.cuda.synchronize()
+    got = Cd.cpu().numpy().astype(np.complex128)
+    scale = np.sqrt(k) * np.abs(A).max() * np.abs(B).max() + np.abs(C0).max()
+    eps = 1e-15 if dtype == torch.complex128 else 2e-7
+    assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_ragged_depth_repeated(dtype, ta, tb):
     """Depths that end in a partial 16-deep slab, each launched repeatedly
     (the partial slab's zero fill is ordered against the staging writes of
