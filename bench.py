@@ -88,6 +88,7 @@ def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
     they are seeded random numbers here."""
     import torch
     dev = torch.device("cuda:0")
+    lrcc.trim_memory()  # the library's cached blocks back to the device before torch allocates W
     po, pv = o * (o - 1) // 2, v * (v - 1) // 2
     M, N, K = nrhs * po, pv, pv
     g = torch.Generator(device=dev)
@@ -159,6 +160,7 @@ def _product_rates(lrcc, inp, nvec, graphs, stream, min_s=0.5):
                   file=sys.stderr, flush=True)
         c.close()
     del X, out
+    lrcc.trim_memory()
     torch.cuda.empty_cache()
     return rates
 
@@ -174,6 +176,7 @@ def sigma_rates(lrcc, names=("c1", "c2", "c3", "c4"), max_batch={"c4": 16}):
     import torch
 
     from paper_2503_23144_amd.synth import CONFIGS, config_inputs
+    lrcc.trim_memory()
     stream = torch.cuda.Stream()  # graphs are captured on the caller's stream unless it is the null stream
     table = {}
     for name in names:

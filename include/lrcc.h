@@ -81,7 +81,8 @@ typedef struct lrcc_config {
                             fastest (process-wide; cache file from LRCC_AUTOTUNE_CACHE); default 1 */
   int verbose;           /* 0 silent, 1 per-solve summary, 2 per-iteration lines on stderr */
   int graphs;            /* 1: replay the Jacobian-product programs as HIP graphs (captured on the
-                            second identical call, replayed from the third); default 1 */
+                            second identical call, replayed from the third); default 1, or 0 when
+                            the environment variable LRCC_GRAPHS is "0" */
 } lrcc_config;
 
 typedef struct lrcc_stats {
@@ -186,6 +187,13 @@ int lrcc_set_timing(lrcc_ctx *ctx, int on);
 /* Program runs captured into HIP graphs and graph replays so far (FP64 and
    FP32 executors together).  Either pointer may be NULL. */
 int lrcc_graph_stats(lrcc_ctx *ctx, int64_t *captures, int64_t *replays);
+
+/* Device memory released by contexts is kept by the library for reuse by
+   later allocations in this process (up to half of each device's memory);
+   this returns all of it to the devices.  Call it before allocating large
+   buffers elsewhere (e.g. with torch).  Synchronizes every device holding
+   cached memory. */
+int lrcc_trim_memory(void);
 
 /* Build identification string. */
 const char *lrcc_build_info(void);

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrcc.so")
 
-SOURCES = ["program.cpp", "kernels.hip", "gemm.hip", "runtime.hip", "integrals.hip", "solver.hip", "fnspp.hip",
+SOURCES = ["program.cpp", "devmem.hip", "kernels.hip", "gemm.hip", "runtime.hip", "integrals.hip", "solver.hip", "fnspp.hip",
            "abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

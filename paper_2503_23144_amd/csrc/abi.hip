@@ -2,11 +2,13 @@
 // Every call catches all C++ exceptions and maps them to LRCC_E_* codes.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
 
 #include "context.h"
+#include "devmem.h"
 #include "kernels.h"
 
 using lrcc::Context;
@@ -69,7 +71,8 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->rhs_chunk = 0;
   cfg->autotune = 1;
   cfg->verbose = 0;
-  cfg->graphs = 1;
+  const char* g = std::getenv("LRCC_GRAPHS");  // default override, e.g. for profiling launch by launch
+  cfg->graphs = (g && g[0] == '0') ? 0 : 1;
 }
 
 int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
@@ -383,6 +386,16 @@ int lrcc_graph_stats(lrcc_ctx* ctx, int64_t* captures, int64_t* replays) {
     if (captures) *captures = cap;
     if (replays) *replays = rep;
   });
+}
+
+int lrcc_trim_memory(void) {
+  try {
+    lrcc::dev_trim();
+    return LRCC_OK;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return LRCC_E_HIP;
+  }
 }
 
 const char* lrcc_build_info(void) { return "lrcc gfx950 HIP " __DATE__ " " __TIME__; }

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "devmem.h"
 #include "common.h"
 #include "program.h"
 #include "runtime.h"
@@ -24,14 +25,14 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     bytes = 0;
   }
   void* ensure(size_t b) {
     if (b > bytes) {
       release();
-      HIP_CHECK(hipMalloc(&p, std::max<size_t>(b, 16)));
+      p = dev_alloc(std::max<size_t>(b, 16));
       bytes = std::max<size_t>(b, 16);
     }
     return p;

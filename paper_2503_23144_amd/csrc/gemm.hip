@@ -25,6 +25,7 @@
 // (reuse of the B slab in that XCD's L2).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -33,6 +34,7 @@
 #include <tuple>
 
 #include "common.h"
+#include "devmem.h"
 #include "kernels.h"
 
 namespace lrcc {
@@ -464,6 +466,15 @@ static int heuristic_tile(int64_t m, int64_t n) {
   return 0;
 }
 
+// LRCC_TRACE_GEMM=1 prints every launch's shape and tile choice to stderr.
+static bool trace_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("LRCC_TRACE_GEMM");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
 // Split-K for deep products with few output tiles: a 64 x 64 tile grid of
 // fewer than 256 workgroups leaves most CUs idle while each workgroup walks
 // all of K, so the depth is split until about 1024 workgroups run, keeping
@@ -489,6 +500,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   {
     const int splits = gemm_splits(m, n, k);
     if (splits > 1 && ws && ws_bytes >= gemm_workspace_bytes<T>(m, n, k)) {
+      if (trace_on())
+        fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=0 splits=%d\n",
+                sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k,
+                splits);
       if (kind == 1)
         go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st, splits, ws);
       else
@@ -530,7 +545,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   if (tune && !small) {
     const int ncand = sizeof(T) == 4 ? 3 : 2;
     void* scratch = nullptr;
-    HIP_CHECK(hipMalloc(&scratch, (size_t)m * ldc * 2 * sizeof(T)));
+    scratch = dev_alloc((size_t)m * ldc * 2 * sizeof(T));
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -551,13 +566,16 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    HIP_CHECK(hipFree(scratch));
+    dev_free(scratch);
   }
   if (tune) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[key] = cfg;
     if (!small) save_entry(key, cfg);
   }
+  if (trace_on())
+    fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=%d splits=1\n",
+            sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k, cfg);
   run(cfg, C, bre, bim, false);
 }
 

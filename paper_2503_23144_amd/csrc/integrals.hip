@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <string>
 
+#include "devmem.h"
 #include "integrals.h"
 #include "kernels.h"
 
@@ -22,8 +23,8 @@ namespace {
 
 struct DevTmp {
   void* p = nullptr;
-  explicit DevTmp(size_t bytes) { HIP_CHECK(hipMalloc(&p, std::max<size_t>(bytes, 16))); }
-  ~DevTmp() { (void)hipFree(p); }
+  explicit DevTmp(size_t bytes) { p = dev_alloc(std::max<size_t>(bytes, 16)); }
+  ~DevTmp() { dev_free(p); }
 };
 
 constexpr size_t kChunkBytes = size_t(1) << 30;

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <tuple>
 
+#include "devmem.h"
 #include "kernels.h"
 
 namespace lrcc {
@@ -40,8 +41,8 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   pooled_.assign(n, 0);
   scr_.assign(5, nullptr);  // 0-2 permutations, 3 uploads, 4 split-K partials
   scr_cap_.assign(5, 0);
-  HIP_CHECK(hipMalloc(&dot_out_, 64));
-  HIP_CHECK(hipMalloc(&dot_work_, 1024 * 16));
+  dot_out_ = dev_alloc(64);
+  dot_work_ = dev_alloc(1024 * 16);
 }
 
 template <typename T>
@@ -51,13 +52,13 @@ Executor<T>::~Executor() {
   } catch (...) {
   }
   for (size_t k = 0; k < buf_.size(); ++k)
-    if (buf_[k] && !bound_[k] && !pooled_[k]) (void)hipFree(buf_[k]);
+    if (buf_[k] && !bound_[k] && !pooled_[k]) dev_free(buf_[k]);
   for (void* p : scr_)
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
   for (void* p : pool_)
-    if (p) (void)hipFree(p);
-  (void)hipFree(dot_out_);
-  (void)hipFree(dot_work_);
+    if (p) dev_free(p);
+  dev_free(dot_out_);
+  dev_free(dot_work_);
   if (gst_) (void)hipStreamDestroy(gst_);
   if (fork_) (void)hipEventDestroy(fork_);
   if (join_) (void)hipEventDestroy(join_);
@@ -84,10 +85,10 @@ void* Executor<T>::ptr(int id) {
     on_realloc();
     if (buf_[id]) {
       HIP_CHECK(hipStreamSynchronize(st_));
-      HIP_CHECK(hipFree(buf_[id]));
+      dev_free(buf_[id]);
       buf_[id] = nullptr;
     }
-    HIP_CHECK(hipMalloc(&buf_[id], std::max<int64_t>(need, 1) * sizeof(T) * 2));
+    buf_[id] = dev_alloc(std::max<int64_t>(need, 1) * sizeof(T) * 2);
     cap_[id] = need;
   }
   return buf_[id];
@@ -99,7 +100,7 @@ void Executor<T>::bind(int id, void* p) {
   if (buf_[id] && !bound_[id]) {
     on_realloc();
     HIP_CHECK(hipStreamSynchronize(st_));
-    HIP_CHECK(hipFree(buf_[id]));
+    dev_free(buf_[id]);
   }
   buf_[id] = p;
   cap_[id] = 0;
@@ -127,13 +128,13 @@ void Executor<T>::release_batched() {
   HIP_CHECK(hipStreamSynchronize(st_));
   for (size_t k = 0; k < buf_.size(); ++k)
     if (m_[k].batched && buf_[k] && !bound_[k] && !pooled_[k]) {
-      HIP_CHECK(hipFree(buf_[k]));
+      dev_free(buf_[k]);
       buf_[k] = nullptr;
       cap_[k] = 0;
     }
   for (size_t s = 0; s < pool_.size(); ++s)
     if (pool_[s]) {
-      HIP_CHECK(hipFree(pool_[s]));
+      dev_free(pool_[s]);
       pool_[s] = nullptr;
       pool_cap_[s] = 0;
     }
@@ -145,7 +146,7 @@ void Executor<T>::release_batched() {
     }
   for (size_t s = 0; s < scr_.size(); ++s)
     if (scr_[s]) {
-      HIP_CHECK(hipFree(scr_[s]));
+      dev_free(scr_[s]);
       scr_[s] = nullptr;
       scr_cap_[s] = 0;
     }
@@ -181,10 +182,10 @@ void* Executor<T>::scratch(int slot, size_t bytes) {
     on_realloc();
     if (scr_[slot]) {
       HIP_CHECK(hipStreamSynchronize(st_));
-      HIP_CHECK(hipFree(scr_[slot]));
+      dev_free(scr_[slot]);
     }
     size_t b = std::max(bytes, scr_cap_[slot] + scr_cap_[slot] / 4);
-    HIP_CHECK(hipMalloc(&scr_[slot], b));
+    scr_[slot] = dev_alloc(b);
     scr_cap_[slot] = b;
   }
   return scr_[slot];
@@ -658,10 +659,10 @@ void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& kee
       on_realloc();
       if (pool_[s]) {
         HIP_CHECK(hipStreamSynchronize(st_));
-        HIP_CHECK(hipFree(pool_[s]));
+        dev_free(pool_[s]);
         pool_[s] = nullptr;
       }
-      HIP_CHECK(hipMalloc(&pool_[s], pl.slot_elems[s] * sizeof(T) * 2));
+      pool_[s] = dev_alloc(pl.slot_elems[s] * sizeof(T) * 2);
       pool_cap_[s] = pl.slot_elems[s];
     }
   for (auto& ts : pl.slot) {
@@ -669,7 +670,7 @@ void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& kee
     if (buf_[t] && !bound_[t] && !pooled_[t]) {  // drop a private buffer from earlier runs
       on_realloc();
       HIP_CHECK(hipStreamSynchronize(st_));
-      HIP_CHECK(hipFree(buf_[t]));
+      dev_free(buf_[t]);
     }
     buf_[t] = pool_[ts.second];
     cap_[t] = pool_cap_[ts.second];

@@ -97,7 +97,7 @@ static void ensure_x32(Context& c) {
     }
     size_t fr = 0, tot = 0;
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    if ((double)fr < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
+    if ((double)(fr + dev_cached_bytes()) < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
   }
   c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
   c.x32->ladder_const = c.P.m.find("W");
@@ -712,7 +712,7 @@ static int fit_chunk(int nrhs, int64_t per, Executor<double>* x64, Executor<floa
   auto count = [&]() {
     size_t fr = 0, tot = 0;
     HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    double avail = (double)fr;
+    double avail = (double)fr + (double)dev_cached_bytes();  // the cache is returned on demand
     if (use64 && x64) avail += (double)x64->batched_bytes();
     if (use32 && x32) avail += (double)x32->batched_bytes();
     return (int64_t)(0.85 * avail) / std::max<int64_t>(per, 1);

@@ -77,6 +77,7 @@ _sig = {
     "lrcc_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "lrcc_set_timing": (_i, [_vp, _i]),
     "lrcc_graph_stats": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "lrcc_trim_memory": (_i, []),
     "lrcc_build_info": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -118,6 +119,14 @@ def build_info() -> str:
     return lib.lrcc_build_info().decode()
 
 
+def trim_memory():
+    """Return the device memory the library keeps for reuse (see
+    lrcc_trim_memory) to the device."""
+    rc = lib.lrcc_trim_memory()
+    if rc != OK:
+        raise LrccError(rc, lib.lrcc_last_error(None).decode())
+
+
 def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
     """C = alpha op(A) op(B) + beta C on contiguous 2-D device tensors
     (complex128: FP64 path; complex64: FP32 3M path)."""
@@ -142,7 +151,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True, graphs=True):
+                 verbose=0, autotune=True, graphs=None):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -157,7 +166,8 @@ class Context:
         cfg.rhs_chunk = rhs_chunk
         cfg.autotune = int(autotune)
         cfg.verbose = verbose
-        cfg.graphs = int(graphs)
+        if graphs is not None:  # else the library default (LRCC_GRAPHS)
+            cfg.graphs = int(graphs)
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:

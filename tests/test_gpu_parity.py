@@ -347,6 +347,27 @@ def test_graph_replay_full_pipeline_matches_eager():
     assert res[True][2][1] > 10
 
 
+# ------------------------------------------------------------------ device memory cache
+def test_memory_cache_reuse_and_trim():
+    """Contexts created one after another reuse the blocks their predecessors
+    freed (results unchanged); lrcc_trim_memory returns them to the device."""
+    lrcc = _lrcc()
+    inp = make_inputs(4, 16, 32, seed=0)
+    inp.B = inp.B * 8.0
+    es = []
+    for _ in range(3):
+        c = _ctx(inp, tol=1e-11)
+        e, _ = c.solve_ground()
+        es.append(e)
+        c.close()
+    assert es[0] == es[1] == es[2]
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    lrcc.trim_memory()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 > free0
+
+
 # ------------------------------------------------------------------ adjoint / autograd
 def test_autograd_wrapper_gradcheck_and_dot_product():
     lrcc = _lrcc()
