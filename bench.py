@@ -41,6 +41,22 @@ def host_info():
     return info
 
 
+def measured_traffic(workload):
+    """HBM bytes per ladder launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken for this workload and the GEMM source
+    has not changed since (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "ladder_o20_v150_hbm_traffic.md")
+    if workload != "c3" or not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_hip_sha256_16=([0-9a-f]{16})", open(path).read())
+    src = os.path.join(ROOT, "paper_2503_23144_amd", "csrc", "gemm.hip")
+    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(3):
+        return None
+    return {"bytes_per_launch": int(m.group(1)), "tile": m.group(2), "source": os.path.relpath(path, ROOT)}
+
+
 def resident(inp):
     """The workload's inputs (DF factors, Fock and dipole matrices) as device
     tensors, so that timed passes start from data already in HBM."""
@@ -279,6 +295,7 @@ def main():
     dt = time.perf_counter() - t0
     value = sig / dt
 
+    traffic = measured_traffic(args.workload)
     ladder_ms, ladder_n, ladder_fl = last["ladder"]
     gemm_ms, gemm_n, gemm_fl = last["gemm"]
     ladder_avg_s = ladder_ms / 1e3 / max(ladder_n, 1)
@@ -295,7 +312,9 @@ def main():
         "ladder_complex_equiv_tflops": ladder_tf * 8.0 / 6.0,
         "gemm_all_tflops": gemm_fl / max(gemm_ms / 1e3, 1e-30) / 1e12, "gemm_all_ms": gemm_ms, "gemm_launches": gemm_n,
         "roofline": {"bound": "mfma", "achieved": ladder_tf, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                     "frac": ladder_tf / PEAK["fp32"], "traffic": None,
+                     "frac": ladder_tf / PEAK["fp32"],
+                     "traffic": (traffic or {}).get("bytes_per_launch"), "traffic_unit": "bytes per launch",
+                     "traffic_source": traffic,
                      "kernel": "zgemm_kernel<float, false, true, 1> (packed vvvv ladder, 3M)",
                      "avg_launch_ms": 1e3 * ladder_avg_s, "launches": ladder_n},
     }

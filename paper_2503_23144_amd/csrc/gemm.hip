@@ -65,28 +65,36 @@ struct cpx<float> {
 __device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int BK = 16, NT = 256;
+constexpr int NT = 256;
 constexpr int PADK = 4;   // row layout [row][k]: row stride BK + PADK words (reads conflict-free)
 constexpr int PADR = 16;  // k-major layout [k][row]: row stride BM + PADR (lane groups on distinct banks)
 
 // Map a linear workgroup id to (tile_m, tile_n).  Hardware dispatches
 // consecutive ids round-robin over the 8 XCDs; regroup so that each XCD sees
-// a contiguous run of ids, which walk M fastest inside one N column.
+// a contiguous run of ids (XCDs 0..r-1 take one tile more when the grid does
+// not divide by 8).  Runs are then walked in groups of GM tile rows, M
+// fastest: 32 consecutive tiles on one XCD cover 8 x 4 tiles, so A and B
+// panels are both shared in that XCD's L2.
+constexpr int64_t GM = 8;
 __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& tm, int64_t& tn) {
-  int64_t total = nbm * nbn;
+  const int64_t total = nbm * nbn;
   int64_t id = bid;
-  if (total >= 64 && total % 8 == 0) {
-    int64_t per = total / 8;
-    id = (bid % 8) * per + bid / 8;
+  if (total >= 64) {
+    const int64_t q = total / 8, r = total % 8, x = bid % 8, j = bid / 8;
+    id = (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
   }
-  tm = id % nbm;
-  tn = id / nbm;
+  const int64_t width = GM * nbn;
+  const int64_t first_m = (id / width) * GM;
+  const int64_t gm = nbm - first_m < GM ? nbm - first_m : GM;
+  const int64_t rem = id % width;
+  tm = first_m + rem % gm;
+  tn = rem / gm;
 }
 
 // Register staging of one operand tile: IN elements along the dimension
 // that is contiguous in global memory, PER elements per thread, STEP rows of
 // the other dimension per pass of the 256 threads.
-template <int ROWS, bool KMAJ>
+template <int ROWS, bool KMAJ, int BK>
 struct Stage {
   static constexpr int IN = KMAJ ? ROWS : BK;
   static constexpr int PER = ROWS * BK / NT;
@@ -99,7 +107,7 @@ struct Stage {
 // consecutive banks:
 //   KMAJ (global contiguous along rows):  [k][row + PADR]
 //   row layout (global contiguous along k): [row][k + PADK]
-template <typename T, int ROWS, bool KMAJ>
+template <typename T, int ROWS, bool KMAJ, int BK>
 struct Tile {
   static constexpr int LD = KMAJ ? ROWS + PADR : BK + PADK;
   static constexpr int SIZE = KMAJ ? BK * LD : ROWS * LD;
@@ -113,7 +121,7 @@ struct Tile {
 //
 // Split-K: blockIdx.y selects the depth range [y * kchunk, (y + 1) * kchunk)
 // and the output C + y * cstride (partial products, reduced afterwards).
-template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM>
+template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM, int BK>
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
@@ -133,13 +141,14 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   constexpr int WGN = 4 / WGM;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TI = WM / 16, TJ = WN / 16;
-  using TA_ = Tile<T, BM, TA>;   // A stored [k][m] when transposed
-  using TB_ = Tile<T, BN, !TB>;  // B stored [k][n] when not transposed
+  using TA_ = Tile<T, BM, TA, BK>;   // A stored [k][m] when transposed
+  using TB_ = Tile<T, BN, !TB, BK>;  // B stored [k][n] when not transposed
   // two real planes (re, im) per stage; the Gauss sums are formed in
   // registers.  Double-buffer when two stages still leave room for two
   // workgroups per CU (160 KB LDS), else stage once with two barriers.
   constexpr int STAGE_BYTES = 2 * (TA_::SIZE + TB_::SIZE) * (int)sizeof(T);
-  constexpr int ST = 2 * STAGE_BYTES <= 81920 ? 2 : 1;
+  constexpr bool ONE_PER_CU = sizeof(T) == 4 && BM * BN >= 128 * 128;  // register-bound to 1 wave per SIMD
+  constexpr int ST = (2 * STAGE_BYTES <= 81920 || (ONE_PER_CU && 2 * STAGE_BYTES <= 160 * 1024)) ? 2 : 1;
   __shared__ T As[ST][2][TA_::SIZE];
   __shared__ T Bs[ST][2][TB_::SIZE];
 
@@ -159,8 +168,8 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   // columns of B beyond N only feed outputs that are never stored, and in the
   // last, partial K slab the A tile's k >= K entries are zeroed in LDS, which
   // cancels whatever B holds there.
-  using LA = Stage<BM, TA>;
-  using LB = Stage<BN, !TB>;
+  using LA = Stage<BM, TA, BK>;
+  using LB = Stage<BN, !TB, BK>;
   const int a_in = tid % LA::IN, a_out = tid / LA::IN;
   const int b_in = tid % LB::IN, b_out = tid / LB::IN;
   V2 ra[LA::PER], rb[LB::PER];
@@ -352,6 +361,9 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
                const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc, hipStream_t st,
                int splits = 1, void* ws = nullptr) {
   using V2 = typename cpx<T>::type;
+  // deeper slabs for the FP32 128 x 128 tile (one workgroup per CU: fewer
+  // barriers and a longer prefetch distance)
+  constexpr int BK = (sizeof(T) == 4 && BM == 128 && BN == 128) ? 32 : 16;
   int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
   LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
   // split-K: equal depth ranges, multiples of the slab depth, none empty
@@ -366,7 +378,7 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
     ar = 1, ai = 0, br = 0, bi = 0;
   }
 #define GO_(TA_, TB_)                                                                                        \
-  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
+  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM, BK>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
                      0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, ldo, \
                      kchunk, cstride)
   if (!ta && !tb)
