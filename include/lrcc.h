@@ -188,6 +188,23 @@ int lrcc_set_timing(lrcc_ctx *ctx, int on);
    FP32 executors together).  Either pointer may be NULL. */
 int lrcc_graph_stats(lrcc_ctx *ctx, int64_t *captures, int64_t *replays);
 
+/* Caller-owned device memory.  lrcc_workspace_bytes estimates (from sizes
+   alone, no device needed) the device bytes of the whole pipeline -- load,
+   T, Lambda, and X/Y solved in batches of up to nrhs right-hand sides, at
+   cfg->precision (cfg may be NULL for the defaults) -- or returns 0 for
+   invalid sizes.  FNS++ truncation is not included.  lrcc_set_workspace
+   hands the context a device buffer of `bytes` bytes (at least 1 MiB); it
+   must come once, right after lrcc_create and before lrcc_load_df
+   (LRCC_E_STATE otherwise).  From then on every allocation of the context
+   is carved from that buffer and nothing is taken from the device; batch
+   sizes adapt to what is free in it, and an allocation that does not fit
+   fails with LRCC_E_NOMEM.  The buffer stays owned by the caller, who frees
+   it after lrcc_destroy.  lrcc_workspace_peak returns the most of it in use
+   at any time so far (0 without a workspace). */
+size_t lrcc_workspace_bytes(const lrcc_config *cfg, int nocc, int nvir, int naux, int nrhs);
+int lrcc_set_workspace(lrcc_ctx *ctx, void *dptr, size_t bytes);
+size_t lrcc_workspace_peak(const lrcc_ctx *ctx);
+
 /* Device memory released by contexts is kept by the library for reuse by
    later allocations in this process (up to half of each device's memory);
    this returns all of it to the devices.  Call it before allocating large

@@ -15,6 +15,7 @@ using lrcc::Context;
 using lrcc::Error;
 
 struct lrcc_ctx {
+  std::unique_ptr<lrcc::Arena> arena;  // caller-owned workspace (outlives impl)
   std::unique_ptr<Context> impl;
   std::string err;
 };
@@ -24,6 +25,7 @@ static thread_local std::string g_create_error;
 template <typename F>
 static int guard(lrcc_ctx* ctx, F&& f) {
   if (!ctx || !ctx->impl) return LRCC_E_INVALID;
+  lrcc::ArenaScope scope(ctx->arena.get());  // every allocation of this call comes from the workspace
   try {
     HIP_CHECK(hipSetDevice(ctx->impl->cfg.device));
     f(*ctx->impl);
@@ -107,7 +109,11 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
 void lrcc_destroy(lrcc_ctx* ctx) {
   if (!ctx) return;
   try {
-    if (ctx->impl) (void)hipSetDevice(ctx->impl->cfg.device);
+    lrcc::ArenaScope scope(ctx->arena.get());  // workspace blocks go back to the workspace
+    if (ctx->impl) {
+      (void)hipSetDevice(ctx->impl->cfg.device);
+      if (ctx->arena) (void)hipStreamSynchronize(ctx->impl->st);  // the caller may free the buffer next
+    }
     ctx->impl.reset();
   } catch (...) {
   }
@@ -387,6 +393,34 @@ int lrcc_graph_stats(lrcc_ctx* ctx, int64_t* captures, int64_t* replays) {
     if (replays) *replays = rep;
   });
 }
+
+size_t lrcc_workspace_bytes(const lrcc_config* cfg, int nocc, int nvir, int naux, int nrhs) {
+  try {
+    lrcc_config c;
+    lrcc_default_config(&c);
+    if (cfg) c = *cfg;
+    return lrcc::workspace_estimate(c, nocc, nvir, naux, nrhs);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int lrcc_set_workspace(lrcc_ctx* ctx, void* dptr, size_t bytes) {
+  if (!ctx || !ctx->impl) return LRCC_E_INVALID;
+  if (!dptr || bytes < (size_t(1) << 20)) {
+    ctx->err = "workspace must be a device pointer to at least 1 MiB";
+    return LRCC_E_INVALID;
+  }
+  if (ctx->arena || ctx->impl->n != 0) {
+    ctx->err = "lrcc_set_workspace must come once, before lrcc_load_df";
+    return LRCC_E_STATE;
+  }
+  ctx->arena.reset(new lrcc::Arena(dptr, bytes));
+  ctx->err.clear();
+  return LRCC_OK;
+}
+
+size_t lrcc_workspace_peak(const lrcc_ctx* ctx) { return (ctx && ctx->arena) ? ctx->arena->peak() : 0; }
 
 int lrcc_trim_memory(void) {
   try {

@@ -53,6 +53,9 @@ struct SolveStats {
 
 enum class Side { Right, Left };
 
+// Device bytes the pipeline needs with batches of up to nrhs right-hand sides.
+size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nrhs);
+
 struct Context {
   explicit Context(const lrcc_config& cfg);
   ~Context();

@@ -7,10 +7,17 @@
 // cached only after a device synchronization, so no stream can still be using
 // it when it is reused.  A failing allocation first returns the cache to the
 // device and retries; lrcc_trim_memory returns it on request.
+//
+// A context given a caller-owned workspace (lrcc_set_workspace) takes all
+// its memory from that buffer instead, through an Arena active on the
+// calling thread for the duration of each of its entry points.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <map>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 
 #include "common.h"
@@ -52,9 +59,71 @@ void trim_device(int dev) {  // caller holds g_mu
   g_cached[dev] = 0;
 }
 
+thread_local Arena* t_arena = nullptr;
+
 }  // namespace
 
+// ---------------------------------------------------------------- arena
+Arena::Arena(void* base, size_t bytes) : base_((char*)base), size_(bytes) {
+  // the usable range starts at the first 256-byte boundary
+  const size_t skew = (256 - ((uintptr_t)base_ & 255)) & 255;
+  if (bytes > skew) free_[skew] = bytes - skew;
+  used_ = std::min(skew, bytes);
+}
+
+void* Arena::alloc(size_t bytes) {
+  const size_t b = (std::max<size_t>(bytes, 16) + 255) / 256 * 256;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < b) continue;
+    const size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > b) free_[off + b] = len - b;
+    void* p = base_ + off;
+    live_[p] = b;
+    used_ += b;
+    peak_ = std::max(peak_, used_);
+    return p;
+  }
+  throw Error(LRCC_E_NOMEM, "workspace too small: " + std::to_string(b) + " bytes requested, " +
+                                std::to_string(largest_free()) + " in the largest free range");
+}
+
+bool Arena::owns(const void* p) const { return p >= base_ && p < base_ + size_; }
+
+void Arena::free(void* p) {
+  auto it = live_.find(p);
+  if (it == live_.end()) return;
+  size_t off = (char*)p - base_, len = it->second;
+  live_.erase(it);
+  used_ -= len;
+  auto nx = free_.lower_bound(off);
+  if (nx != free_.end() && off + len == nx->first) {  // merge with the next range
+    len += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {  // merge with the previous range
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      pv->second += len;
+      return;
+    }
+  }
+  free_[off] = len;
+}
+
+size_t Arena::largest_free() const {
+  size_t m = 0;
+  for (auto& kv : free_) m = std::max(m, kv.second);
+  return m;
+}
+
+ArenaScope::ArenaScope(Arena* a) : prev_(t_arena) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = prev_; }
+Arena* current_arena() { return t_arena; }
+
+// ---------------------------------------------------------------- device memory
 void* dev_alloc(size_t bytes) {
+  if (t_arena) return t_arena->alloc(bytes);
   int dev = 0;
   HIP_CHECK(hipGetDevice(&dev));
   const size_t b = round_up(bytes);
@@ -86,6 +155,10 @@ void* dev_alloc(size_t bytes) {
 
 void dev_free(void* p) {
   if (!p) return;
+  if (t_arena && t_arena->owns(p)) {  // stream-ordered reuse within the context
+    t_arena->free(p);
+    return;
+  }
   std::lock_guard<std::mutex> g(g_mu);
   auto it = g_live.find(p);
   if (it == g_live.end()) {  // not ours
@@ -119,6 +192,13 @@ void dev_trim() {
     trim_device(kv.first);
   }
   (void)hipSetDevice(cur);
+}
+
+size_t dev_available() {
+  if (t_arena) return t_arena->free_bytes();
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+  return fr + dev_cached_bytes();
 }
 
 size_t dev_cached_bytes() {

@@ -73,7 +73,7 @@ void build_packed_vvvv(const void* Bdev, int64_t naux, int64_t o, int64_t v, voi
   DevTmp L(naux * v * v * 16);
   launch_gather_block(naux, nmo, o, v, o, v, Bdev, L.p, st);
   int64_t a0 = 0;
-  DevTmp tmp(kChunkBytes);
+  DevTmp tmp(std::min<int64_t>((int64_t)kChunkBytes, v * v * v * v * 16));
   while (a0 < v - 1) {
     int64_t per_a = v * (v - a0) * v * 16;
     int64_t na = std::max<int64_t>(1, std::min<int64_t>(v - 1 - a0, (int64_t)kChunkBytes / per_a));

@@ -36,6 +36,17 @@ struct KernelTimes {
   void clear() { *this = KernelTimes(); }
 };
 
+// Liveness plan of the batched transients of one program run: pool slot
+// sizes (complex elements) and the (tensor, slot) assignment.  Tensors in
+// `keep` and bound tensors are not pooled.
+struct PoolPlan {
+  std::vector<std::pair<int, int>> slot;
+  std::vector<int64_t> slot_elems;
+};
+int64_t tensor_elems(const Module& m, const Dims& d, int id, int nb);
+PoolPlan plan_pool(const Module& m, const Dims& d, const OpList& ops, int nb, const std::vector<int>& keep,
+                   const std::vector<char>* bound);
+
 template <typename T>
 class Executor {
  public:
@@ -51,8 +62,6 @@ class Executor {
   void unbind(int id);
   void set_max_batch(int nb);
   int max_batch() const { return max_nb_; }
-  // Copy host/device data into an owned tensor (converting FP64 -> T).
-  void upload(int id, const void* src_fp64, int nb = 1);
   // Run a program at batch nb.  Batched tensors written by the program
   // (except those listed in `keep`) are transient: they live in a pool whose
   // buffers are reused once a tensor's last reader has run.
@@ -143,12 +152,8 @@ class Executor {
             int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
             int64_t capC, bool ladder);
 
-  struct Plan {
-    std::vector<std::pair<int, int>> slot;  // (tensor, pool slot) of each transient
-    std::vector<int64_t> slot_elems;
-  };
-  const Plan& plan_for(const OpList& ops, int nb, const std::vector<int>& keep);
-  std::map<std::pair<const OpList*, int>, Plan> plans_;
+  const PoolPlan& plan_for(const OpList& ops, int nb, const std::vector<int>& keep);
+  std::map<std::pair<const OpList*, int>, PoolPlan> plans_;
   std::vector<void*> pool_;
   std::vector<int64_t> pool_cap_;
   std::vector<char> pooled_;

@@ -164,19 +164,6 @@ size_t Executor<T>::bytes_allocated() const {
 }
 
 template <typename T>
-void Executor<T>::upload(int id, const void* src, int nb) {
-  int64_t n = elems(id, nb);
-  void* dst = ptr(id);
-  if constexpr (sizeof(T) == 8) {
-    HIP_CHECK(hipMemcpyAsync(dst, src, n * 16, hipMemcpyDefault, st_));
-  } else {
-    void* tmp = scratch(3, n * 16);
-    HIP_CHECK(hipMemcpyAsync(tmp, src, n * 16, hipMemcpyDefault, st_));
-    launch_d2s(n, tmp, dst, st_);
-  }
-}
-
-template <typename T>
 void* Executor<T>::scratch(int slot, size_t bytes) {
   if (scr_cap_[slot] < bytes) {
     on_realloc();
@@ -577,12 +564,16 @@ void Executor<T>::unpack(const Op& op, int nb) {
   launch_unpack<T>(ptr(op.a), ptr(op.out), d, op.are, op.aim, op.acc, st_);
 }
 
-template <typename T>
-const typename Executor<T>::Plan& Executor<T>::plan_for(const OpList& ops, int nb, const std::vector<int>& keep) {
-  auto key = std::make_pair(&ops, nb);
-  auto it = plans_.find(key);
-  if (it != plans_.end()) return it->second;
-  const int nt = (int)m_.tensors.size();
+int64_t tensor_elems(const Module& m, const Dims& d, int id, int nb) {
+  const TensorDecl& t = m[id];
+  int64_t n = t.batched ? nb : 1;
+  for (char c : t.cls) n *= d.of(c);
+  return n;
+}
+
+PoolPlan plan_pool(const Module& m, const Dims& d, const OpList& ops, int nb, const std::vector<int>& keep,
+                   const std::vector<char>* bound) {
+  const int nt = (int)m.tensors.size();
   std::vector<int> first(nt, -1), last(nt, -1);
   std::vector<char> is_keep(nt, 0);
   for (int k : keep) is_keep[k] = 1;
@@ -593,13 +584,13 @@ const typename Executor<T>::Plan& Executor<T>::plan_for(const OpList& ops, int n
     if (op.a >= 0) last[op.a] = std::max(last[op.a], k);
     if (op.b >= 0) last[op.b] = std::max(last[op.b], k);
   }
-  Plan pl;
+  PoolPlan pl;
   std::vector<int> slot_of(nt, -1);
   std::vector<char> busy;
   for (int k = 0; k < (int)ops.size(); ++k) {
     int t = ops[k].out;
-    if (first[t] == k && m_[t].batched && !is_keep[t] && !bound_[t]) {
-      int64_t need = elems(t, nb);
+    if (first[t] == k && m[t].batched && !is_keep[t] && !(bound && (*bound)[t])) {
+      int64_t need = tensor_elems(m, d, t, nb);
       int best = -1;
       for (int s = 0; s < (int)pl.slot_elems.size(); ++s)
         if (!busy[s] && (best < 0 || std::abs(pl.slot_elems[s] - need) < std::abs(pl.slot_elems[best] - need)))
@@ -619,12 +610,20 @@ const typename Executor<T>::Plan& Executor<T>::plan_for(const OpList& ops, int n
     for (int u : used)
       if (u >= 0 && slot_of[u] >= 0 && last[u] == k) busy[slot_of[u]] = 0;
   }
-  return plans_.emplace(key, std::move(pl)).first->second;
+  return pl;
+}
+
+template <typename T>
+const PoolPlan& Executor<T>::plan_for(const OpList& ops, int nb, const std::vector<int>& keep) {
+  auto key = std::make_pair(&ops, nb);
+  auto it = plans_.find(key);
+  if (it != plans_.end()) return it->second;
+  return plans_.emplace(key, plan_pool(m_, d_, ops, nb, keep, &bound_)).first->second;
 }
 
 template <typename T>
 int64_t Executor<T>::transient_bytes(const OpList& ops, int nb, const std::vector<int>& keep) {
-  const Plan& pl = plan_for(ops, nb, keep);
+  const PoolPlan& pl = plan_for(ops, nb, keep);
   int64_t e = 0, big = 0;
   for (int64_t x : pl.slot_elems) e += x;
   for (int k : keep)
@@ -649,7 +648,7 @@ size_t Executor<T>::batched_bytes() const {
 
 template <typename T>
 void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& keep) {
-  const Plan& pl = plan_for(ops, nb, keep);
+  const PoolPlan& pl = plan_for(ops, nb, keep);
   if (pool_.size() < pl.slot_elems.size()) {
     pool_.resize(pl.slot_elems.size(), nullptr);
     pool_cap_.resize(pl.slot_elems.size(), 0);

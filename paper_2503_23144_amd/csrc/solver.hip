@@ -95,9 +95,7 @@ static void ensure_x32(Context& c) {
       Role r = c.P.m[(int)id].role;
       if (r == Role::Const || r == Role::Scalar1 || r == Role::Fock) need += c.x64->elems((int)id, 1) * 8;
     }
-    size_t fr = 0, tot = 0;
-    HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    if ((double)(fr + dev_cached_bytes()) < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
+    if ((double)dev_available() < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
   }
   c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
   c.x32->ladder_const = c.P.m.find("W");
@@ -710,9 +708,7 @@ void Context::solve_lambda(SolveStats& so) {
 // that will not run is released first.
 static int fit_chunk(int nrhs, int64_t per, Executor<double>* x64, Executor<float>* x32, bool use64, bool use32) {
   auto count = [&]() {
-    size_t fr = 0, tot = 0;
-    HIP_CHECK(hipMemGetInfo(&fr, &tot));
-    double avail = (double)fr + (double)dev_cached_bytes();  // the cache is returned on demand
+    double avail = (double)dev_available();  // free + cached device memory, or the workspace's free bytes
     if (use64 && x64) avail += (double)x64->batched_bytes();
     if (use32 && x32) avail += (double)x32->batched_bytes();
     return (int64_t)(0.85 * avail) / std::max<int64_t>(per, 1);
@@ -724,6 +720,63 @@ static int fit_chunk(int nrhs, int64_t per, Executor<double>* x64, Executor<floa
     k = count();
   }
   return (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, k));
+}
+
+// Device bytes for the whole pipeline (load, T, Lambda, X/Y in batches of
+// up to nrhs right-hand sides, alpha) at the configured precision: the sum
+// of every buffer the context, its executors and the solves allocate, with
+// the batched parts sized by the same liveness plans the executors use.
+size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nrhs) {
+  if (o < 2 || v < 2 || naux < 1 || nrhs < 1) return 0;
+  static CcPrograms P = [] {
+    CcPrograms p;
+    build_programs(p);
+    return p;
+  }();
+  const Module& m = P.m;
+  const Dims d{o, v, (int64_t)o * (o - 1) / 2, (int64_t)v * (v - 1) / 2};
+  const int64_t nmo = o + v, n = (int64_t)o * v + d.O * d.V;
+  const bool mixed = cfg.precision == LRCC_MIXED;
+  const int nb = nrhs;
+  // context buffers: B, F, mu, D, t, lambda, work, xi, eta, X, Y (+ FP32 copies)
+  double bytes = 16.0 * ((double)naux * nmo * nmo + 4.0 * nmo * nmo) + 8.0 * n + 16.0 * n * (3 + 6) +
+                 2 * 16.0 * (double)nrhs * n + (mixed ? 8.0 * n * (2 + nb) : 0.0);
+  // one executor: its unbatched tensors (constants, Fock blocks, primal
+  // intermediates), the pool, the batched tensors outside the pool, scratch
+  auto executor = [&](double elem, const std::vector<std::pair<const OpList*, int>>& runs) {
+    double b = 0;
+    for (size_t id = 0; id < m.tensors.size(); ++id)
+      if (!m.tensors[id].batched) b += elem * (double)tensor_elems(m, d, (int)id, 1);
+    std::vector<int64_t> pool;
+    std::vector<char> pooled(m.tensors.size(), 0), used(m.tensors.size(), 0);
+    int64_t big = 0;
+    for (auto& r : runs) {
+      PoolPlan pl = plan_pool(m, d, *r.first, r.second, {}, nullptr);
+      if (pool.size() < pl.slot_elems.size()) pool.resize(pl.slot_elems.size(), 0);
+      for (size_t k = 0; k < pl.slot_elems.size(); ++k) pool[k] = std::max(pool[k], pl.slot_elems[k]);
+      for (auto& ts : pl.slot) pooled[ts.first] = 1;
+      for (const Op& op : *r.first)
+        for (int u : {op.out, op.a, op.b})
+          if (u >= 0 && m.tensors[u].batched) {
+            used[u] = 1;
+            big = std::max(big, tensor_elems(m, d, u, r.second));
+          }
+    }
+    for (int64_t e : pool) b += elem * (double)e;
+    for (size_t id = 0; id < m.tensors.size(); ++id)
+      if (used[id] && !pooled[id]) b += elem * (double)tensor_elems(m, d, (int)id, nb);
+    b += elem * 4.0 * (double)big;  // three permutation slots and one tile-timing output
+    return b + 96.0 * (1 << 20);     // split-K partials and small buffers
+  };
+  bytes += executor(16.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 3}, {&P.eta0, 1},
+                           {&P.gradL, 1}, {&P.hvp, nb}});
+  if (mixed) bytes += executor(8.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.gradL, 1}, {&P.hvpt, nb}});
+  // solver buffers per right-hand side (iterates, residuals, driving terms,
+  // DIIS history, products, certification)
+  bytes += (double)nb * (2.0 * std::max(cfg.diis_size, 0) + 12.0) * 16.0 * n;
+  // integral build temporaries (freed before the solves; counted on top)
+  bytes += 4.0 * 16.0 * naux * (double)v * v + (double)(size_t(1) << 30);
+  return (size_t)(1.1 * bytes) + (size_t(64) << 20);
 }
 
 int Context::rhs_chunk_for(int nrhs, int prec) {

@@ -78,6 +78,9 @@ _sig = {
     "lrcc_set_timing": (_i, [_vp, _i]),
     "lrcc_graph_stats": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "lrcc_trim_memory": (_i, []),
+    "lrcc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Config), _i, _i, _i, _i]),
+    "lrcc_set_workspace": (_i, [_vp, _vp, ctypes.c_size_t]),
+    "lrcc_workspace_peak": (ctypes.c_size_t, [_vp]),
     "lrcc_build_info": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -117,6 +120,16 @@ def program_text(which: int) -> str:
 
 def build_info() -> str:
     return lib.lrcc_build_info().decode()
+
+
+def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8):
+    """Device bytes of the whole pipeline with batches of up to nrhs
+    right-hand sides (lrcc_workspace_bytes)."""
+    cfg = Config()
+    lib.lrcc_default_config(ctypes.byref(cfg))
+    cfg.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+    cfg.diis_size = diis
+    return int(lib.lrcc_workspace_bytes(ctypes.byref(cfg), o, v, naux, nrhs))
 
 
 def trim_memory():
@@ -274,6 +287,15 @@ class Context:
         ms, ln, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
         self._check(lib.lrcc_kernel_time(self._h, cls, ctypes.byref(ms), ctypes.byref(ln), ctypes.byref(fl)))
         return ms.value, ln.value, fl.value
+
+    def set_workspace(self, buf):
+        """Carve every device allocation of this context from `buf` (a device
+        tensor the caller keeps alive until close()); before load_df."""
+        self._workspace = buf
+        self._check(lib.lrcc_set_workspace(self._h, buf.data_ptr(), buf.numel() * buf.element_size()))
+
+    def workspace_peak(self):
+        return int(lib.lrcc_workspace_peak(self._h))
 
     def graph_stats(self):
         """(program runs captured into HIP graphs, graph replays)."""

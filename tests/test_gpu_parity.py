@@ -368,6 +368,57 @@ def test_memory_cache_reuse_and_trim():
     assert free1 > free0
 
 
+# ------------------------------------------------------------------ caller-owned workspace
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_workspace_pipeline_matches_default_allocation(precision):
+    """With a caller-owned workspace of lrcc_workspace_bytes, the whole
+    pipeline runs inside it and gives the same alpha; a workspace that is
+    too small fails cleanly; the workspace must precede load_df."""
+    lrcc = _lrcc()
+    inp = make_inputs(3, 17, 11, seed=5)
+    inp.B = inp.B * 8.0
+    omegas = [0.0, 0.1]
+    nrhs = 3 * len(omegas)
+    ref = _ctx(inp, precision=precision, tol=1e-10)
+    ref.solve_ground()
+    ref.solve_lambda()
+    ref.solve_response(omegas)
+    a_ref = ref.alpha(len(omegas))
+    ref.close()
+    est = lrcc.workspace_bytes(inp.o, inp.v, inp.naux, nrhs, precision)
+    assert est > 0
+    buf = torch.empty(est, dtype=torch.uint8, device="cuda:0")
+    c = lrcc.Context(precision=precision, tol=1e-10)
+    c.set_workspace(buf)
+    c.load_df(inp.o, inp.v, inp.B)
+    c.load_fock(inp.fock)
+    c.load_dipoles(inp.mu)
+    c.solve_ground()
+    c.solve_lambda()
+    c.solve_response(omegas)
+    a = c.alpha(len(omegas))
+    peak = c.workspace_peak()
+    c.close()
+    assert 0 < peak <= est
+    assert _relerr(a, a_ref) < 1e-12
+    print(f"workspace estimate {est} bytes, peak use {peak} ({peak / est:.2f})")
+    # too small: a clean LRCC_E_NOMEM, nothing taken from the device
+    small = torch.empty(2 << 20, dtype=torch.uint8, device="cuda:0")
+    c = lrcc.Context(precision=precision)
+    c.set_workspace(small)
+    with pytest.raises(lrcc.LrccError) as e:
+        c.load_df(inp.o, inp.v, inp.B)
+    assert e.value.code == lrcc.E_NOMEM
+    c.close()
+    # order: the workspace comes before load_df
+    c = _ctx(inp)
+    with pytest.raises(lrcc.LrccError) as e:
+        c.set_workspace(buf)
+    assert e.value.code == lrcc.E_STATE
+    c.close()
+    del buf, small
+
+
 # ------------------------------------------------------------------ adjoint / autograd
 def test_autograd_wrapper_gradcheck_and_dot_product():
     lrcc = _lrcc()
