@@ -125,7 +125,7 @@ template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM, int B
 __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
-                                                  T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc,
+                                                  T bim, typename cpx<T>::type* __restrict__ C, OutMap om,
                                                   int64_t kchunk, int64_t cstride) {
   using V2 = typename cpx<T>::type;
   {
@@ -302,17 +302,25 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
     __syncthreads();
   }
 
-  // epilogue: register r of a lane holds row cpx<T>::row(lane/16, r), column lane%16
+  // epilogue: register r of a lane holds row cpx<T>::row(lane/16, r), column
+  // lane%16; element (m, n) goes to C + om.row(m) + om.col(n)
   const bool use_beta = (bre != T(0) || bim != T(0));
+  int64_t coff[TJ];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) {
+    const int64_t gn = n0 + wn + j * 16 + r16;
+    coff[j] = gn < N ? om.col(gn) : -1;
+  }
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < TJ; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gm = m0 + wm + i * 16 + cpx<T>::row(kq, r);
+      if (gm >= M) continue;
+      const int64_t roff = om.row(gm);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int64_t gm = m0 + wm + i * 16 + cpx<T>::row(kq, r);
-        int64_t gn = n0 + wn + j * 16 + r16;
-        if (gm >= M || gn >= N) continue;
+      for (int j = 0; j < TJ; ++j) {
+        if (coff[j] < 0) continue;
         T re, im;
         if constexpr (!G3) {
           re = acc[0][i][j][r];
@@ -323,7 +331,7 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
           im = p3 - p1 - p2;
         }
         T cr = are * re - aim * im, ci = are * im + aim * re;
-        V2* c = C + gm * ldc + gn;
+        V2* c = C + roff + coff[j];
         if (use_beta) {
           V2 y = *c;
           cr += bre * y.x - bim * y.y;
@@ -331,12 +339,13 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
         }
         *c = V2{cr, ci};
       }
+    }
 }
 
 // C = alpha * sum_s P[s] + beta * C over an m x n tile set (split-K reduction)
 template <typename T>
 __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typename cpx<T>::type* __restrict__ P,
-                                     T are, T aim, T bre, T bim, typename cpx<T>::type* __restrict__ C, int64_t ldc) {
+                                     T are, T aim, T bre, T bim, typename cpx<T>::type* __restrict__ C, OutMap om) {
   const int64_t total = m * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     T sr = 0, si = 0;
@@ -346,7 +355,7 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typ
       si += p.y;
     }
     T cr = are * sr - aim * si, ci = are * si + aim * sr;
-    typename cpx<T>::type* c = C + (e / n) * ldc + e % n;
+    typename cpx<T>::type* c = C + om.row(e / n) + om.col(e % n);
     if (bre != T(0) || bim != T(0)) {
       const typename cpx<T>::type y = *c;
       cr += bre * y.x - bim * y.y;
@@ -358,7 +367,7 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typ
 
 template <typename T, int KIND, int BM, int BN, int WGM>
 static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A, int64_t lda,
-               const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc, hipStream_t st,
+               const void* B, int64_t ldb, double bre, double bim, void* C, const OutMap& om, hipStream_t st,
                int splits = 1, void* ws = nullptr) {
   using V2 = typename cpx<T>::type;
   // deeper slabs for the FP32 128 x 128 tile (one workgroup per CU: fewer
@@ -369,17 +378,17 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
   // split-K: equal depth ranges, multiples of the slab depth, none empty
   int64_t kchunk = k, cstride = 0;
   void* out = C;
-  int64_t ldo = ldc;
+  OutMap mo = om;
   double ar = are, ai = aim, br = bre, bi = bim;
   if (splits > 1) {
     kchunk = ((k + splits - 1) / splits + BK - 1) / BK * BK;
     splits = (int)((k + kchunk - 1) / kchunk);
-    out = ws, ldo = n, cstride = m * n;
+    out = ws, mo = OutMap::plain(n), cstride = m * n;
     ar = 1, ai = 0, br = 0, bi = 0;
   }
 #define GO_(TA_, TB_)                                                                                        \
   hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM, BK>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
-                     0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, ldo, \
+                     0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, mo,  \
                      kchunk, cstride)
   if (!ta && !tb)
     GO_(false, false);
@@ -395,7 +404,7 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
     const int64_t total = m * n;
     const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(blocks), dim3(256), 0, st, m, n, splits, (const V2*)ws, (T)are,
-                       (T)aim, (T)bre, (T)bim, (V2*)C, ldc);
+                       (T)aim, (T)bre, (T)bim, (V2*)C, om);
     HIP_CHECK(hipGetLastError());
   }
 }
@@ -410,14 +419,14 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 template <typename T, int KIND>
 static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
                      const void* A, int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C,
-                     int64_t ldc, hipStream_t st) {
+                     const OutMap& om, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {  // the FP64 128 x 128 tile does not fit the register file
-    if (cfgid == 2) return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+    if (cfgid == 2) return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
   }
   if (cfgid >= 1)
-    go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+    go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
   else
-    go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st);
+    go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
 }
 
 namespace {
@@ -507,8 +516,9 @@ size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st, int kind, void* ws, size_t ws_bytes) {
+                 hipStream_t st, int kind, void* ws, size_t ws_bytes, const OutMap* omap) {
   if (m <= 0 || n <= 0) return;
+  const OutMap om = omap ? *omap : OutMap::plain(ldc);
   {
     const int splits = gemm_splits(m, n, k);
     if (splits > 1 && ws && ws_bytes >= gemm_workspace_bytes<T>(m, n, k)) {
@@ -517,22 +527,23 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
                 sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k,
                 splits);
       if (kind == 1)
-        go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st, splits, ws);
+        go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws);
       else
-        go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, ldc, st, splits, ws);
+        go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws);
       return;
     }
   }
   auto run = [&](int cfg, void* Cout, double br, double bi, bool probe) {
-    if (probe) {
+    if (probe) {  // plain layout into the scratch output
+      const OutMap pm = OutMap::plain(n);
       if (kind == 1)
-        dispatch<T, 3>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+        dispatch<T, 3>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st);
       else
-        dispatch<T, 2>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+        dispatch<T, 2>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st);
     } else if (kind == 1) {
-      dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+      dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st);
     } else {
-      dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, ldc, st);
+      dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st);
     }
   };
   int cfg = heuristic_tile<T>(m, n);
@@ -557,7 +568,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   if (tune && !small) {
     const int ncand = sizeof(T) == 4 ? 3 : 2;
     void* scratch = nullptr;
-    scratch = dev_alloc((size_t)m * ldc * 2 * sizeof(T));
+    scratch = dev_alloc((size_t)m * n * 2 * sizeof(T));
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
@@ -593,10 +604,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                   const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                  size_t);
+                                  size_t, const OutMap*);
 template void launch_gemm<float>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                 size_t);
+                                 size_t, const OutMap*);
 template size_t gemm_workspace_bytes<double>(int64_t, int64_t, int64_t);
 template size_t gemm_workspace_bytes<float>(int64_t, int64_t, int64_t);
 

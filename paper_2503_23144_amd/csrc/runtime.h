@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "common.h"
+#include "kernels.h"
 #include "program.h"
 
 namespace lrcc {
@@ -106,6 +107,8 @@ class Executor {
     bool ladder;
     void* ws;  // split-K partials (scratch slot 4)
     size_t wsb;
+    OutMap om;  // output layout when mapped
+    bool mapped;
   };
   struct RunKey {
     const OpList* ops;
@@ -150,7 +153,8 @@ class Executor {
   std::string letters(int id, const std::string& idx) const;
   void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
             int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
-            int64_t capC, bool ladder);
+            int64_t capC, bool ladder, const OutMap* om = nullptr);
+  bool output_map(const std::string& Mc, const std::string& Nc, const std::string& cl, OutMap& om) const;
 
   const PoolPlan& plan_for(const OpList& ops, int nb, const std::vector<int>& keep);
   std::map<std::pair<const OpList*, int>, PoolPlan> plans_;

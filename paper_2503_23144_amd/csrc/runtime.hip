@@ -279,17 +279,20 @@ void Executor<T>::permute_into(const void* src, int64_t src_cap, const std::stri
 template <typename T>
 void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
                        int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C,
-                       int64_t ldc, int64_t capC, bool ladder) {
+                       int64_t ldc, int64_t capC, bool ladder, const OutMap* om) {
   if (M > 0 && N > 0 && K > 0) {
     int64_t spanA = ta ? (K - 1) * lda + M : (M - 1) * lda + K;
     int64_t spanB = tb ? (N - 1) * ldb + K : (K - 1) * ldb + N;
-    LRCC_REQUIRE(spanA <= capA && spanB <= capB && (M - 1) * ldc + N <= capC && lda >= (ta ? M : K) &&
-                     ldb >= (tb ? K : N) && ldc >= N,
+    // the last element the output map reaches (maps are monotone in each digit)
+    int64_t lastC = om ? om->row(M - 1) + om->col(N - 1) : (M - 1) * ldc + N - 1;
+    LRCC_REQUIRE(spanA <= capA && spanB <= capB && lastC < capC && lda >= (ta ? M : K) && ldb >= (tb ? K : N) &&
+                     (om || ldc >= N),
                  LRCC_E_INTERNAL, "gemm operands exceed their buffers");
   }
   const size_t wsb = gemm_workspace_bytes<T>(M, N, K);
   void* ws = wsb ? scratch(4, wsb) : nullptr;
-  const GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder, ws, wsb};
+  GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder, ws, wsb, OutMap(), om != nullptr};
+  if (om) g.om = *om;
   if (capturing_) {
     if (timing_ && ladder) {  // leave the graph: the ladder is timed between segments
       end_segment();
@@ -297,7 +300,7 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
       launch_timed(g);
       HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     } else {
-      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0, ws, wsb);
+      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0, ws, wsb, om);
     }
     return;
   }
@@ -312,13 +315,49 @@ void Executor<T>::launch_timed(const GemmArgs& g) {
     HIP_CHECK(hipEventRecord(e0, st_));
   }
   launch_gemm<T>(g.ta, g.tb, g.M, g.N, g.K, g.are, g.aim, g.A, g.lda, g.B, g.ldb, g.bre, 0.0, g.C, g.ldc, st_,
-                 g.ladder ? 1 : 0, g.ws, g.wsb);
+                 g.ladder ? 1 : 0, g.ws, g.wsb, g.mapped ? &g.om : nullptr);
   if (timing_) {
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));
     double fl = (sizeof(T) == 8 ? 8.0 : 6.0) * (double)g.M * (double)g.N * (double)g.K;
     pending_.push_back({e0, e1, g.ladder ? (sizeof(T) == 4 ? 0 : 1) : -1, fl});
   }
+}
+
+// Digits of the product's M and N index strings in the layout of the output
+// string cl (row-major): each letter's stride in cl, letters that are also
+// adjacent in cl merged.  False if either side needs more than kMapRank.
+template <typename T>
+bool Executor<T>::output_map(const std::string& Mc, const std::string& Nc, const std::string& cl, OutMap& om) const {
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  std::vector<int64_t> str(cl.size());
+  int64_t s = 1;
+  for (int k = (int)cl.size() - 1; k >= 0; --k) {
+    str[k] = s;
+    s *= dimof(cl[k]);
+  }
+  auto side = [&](const std::string& letters, int& nd, int64_t* dims, int64_t* strides) {
+    nd = 0;
+    for (char l : letters) {
+      const int64_t d = dimof(l), st = str[cl.find(l)];
+      if (nd > 0 && strides[nd - 1] == st * d) {  // continues the previous digit in cl
+        dims[nd - 1] *= d;
+        strides[nd - 1] = st;
+        continue;
+      }
+      if (nd == kMapRank) return false;
+      dims[nd] = d;
+      strides[nd] = st;
+      ++nd;
+    }
+    if (nd == 0) {
+      dims[0] = 1;
+      strides[0] = 0;
+      nd = 1;
+    }
+    return true;
+  };
+  return side(Mc, om.nm, om.mdim, om.mstr) && side(Nc, om.nn, om.ndim, om.nstr);
 }
 
 template <typename T>
@@ -436,8 +475,11 @@ void Executor<T>::contract(const Op& op, int nb) {
     tb = false;
     ldb = Ns;
   }
+  OutMap om;
   if (direct) {
     gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder);
+  } else if (output_map(Mc, Nc, c, om)) {  // the epilogue writes straight into c's index order
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder, &om);
   } else {
     void* t = scratch(2, (size_t)Ms * Ns * sizeof(T) * 2);
     gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, 0.0, t, Ns, scratch_elems(2), ladder);

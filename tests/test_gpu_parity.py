@@ -368,6 +368,50 @@ def test_memory_cache_reuse_and_trim():
     assert free1 > free0
 
 
+# ------------------------------------------------------------------ error paths and statistics
+def test_error_codes_and_solve_statistics():
+    """Calls out of order, invalid inputs, a frequency on a pole and an
+    iteration limit return their LRCC_E_* codes (and the context stays
+    usable); the per-right-hand-side statistics of a solve are consistent."""
+    lrcc = _lrcc()
+    inp = make_inputs(3, 9, 10, seed=8)
+    inp.B = inp.B * 8.0
+
+    def code(fn):
+        with pytest.raises(lrcc.LrccError) as e:
+            fn()
+        return e.value.code
+
+    c = lrcc.Context(tol=1e-10)
+    assert code(lambda: c.solve_ground()) == lrcc.E_STATE          # nothing loaded
+    assert code(lambda: c.load_df(1, 9, inp.B)) == lrcc.E_INVALID  # nocc < 2
+    c.load_df(inp.o, inp.v, inp.B)
+    bad = inp.fock.copy()
+    bad[0, 1] = 0.3  # not Hermitian
+    assert code(lambda: c.load_fock(bad)) == lrcc.E_INVALID
+    assert code(lambda: c.solve_ground()) == lrcc.E_STATE          # no Fock matrix yet
+    c.load_fock(inp.fock)
+    assert code(lambda: c.load_dipoles(np.concatenate([inp.mu, inp.mu[:1]]))) == lrcc.E_INVALID  # 4 components
+    c.load_dipoles(inp.mu)
+    assert code(lambda: c.solve_lambda()) == lrcc.E_STATE          # before T
+    e, st = c.solve_ground()
+    assert st["converged"] == 1 and 1 <= st["iterations"] <= 100 and st["residual"] <= 1e-10
+    assert code(lambda: c.solve_response([0.1])) == lrcc.E_STATE   # before Lambda
+    c.solve_lambda()
+    eps = np.real(np.diag(inp.fock))
+    pole = float(eps[inp.o] - eps[inp.o - 1])                      # smallest singles denominator
+    assert code(lambda: c.solve_response([pole])) == lrcc.E_SINGULAR
+    per = c.solve_response([0.0, 0.1])
+    assert len(per) == 2 * 3 * 2                                   # X then Y for 3 directions x 2 omegas
+    for s in per:
+        assert s["converged"] == 1 and s["residual"] <= 1e-10
+        assert s["iterations"] >= 1 and s["sigma_evals"] >= s["iterations"]
+    c.close()
+    c = _ctx(inp, maxit=1)
+    assert code(lambda: c.solve_ground()) == lrcc.E_NOCONV
+    c.close()
+
+
 # ------------------------------------------------------------------ caller-owned workspace
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_workspace_pipeline_matches_default_allocation(precision):
