@@ -352,7 +352,10 @@ std::string serialize(const Module& m, const OpList& prog) {
 // Fock matrix appears in F_ae and F_mi, so Omega includes its diagonal part).
 // The vvvv term is written on packed pairs (the ladder) and the vovv/tau
 // contraction Z is factored out of W_abef; the quarter of tau<mn||ef>tau
-// that belongs to W_abef is folded into W_mnij (coefficient 1/2).
+// that belongs to W_abef is folded into W_mnij (coefficient 1/2).  W_mbej is
+// stored in ring order [j b m e] and its doubles term written with (e,f)
+// swapped in both factors, so both ring contractions of a Jacobian product
+// read the doubles in the same permuted order [i a m e].
 const char* kCcsdProgram = R"(
 input  t1[ia] t2p[IA]
 fock   foo[ij] fov[ia] fvo[ai] fvv[ab]
@@ -386,11 +389,11 @@ Wmnij[mnij] += -1 * Xmnij[mnji]
 Wmnij[mnij] += 0.5 * tau[ijef] * goovv[mnef]
 
 Xmnej[mnej]  = t1[jf] * goovv[mnef]
-Wmbej[mbej]  = govvo[mbej]
-Wmbej[mbej] += t1[jf] * govvv[mbef]
-Wmbej[mbej] += t1[nb] * gooov[mnje]
-Wmbej[mbej] += -0.5 * t2[jnfb] * goovv[mnef]
-Wmbej[mbej] += -1 * t1[nb] * Xmnej[mnej]
+Wmbej[jbme]  = govvo[mbej]
+Wmbej[jbme] += t1[jf] * govvv[mbef]
+Wmbej[jbme] += t1[nb] * gooov[mnje]
+Wmbej[jbme] += -0.5 * t2[jnbf] * goovv[mnfe]
+Wmbej[jbme] += -1 * t1[nb] * Xmnej[mnej]
 
 O1[ia]  = fvo[ai]
 O1[ia] += t1[ie] * Fae[ae]
@@ -410,7 +413,7 @@ Pab[ijab]    = t2[ijae] * Ft[be]
 Pab[ijab]   += -1 * t1[ma] * govoo[mbij]
 Pij[ijab]    = -1 * t2[imab] * Fmt[mj]
 Pij[ijab]   += t1[ie] * gvvvo[abej]
-Pijab[ijab]  = t2[imae] * Wmbej[mbej]
+Pijab[ijab]  = t2[imae] * Wmbej[jbme]
 Pijab[ijab] += -1 * t1[ma] * Xmbij[mbij]
 S0[ijab]     = gvvoo[abij]
 S0[ijab]    += 0.5 * tau[mnab] * Wmnij[mnij]

@@ -155,6 +155,15 @@ class Executor {
             int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
             int64_t capC, bool ladder, const OutMap* om = nullptr);
   bool output_map(const std::string& Mc, const std::string& Nc, const std::string& cl, OutMap& om) const;
+  int cached_permute(int id, const std::string& src, const std::string& dst, const void* p, int64_t cap);
+  static constexpr int kPermSlot = 5;
+  struct PermEntry {
+    int tensor = -1;
+    std::vector<int> perm;
+    int64_t nb = 0;
+  };
+  PermEntry pcache_[2];
+  int pnext_ = 0;
 
   const PoolPlan& plan_for(const OpList& ops, int nb, const std::vector<int>& keep);
   std::map<std::pair<const OpList*, int>, PoolPlan> plans_;

@@ -39,8 +39,8 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   cap_.assign(n, 0);
   bound_.assign(n, 0);
   pooled_.assign(n, 0);
-  scr_.assign(5, nullptr);  // 0-2 permutations, 3 uploads, 4 split-K partials
-  scr_cap_.assign(5, 0);
+  scr_.assign(7, nullptr);  // 0-2 permutations, 3 unused, 4 split-K partials, 5-6 cached permutations
+  scr_cap_.assign(7, 0);
   dot_out_ = dev_alloc(64);
   dot_work_ = dev_alloc(1024 * 16);
 }
@@ -360,6 +360,27 @@ bool Executor<T>::output_map(const std::string& Mc, const std::string& Nc, const
   return side(Mc, om.nm, om.mdim, om.mstr) && side(Nc, om.nn, om.ndim, om.nstr);
 }
 
+// Permuted copies of batched operands live in two scratch slots for the
+// rest of a run, keyed by (tensor, permutation of its index positions).  A
+// tensor is final once it is first read in a program, so a copy made from it
+// stays valid until the run ends; graph replays repeat the permutation that
+// was recorded for the first use.
+template <typename T>
+int Executor<T>::cached_permute(int id, const std::string& src, const std::string& dst, const void* p, int64_t cap) {
+  std::vector<int> perm;
+  for (char ch : dst) perm.push_back((int)src.find(ch));
+  for (int s = 0; s < 2; ++s)
+    if (pcache_[s].tensor == id && pcache_[s].perm == perm && pcache_[s].nb == g_nb) return kPermSlot + s;
+  const int s = pnext_;
+  pnext_ ^= 1;
+  int64_t n = 1;
+  for (char ch : src) n *= ch == '#' ? g_nb : dim(ch);
+  void* t = scratch(kPermSlot + s, (size_t)n * sizeof(T) * 2);
+  permute_into(p, cap, src, t, scratch_elems(kPermSlot + s), dst, 1, 0, 0, 0);
+  pcache_[s] = PermEntry{id, perm, g_nb};
+  return kPermSlot + s;
+}
+
 template <typename T>
 void Executor<T>::contract(const Op& op, int nb) {
   (void)nb;
@@ -374,7 +395,9 @@ void Executor<T>::contract(const Op& op, int nb) {
     return p;
   };
   bool ladder = (op.a == ladder_const || op.b == ladder_const);
+  int ida = op.a;
   if (m_[op.b].batched && !m_[op.a].batched) {
+    ida = op.b;
     std::swap(a, b);
     std::swap(pa, pb);
     std::swap(ca, cb);
@@ -454,10 +477,17 @@ void Executor<T>::contract(const Op& op, int nb) {
     ta = true;
     lda = Ms;
   } else {
-    void* t = scratch(0, size(a) * sizeof(T) * 2);
-    permute_into(pa, ca, a, t, scratch_elems(0), Mc + Kx, 1, 0, 0, 0);
-    A = t;
-    capA = scratch_elems(0);
+    const std::string tgt = Mc + Kx;
+    if (m_[ida].batched) {  // batched operands: reuse a copy already permuted this run
+      const int slot = cached_permute(ida, a, tgt, pa, ca);
+      A = scr_[slot];
+      capA = scratch_elems(slot);
+    } else {
+      void* t = scratch(0, size(a) * sizeof(T) * 2);
+      permute_into(pa, ca, a, t, scratch_elems(0), tgt, 1, 0, 0, 0);
+      A = t;
+      capA = scratch_elems(0);
+    }
     ta = false;
     lda = Ks;
   }
@@ -721,6 +751,7 @@ void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& kee
 
 template <typename T>
 void Executor<T>::run_ops(const OpList& ops, int nb) {
+  pcache_[0] = pcache_[1] = PermEntry();
   for (const Op& op : ops) {
     switch (op.kind) {
       case OpKind::Contract: contract(op, nb); break;
