@@ -222,8 +222,10 @@ def cpu_baseline(inp, budget_s=25.0):
     n = P.lay.n
     t = torch.as_tensor(0.01 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))
     X = torch.as_tensor(rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    print("[bench] cpu baseline: oracle integral build (not timed)", file=sys.stderr, flush=True)
     P.g("vvvv")  # integral build is not timed
     right_sigma(P, t, X)  # warm
+    print("[bench] cpu baseline: timing oracle right sigmas", file=sys.stderr, flush=True)
     k, t0 = 0, time.perf_counter()
     while True:
         right_sigma(P, t, X)
