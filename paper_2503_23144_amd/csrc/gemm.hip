@@ -10,19 +10,21 @@
 //       (Br+Bi) are formed in registers from the staged planes.
 //
 // Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, 2 x 2) owns a
-// BM x BN tile of C (128 x 128 FP32 / 128 x 64 FP64 for large problems,
-// 64 x 64 otherwise); each wavefront owns (BM/2) x (BN/2) made of 16 x 16
-// MFMA blocks.  K advances in 16-deep slabs staged in LDS as two real
-// planes (re, im; the Gauss sums are formed in registers) whose layout
-// follows the operand's global layout, with padding that keeps the MFMA
-// operand reads (lane l takes row l%16 at k = l/16) free of bank conflicts.
+// BM x BN tile of C (64 x 64, 128 x 64, or 128 x 128 for FP32, chosen per
+// shape by the autotuner); each wavefront owns (BM/2) x (BN/2) made of
+// 16 x 16 MFMA blocks.  K advances in 16-deep slabs (32 for the FP32
+// 128 x 128 tile) staged in LDS as two real planes (re, im; the Gauss sums
+// are formed in registers) whose layout follows the operand's global
+// layout, padded so that the MFMA operand reads are free of bank conflicts.
 // Global loads are lane-contiguous along the operand's contiguous dimension
-// and unconditional (clamped addresses; the K tail is zeroed in LDS).  The next slab is
-// fetched into registers while the current one is consumed; where LDS allows
-// two workgroups per CU it is double-buffered (one barrier per slab).  MFMA
-// operand fragments are read from LDS one 4-deep step ahead.  Blocks are remapped so that
-// consecutive workgroups on one XCD walk the M tiles of the same N column
-// (reuse of the B slab in that XCD's L2).
+// and unconditional (clamped addresses; the K tail is zeroed in LDS).  The
+// next slab is fetched into registers while the current one is consumed;
+// where LDS allows, it is double-buffered (one barrier per slab).  MFMA
+// operand fragments are read from LDS one 4-deep step ahead.  Each XCD
+// walks a contiguous run of tiles in groups of 8 tile rows, so both operand
+// panels are shared in its L2.  The epilogue stores through an output map,
+// so a product can land directly in a tensor of any index order; deep
+// products with few tiles are split over K.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -66,8 +68,15 @@ __device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mf
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 constexpr int NT = 256;
-constexpr int PADK = 4;   // row layout [row][k]: row stride BK + PADK words (reads conflict-free)
-constexpr int PADR = 16;  // k-major layout [k][row]: row stride BM + PADR (lane groups on distinct banks)
+// LDS padding (32 banks of 4 bytes).  MFMA operand reads take row l%16 at
+// k = l/16 for lane l.  Row layout [row][k]: an FP32 read serves 32 lanes
+// (16 rows x 2 k) at once, so the row stride must be twice an odd number;
+// an FP64 read serves 16 lanes (16 rows, 2 banks each), so it must be odd.
+// k-major layout [k][row]: the row stride is 16 mod 32, putting the two
+// lane groups of a 32-lane FP32 read on disjoint halves of the banks.
+template <typename T>
+constexpr int padk() { return sizeof(T) == 4 ? 2 : 1; }
+constexpr int PADR = 16;
 
 // Map a linear workgroup id to (tile_m, tile_n).  Hardware dispatches
 // consecutive ids round-robin over the 8 XCDs; regroup so that each XCD sees
@@ -106,10 +115,10 @@ struct Stage {
 // the operand's global layout, so lane-consecutive staging writes hit
 // consecutive banks:
 //   KMAJ (global contiguous along rows):  [k][row + PADR]
-//   row layout (global contiguous along k): [row][k + PADK]
+//   row layout (global contiguous along k): [row][k + padk]
 template <typename T, int ROWS, bool KMAJ, int BK>
 struct Tile {
-  static constexpr int LD = KMAJ ? ROWS + PADR : BK + PADK;
+  static constexpr int LD = KMAJ ? ROWS + PADR : BK + padk<T>();
   static constexpr int SIZE = KMAJ ? BK * LD : ROWS * LD;
   static __device__ inline int at(int row, int k) { return KMAJ ? k * LD + row : row * LD + k; }
 };
