@@ -167,6 +167,15 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
               const double alpha[2], const void *A, int64_t lda, const void *B, int64_t ldb,
               const double beta[2], void *C, int64_t ldc, void *stream);
 
+/* Workgroup tile of every later unsplit GEMM launch, process-wide:
+   -1 = automatic (the autotuner when a context enables it, else a size
+   heuristic); 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 with 4 wavefronts
+   (FP32 only; FP64 runs tile 1), 3 = 128 x 128 with 8 wavefronts.  Every
+   tile computes the same product (results agree to rounding); the choice
+   only changes speed.  Returns LRCC_E_INVALID outside -1..3.  The
+   environment variable LRCC_GEMM_TILE gives the initial value. */
+int lrcc_gemm_set_tile(int tile);
+
 /* Text of the derived operation lists (host-only, no GPU needed):
    which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L
    along (X, mu), 5 dE/dt, 6 grad L, 7 F X (tangent of grad L along X),

@@ -345,6 +345,15 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
   }
 }
 
+int lrcc_gemm_set_tile(int tile) {
+  if (tile < -1 || tile > 3) {
+    g_create_error = "tile must be -1..3";
+    return LRCC_E_INVALID;
+  }
+  lrcc::set_gemm_tile(tile);
+  return LRCC_OK;
+}
+
 int64_t lrcc_program_text(int which, char* buf, int64_t cap) {
   try {
     static lrcc::CcPrograms P = [] {

@@ -27,6 +27,7 @@
 // products with few tiles are split over K.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -67,7 +68,6 @@ struct cpx<float> {
 __device__ inline d4 mfma(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4 mfma(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int NT = 256;
 // LDS padding (32 banks of 4 bytes).  MFMA operand reads take row l%16 at
 // k = l/16 for lane l.  Row layout [row][k]: an FP32 read serves 32 lanes
 // (16 rows x 2 k) at once, so the row stride must be twice an odd number;
@@ -102,8 +102,8 @@ __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& t
 
 // Register staging of one operand tile: IN elements along the dimension
 // that is contiguous in global memory, PER elements per thread, STEP rows of
-// the other dimension per pass of the 256 threads.
-template <int ROWS, bool KMAJ, int BK>
+// the other dimension per pass of the NT threads.
+template <int ROWS, bool KMAJ, int BK, int NT>
 struct Stage {
   static constexpr int IN = KMAJ ? ROWS : BK;
   static constexpr int PER = ROWS * BK / NT;
@@ -126,17 +126,18 @@ struct Tile {
 // KIND only separates kernel symbols (0: general contraction, 1: the packed
 // vvvv ladder, +2: autotuner probes of either), so that profiles attribute
 // time to the ladder and never mix probes into it.  The workgroup
-// (4 wavefronts, WGM x (4/WGM)) owns a BM x BN tile of C.
+// (NW wavefronts, WGM x (NW/WGM)) owns a BM x BN tile of C.
 //
 // Split-K: blockIdx.y selects the depth range [y * kchunk, (y + 1) * kchunk)
 // and the output C + y * cstride (partial products, reduced afterwards).
-template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM, int BK>
-__global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
+template <typename T, bool TA, bool TB, int KIND, int BM, int BN, int WGM, int BK, int NW>
+__global__ void __launch_bounds__(64 * NW) zgemm_kernel(int64_t M, int64_t N, int64_t K, T are, T aim,
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
                                                   T bim, typename cpx<T>::type* __restrict__ C, OutMap om,
                                                   int64_t kchunk, int64_t cstride) {
   using V2 = typename cpx<T>::type;
+  constexpr int NT = 64 * NW;
   {
     const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
     K = (K < kbeg + kchunk ? K : kbeg + kchunk) - kbeg;
@@ -147,7 +148,7 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   using ACC = typename cpx<T>::acc;
   constexpr bool G3 = cpx<T>::gauss;
   constexpr int NA = G3 ? 3 : 2;  // accumulators per block
-  constexpr int WGN = 4 / WGM;
+  constexpr int WGN = NW / WGM;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TI = WM / 16, TJ = WN / 16;
   using TA_ = Tile<T, BM, TA, BK>;   // A stored [k][m] when transposed
@@ -155,8 +156,9 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   // two real planes (re, im) per stage; the Gauss sums are formed in
   // registers.  Double-buffer when two stages still leave room for two
   // workgroups per CU (160 KB LDS), else stage once with two barriers.
+  // Tiles that are register-bound to one workgroup per CU may use all of LDS.
   constexpr int STAGE_BYTES = 2 * (TA_::SIZE + TB_::SIZE) * (int)sizeof(T);
-  constexpr bool ONE_PER_CU = sizeof(T) == 4 && BM * BN >= 128 * 128;  // register-bound to 1 wave per SIMD
+  constexpr bool ONE_PER_CU = NW == 8 || (sizeof(T) == 4 && BM * BN >= 128 * 128);
   constexpr int ST = (2 * STAGE_BYTES <= 81920 || (ONE_PER_CU && 2 * STAGE_BYTES <= 160 * 1024)) ? 2 : 1;
   __shared__ T As[ST][2][TA_::SIZE];
   __shared__ T Bs[ST][2][TB_::SIZE];
@@ -177,8 +179,8 @@ __global__ void __launch_bounds__(NT) zgemm_kernel(int64_t M, int64_t N, int64_t
   // columns of B beyond N only feed outputs that are never stored, and in the
   // last, partial K slab the A tile's k >= K entries are zeroed in LDS, which
   // cancels whatever B holds there.
-  using LA = Stage<BM, TA, BK>;
-  using LB = Stage<BN, !TB, BK>;
+  using LA = Stage<BM, TA, BK, NT>;
+  using LB = Stage<BN, !TB, BK, NT>;
   const int a_in = tid % LA::IN, a_out = tid / LA::IN;
   const int b_in = tid % LB::IN, b_out = tid / LB::IN;
   V2 ra[LA::PER], rb[LB::PER];
@@ -374,14 +376,15 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typ
   }
 }
 
-template <typename T, int KIND, int BM, int BN, int WGM>
+template <typename T, int KIND, int BM, int BN, int WGM, int NW = 4>
 static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A, int64_t lda,
                const void* B, int64_t ldb, double bre, double bim, void* C, const OutMap& om, hipStream_t st,
                int splits = 1, void* ws = nullptr) {
   using V2 = typename cpx<T>::type;
-  // deeper slabs for the FP32 128 x 128 tile (one workgroup per CU: fewer
+  // deeper slabs for the FP32 128 x 128 tiles (one workgroup per CU: fewer
   // barriers and a longer prefetch distance)
   constexpr int BK = (sizeof(T) == 4 && BM == 128 && BN == 128) ? 32 : 16;
+  constexpr int NT = 64 * NW;
   int64_t nb = ((m + BM - 1) / BM) * ((n + BN - 1) / BN);
   LRCC_REQUIRE(nb < (int64_t(1) << 31), LRCC_E_INVALID, "gemm grid too large");
   // split-K: equal depth ranges, multiples of the slab depth, none empty
@@ -396,7 +399,7 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
     ar = 1, ai = 0, br = 0, bi = 0;
   }
 #define GO_(TA_, TB_)                                                                                        \
-  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM, BK>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
+  hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM, BK, NW>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
                      0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, mo,  \
                      kchunk, cstride)
   if (!ta && !tb)
@@ -419,7 +422,9 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 }
 
 // ---------------------------------------------------------------- tile choice
-// Candidate workgroup tiles: 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 (FP32).
+// Candidate workgroup tiles: 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 (FP32),
+// all with 4 wavefronts of (BM/2) x (BN/2); 3 = 128 x 128 with 8 wavefronts
+// of 64 x 32 (two wavefronts per SIMD where tile 2 has one).
 // The autotuner times every candidate once per GEMM shape (into a scratch
 // output, so accumulating calls are not disturbed) and keeps the fastest;
 // without it a size heuristic decides.  Results can persist in a text cache
@@ -429,9 +434,10 @@ template <typename T, int KIND>
 static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
                      const void* A, int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C,
                      const OutMap& om, hipStream_t st) {
-  if constexpr (sizeof(T) == 4) {  // the FP64 128 x 128 tile does not fit the register file
+  if constexpr (sizeof(T) == 4) {  // 4 wavefronts of 64 x 64 FP64 would not fit the register file
     if (cfgid == 2) return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
   }
+  if (cfgid == 3) return go<T, KIND, 128, 128, 2, 8>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
   if (cfgid >= 1)
     go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
   else
@@ -490,9 +496,11 @@ int gemm_tuned_shapes() {
 
 template <typename T>
 static int heuristic_tile(int64_t m, int64_t n) {
-  // the large tile only when it still gives every CU several workgroups
+  // Measured on MI355X: in FP32 the 64 x 64 tile (four workgroups per CU) is
+  // the fastest on every large shape; in FP64 the 8-wavefront 128 x 128 tile
+  // is, once it still gives every CU several workgroups.
   const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
-  if (sizeof(T) == 4 && big_tiles >= 2048) return 2;
+  if (sizeof(T) == 8 && big_tiles >= 2048) return 3;
   return 0;
 }
 
@@ -504,6 +512,23 @@ static bool trace_on() {
   }();
   return on;
 }
+
+// A forced workgroup tile (0..3, -1 = automatic) for every unsplit launch,
+// so that each tile can be tested and measured on its own; tile 2 runs as
+// tile 1 in FP64.  The initial value comes from LRCC_GEMM_TILE.
+static std::atomic<int> g_forced_tile{-2};
+static int forced_tile() {
+  int t = g_forced_tile.load(std::memory_order_relaxed);
+  if (t == -2) {
+    const char* e = std::getenv("LRCC_GEMM_TILE");
+    t = (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0) ? e[0] - '0' : -1;
+    int expect = -2;
+    if (!g_forced_tile.compare_exchange_strong(expect, t)) t = expect;
+  }
+  return t;
+}
+
+void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 3 ? tile : -1); }
 
 // Split-K for deep products with few output tiles: a 64 x 64 tile grid of
 // fewer than 256 workgroups leaves most CUs idle while each workgroup walks
@@ -570,19 +595,22 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
       if (it != g_tune.end())
         cfg = it->second;
       else
-        tune = !capturing;
+        tune = !capturing && forced_tile() < 0;
     }
   }
   const bool small = (double)m * n * k < 1e8;  // not worth timing
   if (tune && !small) {
-    const int ncand = sizeof(T) == 4 ? 3 : 2;
+    static const int cand32[] = {0, 1, 2, 3}, cand64[] = {0, 1, 3};
+    const int* cand = sizeof(T) == 4 ? cand32 : cand64;
+    const int ncand = sizeof(T) == 4 ? 4 : 3;
     void* scratch = nullptr;
     scratch = dev_alloc((size_t)m * n * 2 * sizeof(T));
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
     float best = 1e30f;
-    for (int c = 0; c < ncand; ++c) {
+    for (int ci = 0; ci < ncand; ++ci) {
+      const int c = cand[ci];
       float ms = 0;
       for (int rep = 0; rep < 2; ++rep) {
         HIP_CHECK(hipEventRecord(e0, st));
@@ -605,6 +633,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     g_tune[key] = cfg;
     if (!small) save_entry(key, cfg);
   }
+  if (forced_tile() >= 0) cfg = forced_tile();
   if (trace_on())
     fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=%d splits=1\n",
             sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k, cfg);

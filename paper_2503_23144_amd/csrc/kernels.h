@@ -112,6 +112,7 @@ size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k);
 
 // Per-shape tile autotuning of launch_gemm (process-wide).
 void set_gemm_autotune(bool on);
+void set_gemm_tile(int tile);  // -1: automatic (autotuner or size heuristic)
 int gemm_tuned_shapes();
 
 // Solver kernels (FP64 vectors, nvec right-hand sides of length n).

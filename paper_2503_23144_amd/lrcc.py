@@ -73,6 +73,7 @@ _sig = {
     "lrcc_get_amplitudes": (_i, [_vp, _i, _i, _vp, _i]),
     "lrcc_set_amplitudes": (_i, [_vp, _i, _i, _vp, _i]),
     "lrcc_gemm": (_i, [_i, _i, _i, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp]),
+    "lrcc_gemm_set_tile": (_i, [_i]),
     "lrcc_program_text": (_i64, [_i, ctypes.c_char_p, _i64]),
     "lrcc_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "lrcc_set_timing": (_i, [_vp, _i]),
@@ -157,6 +158,14 @@ def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
     if rc != OK:
         raise LrccError(rc, lib.lrcc_last_error(None).decode())
     return C
+
+
+def gemm_set_tile(tile):
+    """Force the GEMM workgroup tile (0..3) of later launches; -1 restores
+    the automatic choice."""
+    rc = lib.lrcc_gemm_set_tile(int(tile))
+    if rc != OK:
+        raise LrccError(rc, lib.lrcc_last_error(None).decode())
 
 
 class Context:

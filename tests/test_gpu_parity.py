@@ -76,13 +76,15 @@ def test_gemm_split_depth_matches_host_matmul(dtype, ta, tb, m, n, k):
     assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k)
 
 
+@pytest.mark.parametrize("tile", [-1, 2, 3])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_gemm_ragged_depth_repeated(dtype, ta, tb):
-    """Depths that end in a partial 16-deep slab, each launched repeatedly
-    (the partial slab's zero fill is ordered against the staging writes of
-    other wavefronts; a missing barrier shows up as run-to-run differences)."""
+def test_gemm_ragged_depth_repeated(forced_tile, tile, dtype, ta, tb):
+    """Depths that end in a partial slab, each launched repeatedly (the
+    partial slab's zero fill is ordered against the staging writes of other
+    wavefronts; a missing barrier shows up as run-to-run differences)."""
     lrcc = _lrcc()
+    forced_tile(tile)
     dev = torch.device("cuda:0")
     for m, n, k in [(70, 90, 1), (37, 53, 29), (130, 129, 17), (300, 260, 45), (64, 64, 15)]:
         rng = np.random.default_rng(m + n + k)
@@ -98,6 +100,50 @@ def test_gemm_ragged_depth_repeated(dtype, ta, tb):
             lrcc.gemm(Ad, Bd, Cd, transa=bool(ta), transb=bool(tb))
             torch.cuda.synchronize()
             assert np.abs(Cd.cpu().numpy().astype(np.complex128) - ref).max() <= tol, (m, n, k)
+
+
+@pytest.fixture
+def forced_tile():
+    """Sets a forced GEMM tile for one test and restores the automatic choice."""
+    lrcc = _lrcc()
+    yield lrcc.gemm_set_tile
+    lrcc.gemm_set_tile(-1)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_gemm_each_tile(forced_tile, tile, dtype, ta, tb):
+    """Every workgroup tile (including those the autotuner picks only for
+    large shapes) on ragged shapes: partial tiles in M and N, a partial last
+    slab in K (16- and 32-deep slabs), and beta accumulation."""
+    lrcc = _lrcc()
+    forced_tile(tile)
+    dev = torch.device("cuda:0")
+    for m, n, k in [(37, 53, 29), (200, 130, 257), (260, 300, 45), (129, 385, 70), (1, 5, 7)]:
+        rng = np.random.default_rng(1000 * tile + m + n + k)
+        A = _rand(rng, *((k, m) if ta else (m, k)))
+        B = _rand(rng, *((n, k) if tb else (k, n)))
+        C0 = _rand(rng, m, n)
+        al, be = -0.4 + 0.8j, 0.5 - 0.25j
+        ref = al * ((A.T if ta else A) @ (B.T if tb else B)) + be * C0
+        Cd = torch.tensor(C0, dtype=dtype, device=dev)
+        for _ in range(2):  # the second launch checks that nothing depends on leftover LDS contents
+            Cd.copy_(torch.tensor(C0, dtype=dtype))
+            lrcc.gemm(torch.tensor(A, dtype=dtype, device=dev), torch.tensor(B, dtype=dtype, device=dev), Cd,
+                      transa=bool(ta), transb=bool(tb), alpha=al, beta=be)
+            torch.cuda.synchronize()
+            got = Cd.cpu().numpy().astype(np.complex128)
+            scale = np.sqrt(k) * np.abs(A).max() * np.abs(B).max() + np.abs(C0).max()
+            eps = 1e-15 if dtype == torch.complex128 else 2e-7
+            assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k), (m, n, k)
+
+
+def test_gemm_tile_choice_rejects_bad_values():
+    lrcc = _lrcc()
+    with pytest.raises(lrcc.LrccError):
+        lrcc.gemm_set_tile(4)
+    lrcc.gemm_set_tile(-1)
 
 
 # ------------------------------------------------------------------ helpers
