@@ -65,9 +65,10 @@ def resident(inp):
     return {k: torch.as_tensor(getattr(inp, k)).to(dev) for k in ("B", "fock", "mu")}
 
 
-def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None):
+def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None, quadratic=False):
     """One pass of the hot path; returns counts, alpha and phase times.
-    dev_in: the inputs already on the device (resident(inp))."""
+    dev_in: the inputs already on the device (resident(inp)).  quadratic:
+    alpha by the Eq. 36 route (X(w) and X(-w)) instead of Eq. 35 (X and Y)."""
     ph = {}
     src = dev_in if dev_in is not None else {"B": inp.B, "fock": inp.fock, "mu": inp.mu}
     t = time.perf_counter()
@@ -84,7 +85,7 @@ def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None):
     st1 = c.solve_lambda()
     ph["lambda"] = time.perf_counter() - t
     t = time.perf_counter()
-    per = c.solve_response(inp.omegas)
+    per = c.solve_response(inp.omegas, quadratic=quadratic)
     ph["response"] = time.perf_counter() - t
     resp_sig = sum(s["sigma_evals"] for s in per)
     sig = st0["sigma_evals"] + st1["sigma_evals"] + resp_sig
@@ -249,6 +250,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-ladder-scale", action="store_true", help="skip the o=40, v=400 ladder measurement")
     ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
+    ap.add_argument("--no-eq36", action="store_true", help="skip the Eq. 36 (X(w), X(-w)) pass")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
@@ -349,6 +351,20 @@ def main():
             out[f"mixed_over_{name}_sigma_rate"] = value / out[name]["sigma_evals_per_s"]
             if out[name]["sample"] == "full pass":
                 out[f"mixed_over_{name}_time"] = out[name]["seconds"] / (dt / args.steps)
+    if not args.no_eq36:
+        # the same mixed pass with alpha by the Eq. 36 route: right solves at
+        # +w and -w and one F X product per right-hand side instead of the
+        # left (Y) solves; alpha must agree with the Eq. 35 pass
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r36 = run_pass(lrcc, inp, "mixed", args.tol, dev_in=dev_in, quadratic=True)
+        torch.cuda.synchronize()
+        d36 = time.perf_counter() - t1
+        out["eq36_route"] = {"sigma_evals_per_s": r36["sigma_evals"] / d36, "seconds": d36,
+                             "phases_s": r36["phases"],
+                             "alpha_rel_diff_vs_eq35": float(np.abs(r36["alpha"] - last["alpha"]).max()
+                                                             / np.abs(last["alpha"]).max())}
+        print(f"[bench] eq36 route: {d36:.1f} s", file=sys.stderr, flush=True)
     if not args.no_ladder_scale:
         out["ladder_o40_v400"] = ladder_at_scale(lrcc)
     if not args.no_sigma_table:

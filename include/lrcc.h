@@ -66,6 +66,7 @@ extern "C" {
 #define LRCC_AMP_LAMBDA 1
 #define LRCC_AMP_X 2
 #define LRCC_AMP_Y 3
+#define LRCC_AMP_XMINUS 4  /* X(-w), after lrcc_solve_response_quadratic */
 
 typedef struct lrcc_ctx lrcc_ctx;
 
@@ -135,6 +136,19 @@ int lrcc_solve_lambda(lrcc_ctx *ctx, lrcc_stats *stats);
    right-hand sides, and forms alpha.  per_rhs (host, may be NULL) receives
    2 * ncomp * nw stats: X solves first (k-major, then B), then Y solves. */
 int lrcc_solve_response(lrcc_ctx *ctx, int nw, const double *omegas, lrcc_stats *per_rhs);
+/* Response by the quadratic route (Eq. 36): for every component B and
+   frequency w solves (A - w) X^B(w) = -xi^B and (A + w) X^B(-w) = -xi^B
+   (right solves only, batched), then forms
+     f_AB(w) = eta^A.X^B(w) + eta^B.X^A(-w) + X^A(-w).F.X^B(w)
+   (F, the second derivative of the Lagrangian, applied as one
+   Hessian-vector product per X^B(w)) and
+   alpha_AB(w) = -1/2 [f_AB(w) + conj f_AB(-w)], read with lrcc_get_alpha.
+   It reaches the same alpha as lrcc_solve_response (the two differ by the
+   solve residuals), so it serves as an independent check.  per_rhs (host,
+   may be NULL) receives 2 * ncomp * nw stats: X(w) solves first, then X(-w).
+   Afterwards lrcc_get_amplitudes serves LRCC_AMP_X and LRCC_AMP_XMINUS
+   (LRCC_AMP_Y returns LRCC_E_STATE). */
+int lrcc_solve_response_quadratic(lrcc_ctx *ctx, int nw, const double *omegas, lrcc_stats *per_rhs);
 /* alpha[nw][ncomp][ncomp] complex (alpha_AB(w) = -1/2 [f_AB + conj f_BA],
    f_AB = Y^B.xi^A + eta^A.X^B, Eq. 35) from the last lrcc_solve_response. */
 int lrcc_get_alpha(lrcc_ctx *ctx, void *alpha, int where);

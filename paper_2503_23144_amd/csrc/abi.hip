@@ -174,7 +174,7 @@ int lrcc_solve_lambda(lrcc_ctx* ctx, lrcc_stats* stats) {
   });
 }
 
-int lrcc_solve_response(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats* per_rhs) {
+static int solve_response_route(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats* per_rhs, bool quadratic) {
   return guard(ctx, [&](Context& c) {
     std::vector<lrcc::SolveStats> per;
     c.kt.clear();
@@ -184,13 +184,21 @@ int lrcc_solve_response(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats*
       c.collect_times();
     };
     try {
-      c.solve_response(nw, omegas, per);
+      c.solve_response(nw, omegas, per, quadratic);
     } catch (...) {
       out();
       throw;
     }
     out();
   });
+}
+
+int lrcc_solve_response(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats* per_rhs) {
+  return solve_response_route(ctx, nw, omegas, per_rhs, false);
+}
+
+int lrcc_solve_response_quadratic(lrcc_ctx* ctx, int nw, const double* omegas, lrcc_stats* per_rhs) {
+  return solve_response_route(ctx, nw, omegas, per_rhs, true);
 }
 
 int lrcc_get_alpha(lrcc_ctx* ctx, void* alpha, int where) {
@@ -276,8 +284,13 @@ int lrcc_get_amplitudes(lrcc_ctx* ctx, int which, int idx, void* out, int where)
       LRCC_REQUIRE(c.have_lam, LRCC_E_STATE, "no Lambda amplitudes");
       src = c.lam.p;
     } else {
-      LRCC_REQUIRE(which == LRCC_AMP_X || which == LRCC_AMP_Y, LRCC_E_INVALID, "bad amplitude kind");
+      LRCC_REQUIRE(which == LRCC_AMP_X || which == LRCC_AMP_Y || which == LRCC_AMP_XMINUS, LRCC_E_INVALID,
+                   "bad amplitude kind");
       LRCC_REQUIRE(c.have_alpha, LRCC_E_STATE, "no response amplitudes");
+      LRCC_REQUIRE(which != LRCC_AMP_Y || c.response_route == 35, LRCC_E_STATE,
+                   "no Y amplitudes (the last response solve took the Eq. 36 route)");
+      LRCC_REQUIRE(which != LRCC_AMP_XMINUS || c.response_route == 36, LRCC_E_STATE,
+                   "no X(-w) amplitudes (the last response solve took the Eq. 35 route)");
       int nr = (int)c.omegas.size() * c.ncomp;
       LRCC_REQUIRE(idx >= 0 && idx < nr, LRCC_E_INVALID, "bad right-hand-side index");
       src = (const char*)(which == LRCC_AMP_X ? c.X.p : c.Y.p) + idx * vb;

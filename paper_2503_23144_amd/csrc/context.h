@@ -102,7 +102,10 @@ struct Context {
   // ---- solves
   void solve_ground(double ecorr_out[2], SolveStats& s);
   void solve_lambda(SolveStats& s);
-  void solve_response(int nw, const double* om, std::vector<SolveStats>& per);
+  void solve_response(int nw, const double* om, std::vector<SolveStats>& per, bool quadratic = false);
+  void alpha_quadratic(int nw, int chunk, DevBuf& dots, DevBuf& work);
+  void eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec);  // eta^B + F X^B
+  int response_route = 0;  // 35: X and Y (Eq. 35); 36: X(w) and X(-w) (Eq. 36, X(-w) in Y)
 
   // ---- Jacobian products on device FP64 vectors [nb][n] (in/out may alias no)
   void residual64(const void* tvec, void* R, cplx* E);

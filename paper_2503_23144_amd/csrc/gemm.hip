@@ -9,13 +9,14 @@
 //       Re = P1 - P2, Im = P3 - P1 - P2.  The pre-added planes (Ar+Ai),
 //       (Br+Bi) are formed in registers from the staged planes.
 //
-// Tiling: a 256-thread workgroup (4 wavefronts of 64 lanes, 2 x 2) owns a
-// BM x BN tile of C (64 x 64, 128 x 64, or 128 x 128 for FP32, chosen per
-// shape by the autotuner); each wavefront owns (BM/2) x (BN/2) made of
-// 16 x 16 MFMA blocks.  K advances in 16-deep slabs (32 for the FP32
-// 128 x 128 tile) staged in LDS as two real planes (re, im; the Gauss sums
-// are formed in registers) whose layout follows the operand's global
-// layout, padded so that the MFMA operand reads are free of bank conflicts.
+// Tiling: a workgroup of 4 wavefronts of 64 lanes (2 x 2) owns a BM x BN
+// tile of C (64 x 64, 128 x 64, or 128 x 128 for FP32), or 8 wavefronts
+// (2 x 4) own a 128 x 128 tile; the autotuner picks per shape.  Each
+// wavefront owns a block of 16 x 16 MFMA outputs.  K advances in 16-deep
+// slabs (32 for the FP32 128 x 128 tiles) staged in LDS as two real planes
+// (re, im; the Gauss sums are formed in registers) whose layout follows the
+// operand's global layout, padded so that the MFMA operand reads are free of
+// bank conflicts.
 // Global loads are lane-contiguous along the operand's contiguous dimension
 // and unconditional (clamped addresses; the K tail is zeroed in LDS).  The
 // next slab is fetched into registers while the current one is consumed;

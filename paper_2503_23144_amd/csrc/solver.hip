@@ -807,7 +807,13 @@ int Context::sigma_chunk(Side side, int nvec, int prec) {
   return fit_chunk(nvec, per, x64.get(), x32.get(), false, true);
 }
 
-void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& per) {
+// Eq. 35 route (quadratic = false): X(w) from (A - w) X = -xi, then Y(w)
+// from Y (A + w) = -(eta + F X(w)); f_AB = Y^B.xi^A + eta^A.X^B.
+// Eq. 36 route (quadratic = true): X(w) and X(-w), no left solves;
+// f_AB(w) = eta^A.X^B(w) + eta^B.X^A(-w) + X^A(-w).F.X^B(w).  Both give
+// alpha_AB = -1/2 [f_AB(w) + conj f_AB(-w)] (f_AB(-w) = f_BA(w) on the
+// Eq. 35 route).  X(-w) is kept in the Y slot.
+void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& per, bool quadratic) {
   require_sizes();
   LRCC_REQUIRE(have_lam, LRCC_E_STATE, "no Lambda amplitudes (call lrcc_solve_lambda first)");
   LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
@@ -833,6 +839,8 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
   hvp(ncomp, comps.data(), nullptr, eta.p);
   X.ensure(nrhs * vb);
   Y.ensure(nrhs * vb);
+  have_alpha = false;
+  response_route = quadratic ? 36 : 35;
   per.assign(2 * nrhs, SolveStats());
   const int chunk = rhs_chunk_for(nrhs, prec);
   if (cfg.verbose >= 1) fprintf(stderr, "[lrcc] response: %d right-hand sides in chunks of %d\n", nrhs, chunk);
@@ -850,25 +858,17 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
         sh[q] = side == 0 ? -omegas[r / ncomp] : omegas[r / ncomp];
       }
       void* xc = (char*)(side == 0 ? X.p : Y.p) + c0 * vb;
-      if (side == 0) {
+      if (side == 0 || quadratic) {
         for (int q = 0; q < nc; ++q)
           HIP_CHECK(hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
-      } else if (prec == 64) {
-        hvp(nc, cp.data(), (char*)X.p + c0 * vb, bc.p);  // eta^B + F X^B
       } else {
-        // F X^B with FP32 products (F does not involve the Fock diagonal),
-        // plus eta^B (FP64)
-        DevBuf f32;
-        f32.ensure(nc * n * 8);
-        fx32(nc, (char*)X.p + c0 * vb, f32.p);
-        for (int q = 0; q < nc; ++q)
-          launch_residual<float>(1, n, (char*)f32.p + (size_t)q * n * 8, nullptr, nullptr, (char*)eta.p + cp[q] * vb, 0,
-                                 (char*)bc.p + q * vb, st);
+        eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, bc.p, prec);
       }
       HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
       launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);
       std::vector<SolveStats> ss;
-      solve_linear(side == 0 ? Side::Right : Side::Left, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
+      const Side sd = (side == 0 || quadratic) ? Side::Right : Side::Left;
+      solve_linear(sd, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
       for (int q = 0; q < nc; ++q) per[side * nrhs + c0 + q] = ss[q];
     }
   }
@@ -877,6 +877,10 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
   d1.ensure(nrhs * 16);
   d2.ensure(nrhs * 16);
   w.ensure((size_t)nrhs * 1024 * 16);
+  if (quadratic) {
+    alpha_quadratic(nw, chunk, d1, w);
+    bc.release();
+  } else {
   std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
   for (int a = 0; a < ncomp; ++a) {
     launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
@@ -901,10 +905,77 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
       for (int bb = 0; bb < ncomp; ++bb)
         alpha[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
   }
+  }
   have_alpha = true;
   bool all = true;
   for (auto& s : per) all = all && s.converged;
   LRCC_REQUIRE(all, LRCC_E_NOCONV, "some response equations did not converge");
+}
+
+// eta^B + F X^B for nb right-hand sides with components comp.  On the mixed
+// path F X takes FP32 products (F does not involve the Fock diagonal) and
+// eta^B is added in FP64.
+void Context::eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec) {
+  if (prec == 64) return hvp(nb, comp, Xs, out);
+  const size_t vb = n * 16;
+  DevBuf f32;
+  f32.ensure(nb * n * 8);
+  fx32(nb, Xs, f32.p);
+  for (int q = 0; q < nb; ++q)
+    launch_residual<float>(1, n, (char*)f32.p + (size_t)q * n * 8, nullptr, nullptr, (char*)eta.p + comp[q] * vb, 0,
+                           (char*)out + q * vb, st);
+}
+
+// alpha on the Eq. 36 route from X(w) (in X) and X(-w) (in Y).  With
+// H^B = eta^B + F X^B(w) and the symmetry of F (a Hessian: u.F v = v.F u),
+//   f_AB(w)  = eta^A.X^B(w) + eta^B.X^A(-w) + X^A(-w).F X^B(w)
+//            = eta^A.X^B(w) + X^A(-w).H^B,
+//   f_AB(-w) = eta^B.X^A(w) + X^B(-w).H^A.
+// H is built in chunks of right-hand sides; the bilinear dots run on the
+// device.
+void Context::alpha_quadratic(int nw, int chunk, DevBuf& dots, DevBuf& work) {
+  const size_t vb = n * 16;
+  const int nrhs = nw * ncomp;
+  const int prec = cfg.precision == LRCC_MIXED ? 32 : 64;
+  auto fetch = [&](size_t cnt) {
+    std::vector<cplx> h(cnt);
+    HIP_CHECK(hipMemcpyAsync(h.data(), dots.p, cnt * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    return h;
+  };
+  // ep[r][a] = eta^a . X_r(w) for every right-hand side r
+  std::vector<cplx> ep(nrhs * ncomp);
+  for (int a = 0; a < ncomp; ++a) {
+    launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, dots.p, work.p, st);
+    auto h = fetch(nrhs);
+    for (int r = 0; r < nrhs; ++r) ep[r * ncomp + a] = h[r];
+  }
+  // q[r][a] = X^a(-w_k) . H_r for r = k * ncomp + b
+  dots.ensure((size_t)nrhs * ncomp * 16);
+  DevBuf H;
+  H.ensure((size_t)std::min(chunk, nrhs) * vb);
+  for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+    const int nc = std::min(chunk, nrhs - c0);
+    std::vector<int> cp(nc);
+    for (int q = 0; q < nc; ++q) cp[q] = (c0 + q) % ncomp;
+    eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, H.p, prec);
+    for (int q = 0; q < nc; ++q) {
+      const int r = c0 + q, k = r / ncomp;
+      for (int a = 0; a < ncomp; ++a)
+        launch_batched_dot<double>(1, n, (char*)Y.p + ((size_t)k * ncomp + a) * vb, n, (char*)H.p + q * vb, n, false,
+                                   (char*)dots.p + ((size_t)r * ncomp + a) * 16, work.p, st);
+    }
+  }
+  const auto qv = fetch((size_t)nrhs * ncomp);
+  alpha.assign(nw * ncomp * ncomp, 0.0);
+  for (int k = 0; k < nw; ++k)
+    for (int a = 0; a < ncomp; ++a)
+      for (int b = 0; b < ncomp; ++b) {
+        const int ra = k * ncomp + a, rb = k * ncomp + b;
+        const cplx fp = ep[rb * ncomp + a] + qv[rb * ncomp + a];  // eta^a.X^b(w) + X^a(-w).H^b
+        const cplx fm = ep[ra * ncomp + b] + qv[ra * ncomp + b];  // eta^b.X^a(w) + X^b(-w).H^a
+        alpha[(k * ncomp + a) * ncomp + b] = -0.5 * (fp + std::conj(fm));
+      }
 }
 
 }  // namespace lrcc

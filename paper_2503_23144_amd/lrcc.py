@@ -21,7 +21,7 @@ OK, E_INVALID, E_STATE, E_NOMEM, E_HIP, E_NOCONV, E_SINGULAR, E_INTERNAL = 0, -1
 HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 SIDE_RESIDUAL, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
-AMP_T, AMP_LAMBDA, AMP_X, AMP_Y = 0, 1, 2, 3
+AMP_T, AMP_LAMBDA, AMP_X, AMP_Y, AMP_XMINUS = 0, 1, 2, 3, 4
 PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL, PROG_FX, PROG_FNSPP = range(9)
 
 # torch ships its own libamdhip64.so.7; load it first so that torch (device
@@ -67,6 +67,7 @@ _sig = {
     "lrcc_solve_ground": (_i, [_vp, _vp, ctypes.POINTER(Stats)]),
     "lrcc_solve_lambda": (_i, [_vp, ctypes.POINTER(Stats)]),
     "lrcc_solve_response": (_i, [_vp, _i, _vp, _vp]),
+    "lrcc_solve_response_quadratic": (_i, [_vp, _i, _vp, _vp]),
     "lrcc_get_alpha": (_i, [_vp, _vp, _i]),
     "lrcc_sigma": (_i, [_vp, _i, _i, _vp, _vp, _vp, _i, _i]),
     "lrcc_amplitude_length": (_i64, [_vp]),
@@ -248,11 +249,13 @@ class Context:
         self._check(lib.lrcc_solve_lambda(self._h, ctypes.byref(s)))
         return s.as_dict()
 
-    def solve_response(self, omegas, allow_noconv=False):
+    def solve_response(self, omegas, allow_noconv=False, quadratic=False):
+        """X and Y solves and alpha by Eq. 35; quadratic=True takes the Eq. 36
+        route (X(w) and X(-w), no Y)."""
         om = np.ascontiguousarray(omegas, dtype=np.float64)
         st = (Stats * (2 * om.size * self.ncomp))()
-        self._check(lib.lrcc_solve_response(self._h, om.size, om.ctypes.data, st),
-                    allow=(E_NOCONV,) if allow_noconv else ())
+        fn = lib.lrcc_solve_response_quadratic if quadratic else lib.lrcc_solve_response
+        self._check(fn(self._h, om.size, om.ctypes.data, st), allow=(E_NOCONV,) if allow_noconv else ())
         return [s.as_dict() for s in st]
 
     def alpha(self, nw):

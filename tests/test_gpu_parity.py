@@ -234,6 +234,54 @@ def test_polarizability_mixed_precision_close_to_fp64():
     assert _relerr(res["mixed"], res["fp64"]) < 1e-6
 
 
+# ------------------------------------------------------------------ Eq. 36 route
+@pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
+def test_quadratic_route_matches_oracle_eq36(name, o, v, naux, scale, seed):
+    """alpha from X(w), X(-w) and the F term (Eq. 36) against the oracle's
+    Eq. 36 evaluation, X(-w) against the oracle's solve, and the GPU's own
+    Eq. 35 alpha (the two routes agree up to the solve residuals)."""
+    from oracle.response import alpha_eq36, lr_ccsd, solve_x, xi
+    lrcc = _lrcc()
+    inp = make_inputs(o, v, naux, seed=seed)
+    inp.B = inp.B * scale
+    omegas = [0.0, 0.11]
+    ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
+    P = _oracle_problem(inp)
+    c = _ctx(inp, tol=1e-11)
+    c.solve_ground()
+    c.solve_lambda()
+    per = c.solve_response(omegas, quadratic=True)
+    assert len(per) == 2 * 3 * len(omegas) and all(s["converged"] for s in per)
+    a36 = c.alpha(len(omegas))
+    for k, w in enumerate(omegas):
+        assert _relerr(a36[k], alpha_eq36(P, ref.t, ref.lam, (0, 1, 2), w)) < 1e-8, w
+    Xm = c.get_amplitudes(lrcc.AMP_XMINUS, 1 * 3 + 1)
+    ref_xm, _ = solve_x(P, ref.t, xi(P, ref.t, 1), -0.11)
+    assert _relerr(Xm, ref_xm.numpy()) < 1e-8
+    assert _relerr(c.get_amplitudes(lrcc.AMP_X, 1 * 3 + 1), ref.X[(1, 1)].numpy()) < 1e-8
+    with pytest.raises(lrcc.LrccError):
+        c.get_amplitudes(lrcc.AMP_Y, 0)
+    c.solve_response(omegas)
+    assert _relerr(a36, c.alpha(len(omegas))) < 1e-9
+    with pytest.raises(lrcc.LrccError):
+        c.get_amplitudes(lrcc.AMP_XMINUS, 0)
+
+
+def test_quadratic_route_mixed_precision_and_stored_c2_alpha():
+    """Eq. 36 at o=10, v=60 against the stored oracle alpha (Eq. 35, FP64
+    oracle), in FP64 and in mixed precision."""
+    import os
+    from paper_2503_23144_amd.synth import config_inputs
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c2.npz"))
+    inp = config_inputs("c2")
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
+        c = _ctx(inp, precision=prec, tol=1e-11 if prec == "fp64" else 1e-10)
+        c.solve_ground()
+        c.solve_lambda()
+        c.solve_response(ref["omegas"], quadratic=True)
+        assert _relerr(c.alpha(len(ref["omegas"])), ref["alpha"]) < tol, prec
+
+
 # ------------------------------------------------------------------ FNS++ (A2)
 def test_fnspp_truncation_matches_oracle():
     from oracle.fnspp import fnspp_transform
