@@ -239,6 +239,26 @@ def lr_ccsd(B, fock, mu, o, omegas, comps=(0, 1, 2), tol=1e-13) -> Result:
                   alpha=alpha, fab=fab, iters=iters)
 
 
+def alpha_eq36_from(etas, Xp, Xm, FXp, FXm=None):
+    """alpha = -<<A;B>>_w by Eq. 36 from eta^A, X^A(w), X^A(-w) and F X^A(w)
+    (and F X^A(-w); when omitted, F is used as symmetric: u.F v = v.F u)."""
+    n = len(etas)
+
+    def f36(Xa_m, Xb_p, FXb_p, a, b):
+        return complex(bdot(etas[a], Xb_p) + bdot(etas[b], Xa_m) + bdot(Xa_m, FXb_p))
+
+    out = np.zeros((n, n), dtype=np.complex128)
+    for a in range(n):
+        for b in range(n):
+            fp = f36(Xm[a], Xp[b], FXp[b], a, b)      # f(w)
+            if FXm is not None:
+                fm = f36(Xp[a], Xm[b], FXm[b], a, b)  # f(-w)
+            else:
+                fm = complex(bdot(etas[a], Xm[b]) + bdot(etas[b], Xp[a]) + bdot(Xm[b], FXp[a]))
+            out[a, b] = -0.5 * (fp + np.conj(fm))
+    return out
+
+
 def alpha_eq36(P: Problem, t, lam, comps, w, tol=1e-13):
     """Eq. 36: <<A;B>>_w = 1/2 C^{+-w} P[A(-w), B(w)] (eta^A X^B(w)
     + 1/2 X^A(-w) F X^B(w)); returns alpha = -<<A;B>>."""
@@ -248,18 +268,7 @@ def alpha_eq36(P: Problem, t, lam, comps, w, tol=1e-13):
     Xm = [solve_x(P, t, x, -w, tol)[0] for x in xis]
     FXp = [F_times(P, t, lam, X) for X in Xp]
     FXm = [F_times(P, t, lam, X) for X in Xm]
-    n = len(comps)
-
-    def f36(Xa_m, Xb_p, FXb_p, a, b):
-        return complex(bdot(etas[a], Xb_p) + bdot(etas[b], Xa_m) + bdot(Xa_m, FXb_p))
-
-    out = np.zeros((n, n), dtype=np.complex128)
-    for a in range(n):
-        for b in range(n):
-            fp = f36(Xm[a], Xp[b], FXp[b], a, b)      # f(w)
-            fm = f36(Xp[a], Xm[b], FXm[b], a, b)      # f(-w)
-            out[a, b] = -0.5 * (fp + np.conj(fm))
-    return out
+    return alpha_eq36_from(etas, Xp, Xm, FXp, FXm)
 
 
 def alpha_uncoupled(fock, mu, o, w):

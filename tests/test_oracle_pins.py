@@ -304,3 +304,69 @@ def test_alpha_iso_convention_matches_printed_tables():
     # the formula as typeset in the text, (perp + 2 par)/3, does not fit
     bad = [abs((float(p) + 2 * float(q)) / 3 - float(i)) > 0.5 for _, p, q, i, _ in rows]
     assert all(bad)
+
+
+# ---------------------------------------------------------------- MP2-level corrections (Eqs. 51-54)
+def test_mp2_level_noninteracting_limit_is_uncoupled_sum_over_states():
+    """Without two-electron integrals t(1) = lambda(1) = 0, Hbar = F and F X = 0,
+    so the MP2-level alpha is the independent-particle sum over states."""
+    from oracle.mp2 import mp2_level
+    o, v = 3, 6
+    inp = make_inputs(o, v, 4, seed=9)
+    E, al = mp2_level(inp.B * 0.0, inp.fock, inp.mu, o, [0.0, 0.17])
+    assert E == 0
+    for k, w in enumerate((0.0, 0.17)):
+        ref = alpha_uncoupled(inp.fock, inp.mu, o, w)
+        assert np.abs(al[k] - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_mp2_level_energy_is_closed_form_mp2():
+    """E(t(1)) = 1/4 sum |<ij||ab>|^2 / (e_i + e_j - e_a - e_b) (Eq. 39), with
+    the integrals formed here directly from the factors."""
+    from oracle.mp2 import mp2_level
+    o, v = 3, 6
+    inp = make_inputs(o, v, 8, seed=12)
+    B = inp.B * 8.0
+    E, _ = mp2_level(B, inp.fock, inp.mu, o, [0.0])
+    Bo, Bv = B[:, :o, o:], B[:, :o, o:]
+    g = np.einsum("xia,xjb->ijab", Bo, Bv) - np.einsum("xib,xja->ijab", Bo, Bv)
+    e = np.real(np.diag(inp.fock))
+    d = e[:o, None, None, None] + e[None, :o, None, None] - e[None, None, o:, None] - e[None, None, None, o:]
+    ref = 0.25 * np.sum(np.abs(g) ** 2 / d)
+    assert abs(E - ref) < 1e-13 * abs(ref)
+
+
+def test_mp2_level_amplitudes_are_eqs_46_to_48():
+    """The reading's X^B(-w) = -xi^B(t(1)) / (Dbar + w) equals minus the
+    first-order amplitudes of Eqs. 46-48 (written there directly on full
+    tensors), and lambda(1) = conj t(1) for Hermitian integrals."""
+    from oracle.mp2 import first_order, hbar_denominators
+    o, v = 3, 5
+    inp = make_inputs(o, v, 8, seed=5)
+    B = inp.B * 8.0
+    t1, l1, P = first_order(B, inp.fock, inp.mu, o)
+    assert (l1 - t1.conj()).abs().max() < 1e-15 * t1.abs().max()
+    t2, Hii, Haa = mp2_and_hbar(B, inp.fock, o)
+    Dbar = hbar_denominators(P, B, inp.fock)
+    w = 0.13
+    for c in range(3):
+        tA1, tA2 = perturbed_amplitudes(t2, Hii, Haa, inp.mu[c], o, w)
+        ref = P.lay.join(tA1, P.lay.pack(tA2))
+        Xm = -xi(P, t1, c) / (Dbar + w)
+        assert (Xm + ref).abs().max() < 1e-14 * ref.abs().max()
+
+
+def test_mp2_level_alpha_agrees_with_lr_ccsd_to_first_order():
+    """The diagonal Jacobian of the reading drops couplings that are first
+    order in the integrals (which scale as the square of the factors): halving
+    the factors cuts alpha_MP2 - alpha_LR-CCSD by about 4."""
+    from oracle.mp2 import mp2_level
+    o, v = 3, 5
+    inp = make_inputs(o, v, 8, seed=5)
+    d = []
+    for s in (2.0, 1.0):
+        B = inp.B * s
+        _, al = mp2_level(B, inp.fock, inp.mu, o, [0.13])
+        ref = lr_ccsd(B, inp.fock, inp.mu, o, [0.13])
+        d.append(np.abs(al - ref.alpha).max())
+    assert 3.6 < d[0] / d[1] < 4.4
