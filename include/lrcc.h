@@ -149,6 +149,26 @@ int lrcc_solve_response(lrcc_ctx *ctx, int nw, const double *omegas, lrcc_stats 
    Afterwards lrcc_get_amplitudes serves LRCC_AMP_X and LRCC_AMP_XMINUS
    (LRCC_AMP_Y returns LRCC_E_STATE). */
 int lrcc_solve_response_quadratic(lrcc_ctx *ctx, int nw, const double *omegas, lrcc_stats *per_rhs);
+/* MP2-level correlation energy and polarizability in the current virtual
+   space: the terms whose full-space minus truncated-space differences are
+   the FNS++ corrections Delta E_MP2 and Delta alpha_MP2 (Eqs. 51-54; call
+   once before lrcc_fnspp_truncate and once after, and add the differences to
+   the LR-CCSD results of the truncated space).  The paper builds the
+   MP2-level response function from the MP2 amplitudes and the perturbed
+   amplitudes of Eqs. 46-47; the reading implemented here:
+     t(1) = -Omega(0)/D, lambda(1) = -eta0(0)/D (first Jacobi steps of the T
+     and Lambda equations; Eq. 39 for a diagonal Fock matrix);
+     E_MP2 = E(t(1));
+     X^B(+-w) = -xi^B(t(1)) / (Dbar -/+ w) with Dbar the denominators of
+     Eqs. 46-47 from the Hbar diagonals of Eqs. 49-50 (orbital energies
+     from the Fock diagonal);
+     alpha_MP2 from Eq. 36 at (t(1), lambda(1)).
+   FP64 throughout.  emp2[2] (host) receives E_MP2; alpha [nw][ncomp][ncomp]
+   complex (host or device per `where`).  Needs lrcc_load_df, _fock and
+   _dipoles; the context's T and Lambda are kept, X, Y and the alpha of
+   lrcc_get_alpha are not touched.  LRCC_E_SINGULAR if a frequency lies on
+   an Hbar denominator. */
+int lrcc_mp2_response(lrcc_ctx *ctx, int nw, const double *omegas, double emp2[2], void *alpha, int where);
 /* alpha[nw][ncomp][ncomp] complex (alpha_AB(w) = -1/2 [f_AB + conj f_BA],
    f_AB = Y^B.xi^A + eta^A.X^B, Eq. 35) from the last lrcc_solve_response. */
 int lrcc_get_alpha(lrcc_ctx *ctx, void *alpha, int where);

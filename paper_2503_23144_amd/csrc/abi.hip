@@ -201,6 +201,24 @@ int lrcc_solve_response_quadratic(lrcc_ctx* ctx, int nw, const double* omegas, l
   return solve_response_route(ctx, nw, omegas, per_rhs, true);
 }
 
+int lrcc_mp2_response(lrcc_ctx* ctx, int nw, const double* omegas, double emp2[2], void* alpha, int where) {
+  return guard(ctx, [&](Context& c) {
+    LRCC_REQUIRE(emp2 != nullptr && alpha != nullptr, LRCC_E_INVALID, "null output");
+    LRCC_REQUIRE(where == LRCC_HOST || where == LRCC_DEVICE, LRCC_E_INVALID, "bad where");
+    lrcc::cplx e = 0;
+    std::vector<lrcc::cplx> al;
+    c.mp2_response(nw, omegas, e, al);
+    emp2[0] = e.real();
+    emp2[1] = e.imag();
+    if (where == LRCC_HOST) {
+      std::memcpy(alpha, al.data(), al.size() * 16);
+    } else {
+      HIP_CHECK(hipMemcpyAsync(alpha, al.data(), al.size() * 16, hipMemcpyHostToDevice, c.st));
+      c.sync();
+    }
+  });
+}
+
 int lrcc_get_alpha(lrcc_ctx* ctx, void* alpha, int where) {
   return guard(ctx, [&](Context& c) {
     LRCC_REQUIRE(c.have_alpha, LRCC_E_STATE, "no polarizability (call lrcc_solve_response first)");

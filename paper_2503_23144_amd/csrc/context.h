@@ -103,8 +103,13 @@ struct Context {
   void solve_ground(double ecorr_out[2], SolveStats& s);
   void solve_lambda(SolveStats& s);
   void solve_response(int nw, const double* om, std::vector<SolveStats>& per, bool quadratic = false);
-  void alpha_quadratic(int nw, int chunk, DevBuf& dots, DevBuf& work);
-  void eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec);  // eta^B + F X^B
+  void alpha_quadratic(int nw, int chunk, const void* Xp, const void* Xm, const void* etaB, int prec,
+                       std::vector<cplx>& out);
+  // eta^B + F X^B (etaB: [ncomp][n], used on the mixed path)
+  void eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec, const void* etaB);
+  // MP2-level energy and alpha in the current virtual space (FNS++ corrections)
+  void mp2_response(int nw, const double* om, cplx& emp2, std::vector<cplx>& al);
+  void hbar_diagonals(std::vector<double>& Hii, std::vector<double>& Haa);
   int response_route = 0;  // 35: X and Y (Eq. 35); 36: X(w) and X(-w) (Eq. 36, X(-w) in Y)
 
   // ---- Jacobian products on device FP64 vectors [nb][n] (in/out may alias no)

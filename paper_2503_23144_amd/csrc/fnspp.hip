@@ -153,15 +153,12 @@ void rotate(int64_t nq, int64_t nmo, int64_t m, const void* X, const void* C, vo
 
 }  // namespace
 
-void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out) {
-  require_sizes();
-  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
-  LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
-  LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
-  LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
+// Steps 1-2: MP2 doubles (full [i][j][a][b] tensor, left in the projection
+// program's input) and the Hbar diagonals.
+void Context::hbar_diagonals(std::vector<double>& Hii, std::vector<double>& Haa) {
   const int64_t vv = v, oo = o;
   const size_t n2f = (size_t)oo * oo * vv * vv;
-  DevBuf epsd, t2, Hd;
+  DevBuf epsd;
   epsd.ensure(nmo * 8);
   HIP_CHECK(hipMemcpy(epsd.p, eps.data(), nmo * 8, hipMemcpyHostToDevice));
   // 1. MP2 doubles into the projection program's input
@@ -178,7 +175,8 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
   launch_batched_dot<double>(oo, oo * vv * vv, tm2, oo * vv * vv, goovv, oo * vv * vv, false, dots.p, wk.p, st);
   HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, oo * 16, hipMemcpyDeviceToHost, st));
   sync();
-  std::vector<double> Hii(oo), Haa(vv);
+  Hii.assign(oo, 0.0);
+  Haa.assign(vv, 0.0);
   for (int64_t i = 0; i < oo; ++i) Hii[i] = eps[i] + 0.5 * hd[i].real();
   tA.ensure(n2f * 16);
   gA.ensure(n2f * 16);
@@ -189,6 +187,19 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
   HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, vv * 16, hipMemcpyDeviceToHost, st));
   sync();
   for (int64_t a = 0; a < vv; ++a) Haa[a] = eps[o + a] - 0.5 * hd[a].real();
+}
+
+void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out) {
+  require_sizes();
+  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+  LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
+  LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
+  LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
+  const int64_t vv = v, oo = o;
+  const size_t n2f = (size_t)oo * oo * vv * vv;
+  std::vector<double> Hii, Haa;
+  hbar_diagonals(Hii, Haa);
+  DevBuf Hd;
   Hd.ensure((oo + vv) * 8);
   HIP_CHECK(hipMemcpy(Hd.p, Hii.data(), oo * 8, hipMemcpyHostToDevice));
   HIP_CHECK(hipMemcpy((char*)Hd.p + oo * 8, Haa.data(), vv * 8, hipMemcpyHostToDevice));
@@ -285,6 +296,115 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
   load_fock(Fn.p, LRCC_DEVICE);
   load_dipoles(nc, Mn.p, LRCC_DEVICE);
   if (nvir_out) *nvir_out = nk;
+}
+
+// MP2-level energy and polarizability in the current virtual space, the
+// ingredients of the corrections of Eqs. 51-54 (full minus truncated space).
+// Reading of the MP2-level response function (built, per the paper, from
+// the MP2 amplitudes and the perturbed amplitudes of Eqs. 46-47):
+//   t(1) = -Omega(0)/D and lambda(1) = -eta0(0)/D (first Jacobi steps of the
+//   T and Lambda equations; Eq. 39 for a diagonal Fock matrix),
+//   E_MP2 = E(t(1)),
+//   X^B(+-w) = -xi^B(t(1)) / (Dbar -/+ w), Dbar from the Hbar diagonals of
+//   Eqs. 49-50 (the Jacobian replaced by that diagonal, as in Eqs. 46-47),
+//   alpha from Eq. 36 at (t(1), lambda(1)).
+// All in FP64.  The context's T and Lambda are restored afterwards; X, Y and
+// the last alpha are not touched.
+void Context::mp2_response(int nw, const double* om, cplx& emp2, std::vector<cplx>& al) {
+  require_sizes();
+  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+  LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
+  LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
+  const size_t vb = n * 16;
+  const int nrhs = nw * ncomp;
+  // Dbar (packed like D) from the Hbar diagonals
+  std::vector<double> Hii, Haa;
+  hbar_diagonals(Hii, Haa);
+  std::vector<double> hb(Hii);
+  hb.insert(hb.end(), Haa.begin(), Haa.end());
+  DevBuf hbd, Dbar;
+  hbd.ensure(nmo * 8);
+  Dbar.ensure(n * 8);
+  HIP_CHECK(hipMemcpy(hbd.p, hb.data(), nmo * 8, hipMemcpyHostToDevice));
+  launch_denominators(o, v, hbd.as<double>(), Dbar.as<double>(), st);
+  {
+    std::vector<double> hD(n);
+    HIP_CHECK(hipMemcpyAsync(hD.data(), Dbar.p, n * 8, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int k = 0; k < nw; ++k)
+      for (int64_t i = 0; i < n; ++i)
+        LRCC_REQUIRE(std::abs(hD[i] - std::abs(om[k])) >= 1e-8, LRCC_E_SINGULAR,
+                     "frequency " + std::to_string(om[k]) + " lies on an Hbar denominator pole");
+  }
+  // keep the context's amplitudes; primal intermediates are recomputed later
+  DevBuf ts, ls;
+  const bool had_t = have_t, had_lam = have_lam;
+  if (had_t) HIP_CHECK(hipMemcpyAsync(ts.ensure(vb), t.p, vb, hipMemcpyDeviceToDevice, st));
+  if (had_lam) HIP_CHECK(hipMemcpyAsync(ls.ensure(vb), lam.p, vb, hipMemcpyDeviceToDevice, st));
+  auto invalidate = [&]() {
+    primal64 = primal32 = 0;
+    gradL_ready = gradL32_ready = 0;
+  };
+  struct Restore {
+    Context& c;
+    DevBuf &ts, &ls;
+    bool ht, hl;
+    size_t vb;
+    ~Restore() {
+      if (ht) (void)hipMemcpyAsync(c.t.p, ts.p, vb, hipMemcpyDeviceToDevice, c.st);
+      if (hl) (void)hipMemcpyAsync(c.lam.p, ls.p, vb, hipMemcpyDeviceToDevice, c.st);
+      (void)hipStreamSynchronize(c.st);
+      c.have_t = ht;
+      c.have_lam = hl;
+      c.primal64 = c.primal32 = 0;
+      c.gradL_ready = c.gradL32_ready = 0;
+    }
+  } restore{*this, ts, ls, had_t, had_lam, vb};
+  // Omega(0) and eta0(0)
+  DevBuf R, e0;
+  R.ensure(vb);
+  e0.ensure(vb);
+  t.ensure(vb);
+  launch_fill_zero<double>(t.p, n, st);
+  have_t = true;
+  invalidate();
+  residual64(t.p, R.p, nullptr);
+  x64->run(P.eta0, 1);
+  launch_copy_rows<double, double>(1, n1, x64->ptr(P.e_gt1), n1, e0.p, n, st);
+  launch_copy_rows<double, double>(1, n2, x64->ptr(P.e_gt2p), n2, (char*)e0.p + n1 * 16, n, st);
+  // t(1), lambda(1) and E_MP2 = E(t(1))
+  launch_jacobi(1, n, D.as<double>(), nullptr, nullptr, R.p, t.p, nullptr, st);
+  lam.ensure(vb);
+  launch_jacobi(1, n, D.as<double>(), nullptr, nullptr, e0.p, lam.p, nullptr, st);
+  have_lam = true;
+  invalidate();
+  residual64(t.p, R.p, &emp2);
+  // xi^B, eta^B at (t(1), lambda(1)); X^B(+-w) on the Hbar diagonal
+  DevBuf xiB, etaB, Xp, Xm, shp, shm;
+  xiB.ensure(ncomp * vb);
+  etaB.ensure(ncomp * vb);
+  xi_vectors(xiB.p);
+  std::vector<int> comps(ncomp);
+  for (int c = 0; c < ncomp; ++c) comps[c] = c;
+  hvp(ncomp, comps.data(), nullptr, etaB.p);
+  Xp.ensure(nrhs * vb);
+  Xm.ensure(nrhs * vb);
+  std::vector<double> sp(nrhs), sm(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    sp[r] = -om[r / ncomp];
+    sm[r] = om[r / ncomp];
+  }
+  shp.ensure(nrhs * 8);
+  shm.ensure(nrhs * 8);
+  HIP_CHECK(hipMemcpyAsync(shp.p, sp.data(), nrhs * 8, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(shm.p, sm.data(), nrhs * 8, hipMemcpyHostToDevice, st));
+  for (int k = 0; k < nw; ++k) {
+    launch_jacobi(ncomp, n, Dbar.as<double>(), shp.as<double>() + k * ncomp, nullptr, xiB.p,
+                  (char*)Xp.p + (size_t)k * ncomp * vb, nullptr, st);
+    launch_jacobi(ncomp, n, Dbar.as<double>(), shm.as<double>() + k * ncomp, nullptr, xiB.p,
+                  (char*)Xm.p + (size_t)k * ncomp * vb, nullptr, st);
+  }
+  alpha_quadratic(nw, rhs_chunk_for(nrhs, 64), Xp.p, Xm.p, etaB.p, 64, al);
 }
 
 }  // namespace lrcc

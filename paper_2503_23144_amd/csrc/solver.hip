@@ -862,7 +862,7 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
         for (int q = 0; q < nc; ++q)
           HIP_CHECK(hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
       } else {
-        eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, bc.p, prec);
+        eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, bc.p, prec, eta.p);
       }
       HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
       launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);
@@ -873,38 +873,38 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
     }
   }
   // alpha_AB(w) = -1/2 [f_AB + conj f_BA],  f_AB = Y^B . xi^A + eta^A . X^B
-  DevBuf d1, d2, w;
-  d1.ensure(nrhs * 16);
-  d2.ensure(nrhs * 16);
-  w.ensure((size_t)nrhs * 1024 * 16);
   if (quadratic) {
-    alpha_quadratic(nw, chunk, d1, w);
     bc.release();
+    alpha_quadratic(nw, chunk, X.p, Y.p, eta.p, prec, alpha);
   } else {
-  std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
-  for (int a = 0; a < ncomp; ++a) {
-    launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
-    std::vector<cplx> h(nrhs);
-    HIP_CHECK(hipMemcpyAsync(h.data(), d1.p, nrhs * 16, hipMemcpyDeviceToHost, st));
-    sync();
-    for (int r = 0; r < nrhs; ++r) fy[r * ncomp + a] = h[r];
-    launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, d2.p, w.p, st);
-    HIP_CHECK(hipMemcpyAsync(h.data(), d2.p, nrhs * 16, hipMemcpyDeviceToHost, st));
-    sync();
-    for (int r = 0; r < nrhs; ++r) fx[r * ncomp + a] = h[r];
-  }
-  alpha.assign(nw * ncomp * ncomp, 0.0);
-  for (int k = 0; k < nw; ++k) {
-    std::vector<cplx> f(ncomp * ncomp);
-    for (int a = 0; a < ncomp; ++a)
-      for (int bb = 0; bb < ncomp; ++bb) {
-        int r = k * ncomp + bb;
-        f[a * ncomp + bb] = fy[r * ncomp + a] + fx[r * ncomp + a];
-      }
-    for (int a = 0; a < ncomp; ++a)
-      for (int bb = 0; bb < ncomp; ++bb)
-        alpha[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
-  }
+    DevBuf d1, d2, w;
+    d1.ensure(nrhs * 16);
+    d2.ensure(nrhs * 16);
+    w.ensure((size_t)nrhs * 1024 * 16);
+    std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
+    for (int a = 0; a < ncomp; ++a) {
+      launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
+      std::vector<cplx> h(nrhs);
+      HIP_CHECK(hipMemcpyAsync(h.data(), d1.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+      sync();
+      for (int r = 0; r < nrhs; ++r) fy[r * ncomp + a] = h[r];
+      launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, d2.p, w.p, st);
+      HIP_CHECK(hipMemcpyAsync(h.data(), d2.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+      sync();
+      for (int r = 0; r < nrhs; ++r) fx[r * ncomp + a] = h[r];
+    }
+    alpha.assign(nw * ncomp * ncomp, 0.0);
+    for (int k = 0; k < nw; ++k) {
+      std::vector<cplx> f(ncomp * ncomp);
+      for (int a = 0; a < ncomp; ++a)
+        for (int bb = 0; bb < ncomp; ++bb) {
+          int r = k * ncomp + bb;
+          f[a * ncomp + bb] = fy[r * ncomp + a] + fx[r * ncomp + a];
+        }
+      for (int a = 0; a < ncomp; ++a)
+        for (int bb = 0; bb < ncomp; ++bb)
+          alpha[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
+    }
   }
   have_alpha = true;
   bool all = true;
@@ -915,28 +915,32 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
 // eta^B + F X^B for nb right-hand sides with components comp.  On the mixed
 // path F X takes FP32 products (F does not involve the Fock diagonal) and
 // eta^B is added in FP64.
-void Context::eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec) {
+void Context::eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, int prec, const void* etaB) {
   if (prec == 64) return hvp(nb, comp, Xs, out);
   const size_t vb = n * 16;
   DevBuf f32;
   f32.ensure(nb * n * 8);
   fx32(nb, Xs, f32.p);
   for (int q = 0; q < nb; ++q)
-    launch_residual<float>(1, n, (char*)f32.p + (size_t)q * n * 8, nullptr, nullptr, (char*)eta.p + comp[q] * vb, 0,
-                           (char*)out + q * vb, st);
+    launch_residual<float>(1, n, (char*)f32.p + (size_t)q * n * 8, nullptr, nullptr,
+                           (const char*)etaB + comp[q] * vb, 0, (char*)out + q * vb, st);
 }
 
-// alpha on the Eq. 36 route from X(w) (in X) and X(-w) (in Y).  With
+// alpha on the Eq. 36 route from X(w) (Xp) and X(-w) (Xm), [nw][ncomp][n]
+// each, and eta^B (etaB, [ncomp][n]).  With
 // H^B = eta^B + F X^B(w) and the symmetry of F (a Hessian: u.F v = v.F u),
 //   f_AB(w)  = eta^A.X^B(w) + eta^B.X^A(-w) + X^A(-w).F X^B(w)
 //            = eta^A.X^B(w) + X^A(-w).H^B,
 //   f_AB(-w) = eta^B.X^A(w) + X^B(-w).H^A.
 // H is built in chunks of right-hand sides; the bilinear dots run on the
 // device.
-void Context::alpha_quadratic(int nw, int chunk, DevBuf& dots, DevBuf& work) {
+void Context::alpha_quadratic(int nw, int chunk, const void* Xp, const void* Xm, const void* etaB, int prec,
+                              std::vector<cplx>& out) {
   const size_t vb = n * 16;
   const int nrhs = nw * ncomp;
-  const int prec = cfg.precision == LRCC_MIXED ? 32 : 64;
+  DevBuf dots, work;
+  dots.ensure((size_t)nrhs * ncomp * 16);
+  work.ensure((size_t)nrhs * 1024 * 16);
   auto fetch = [&](size_t cnt) {
     std::vector<cplx> h(cnt);
     HIP_CHECK(hipMemcpyAsync(h.data(), dots.p, cnt * 16, hipMemcpyDeviceToHost, st));
@@ -946,35 +950,34 @@ void Context::alpha_quadratic(int nw, int chunk, DevBuf& dots, DevBuf& work) {
   // ep[r][a] = eta^a . X_r(w) for every right-hand side r
   std::vector<cplx> ep(nrhs * ncomp);
   for (int a = 0; a < ncomp; ++a) {
-    launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, dots.p, work.p, st);
+    launch_batched_dot<double>(nrhs, n, Xp, n, (const char*)etaB + a * vb, 0, false, dots.p, work.p, st);
     auto h = fetch(nrhs);
     for (int r = 0; r < nrhs; ++r) ep[r * ncomp + a] = h[r];
   }
   // q[r][a] = X^a(-w_k) . H_r for r = k * ncomp + b
-  dots.ensure((size_t)nrhs * ncomp * 16);
   DevBuf H;
   H.ensure((size_t)std::min(chunk, nrhs) * vb);
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int nc = std::min(chunk, nrhs - c0);
     std::vector<int> cp(nc);
     for (int q = 0; q < nc; ++q) cp[q] = (c0 + q) % ncomp;
-    eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, H.p, prec);
+    eta_plus_fx(nc, cp.data(), (const char*)Xp + c0 * vb, H.p, prec, etaB);
     for (int q = 0; q < nc; ++q) {
       const int r = c0 + q, k = r / ncomp;
       for (int a = 0; a < ncomp; ++a)
-        launch_batched_dot<double>(1, n, (char*)Y.p + ((size_t)k * ncomp + a) * vb, n, (char*)H.p + q * vb, n, false,
-                                   (char*)dots.p + ((size_t)r * ncomp + a) * 16, work.p, st);
+        launch_batched_dot<double>(1, n, (const char*)Xm + ((size_t)k * ncomp + a) * vb, n, (char*)H.p + q * vb, n,
+                                   false, (char*)dots.p + ((size_t)r * ncomp + a) * 16, work.p, st);
     }
   }
   const auto qv = fetch((size_t)nrhs * ncomp);
-  alpha.assign(nw * ncomp * ncomp, 0.0);
+  out.assign(nw * ncomp * ncomp, 0.0);
   for (int k = 0; k < nw; ++k)
     for (int a = 0; a < ncomp; ++a)
       for (int b = 0; b < ncomp; ++b) {
         const int ra = k * ncomp + a, rb = k * ncomp + b;
         const cplx fp = ep[rb * ncomp + a] + qv[rb * ncomp + a];  // eta^a.X^b(w) + X^a(-w).H^b
         const cplx fm = ep[ra * ncomp + b] + qv[ra * ncomp + b];  // eta^b.X^a(w) + X^b(-w).H^a
-        alpha[(k * ncomp + a) * ncomp + b] = -0.5 * (fp + std::conj(fm));
+        out[(k * ncomp + a) * ncomp + b] = -0.5 * (fp + std::conj(fm));
       }
 }
 

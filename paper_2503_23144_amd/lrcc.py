@@ -68,6 +68,7 @@ _sig = {
     "lrcc_solve_lambda": (_i, [_vp, ctypes.POINTER(Stats)]),
     "lrcc_solve_response": (_i, [_vp, _i, _vp, _vp]),
     "lrcc_solve_response_quadratic": (_i, [_vp, _i, _vp, _vp]),
+    "lrcc_mp2_response": (_i, [_vp, _i, _vp, _vp, _vp, _i]),
     "lrcc_get_alpha": (_i, [_vp, _vp, _i]),
     "lrcc_sigma": (_i, [_vp, _i, _i, _vp, _vp, _vp, _i, _i]),
     "lrcc_amplitude_length": (_i64, [_vp]),
@@ -257,6 +258,15 @@ class Context:
         fn = lib.lrcc_solve_response_quadratic if quadratic else lib.lrcc_solve_response
         self._check(fn(self._h, om.size, om.ctypes.data, st), allow=(E_NOCONV,) if allow_noconv else ())
         return [s.as_dict() for s in st]
+
+    def mp2_response(self, omegas):
+        """(E_MP2, alpha_MP2 [nw, ncomp, ncomp]) in the current virtual space:
+        the terms of the FNS++ corrections (full minus truncated space)."""
+        om = np.ascontiguousarray(omegas, dtype=np.float64)
+        e = (ctypes.c_double * 2)()
+        out = np.zeros((om.size, self.ncomp, self.ncomp), dtype=np.complex128)
+        self._check(lib.lrcc_mp2_response(self._h, om.size, om.ctypes.data, e, out.ctypes.data, HOST))
+        return complex(e[0], e[1]), out
 
     def alpha(self, nw):
         out = np.zeros((nw, self.ncomp, self.ncomp), dtype=np.complex128)

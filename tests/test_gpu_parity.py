@@ -282,6 +282,61 @@ def test_quadratic_route_mixed_precision_and_stored_c2_alpha():
         assert _relerr(c.alpha(len(ref["omegas"])), ref["alpha"]) < tol, prec
 
 
+# ------------------------------------------------------------------ MP2-level corrections (Eqs. 51-54)
+@pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
+def test_mp2_response_matches_oracle(name, o, v, naux, scale, seed):
+    """E_MP2 and alpha_MP2 against the oracle's reading; the context's T and
+    Lambda survive the call (the response solve afterwards still matches)."""
+    from oracle.mp2 import mp2_level
+    from oracle.response import lr_ccsd
+    lrcc = _lrcc()
+    inp = make_inputs(o, v, naux, seed=seed)
+    inp.B = inp.B * scale
+    omegas = [0.0, 0.11]
+    e_ref, a_ref = mp2_level(inp.B, inp.fock, inp.mu, o, omegas)
+    c = _ctx(inp, tol=1e-11)
+    e, al = c.mp2_response(omegas)
+    assert abs(e - e_ref) < 1e-12 * abs(e_ref)
+    assert _relerr(al, a_ref) < 1e-11
+    c.solve_ground()
+    c.solve_lambda()
+    T = c.get_amplitudes(lrcc.AMP_T)
+    e2, al2 = c.mp2_response(omegas)
+    assert e2 == e and _relerr(al2, al) < 1e-13
+    assert np.array_equal(c.get_amplitudes(lrcc.AMP_T), T)
+    c.solve_response(omegas)
+    ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
+    assert _relerr(c.alpha(len(omegas)), ref.alpha) < 1e-8
+
+
+def test_fnspp_mp2_corrections_match_oracle():
+    """Delta E_MP2 and Delta alpha_MP2 (full minus FNS++-truncated space) and
+    the corrected LR-CCSD alpha of the truncated space."""
+    from oracle.fnspp import fnspp_transform
+    from oracle.mp2 import mp2_level
+    from oracle.response import lr_ccsd
+    o, v, keep = 3, 10, 6
+    inp = make_inputs(o, v, 12, seed=31)
+    inp.B = inp.B * 8.0
+    omegas = [0.05, 0.12]
+    e_full, a_full = mp2_level(inp.B, inp.fock, inp.mu, o, omegas)
+    _, _, (Bn, fn, mun) = fnspp_transform(inp.B, inp.fock, inp.mu, o, omegas, keep=keep)
+    e_tr, a_tr = mp2_level(Bn, fn, mun, o, omegas)
+    ref_cc = lr_ccsd(Bn, fn, mun, o, omegas, tol=1e-13)
+    c = _ctx(inp)
+    e0, al0 = c.mp2_response(omegas)
+    nk, _ = c.fnspp_truncate(omegas, keep=keep)
+    assert nk == keep
+    e1, al1 = c.mp2_response(omegas)
+    assert abs((e0 - e1) - (e_full - e_tr)) < 1e-10 * abs(e_full)
+    assert _relerr(al0 - al1, a_full - a_tr) < 1e-8
+    c.solve_ground()
+    c.solve_lambda()
+    c.solve_response(omegas)
+    corrected = c.alpha(len(omegas)) + (al0 - al1)
+    assert _relerr(corrected, ref_cc.alpha + (a_full - a_tr)) < 1e-8
+
+
 # ------------------------------------------------------------------ FNS++ (A2)
 def test_fnspp_truncation_matches_oracle():
     from oracle.fnspp import fnspp_transform
