@@ -22,6 +22,10 @@ Steps, in the paper's order (Section II.B-II.C, Eqs. 39-50):
  6. F~ = V~^H F_vv V~, F~ Z~ = Z~ e~ (Eqs. 42-43); U = V~ Z~ (Eq. 44 read with
     the product order that makes U a (v_full x v_kept) matrix).
  7. Rotate the virtual block of B, mu and f with U.
+
+The ground-state scheme (FNS, Section II.B, Eq. 40) takes steps 5-7 with
+the MP2 density D_ab = 1/2 sum_ijc t_ij^ac conj t_ij^bc (same Gram reading)
+in place of step 4.
 """
 from __future__ import annotations
 
@@ -82,10 +86,29 @@ def fnspp_density(B, fock, mu, o, omegas, omega_sign=+1.0):
     return (D / count).numpy(), t2
 
 
+def fns_density(B, fock, o):
+    """Ground-state MP2 vv density of the FNS scheme (Eq. 40), read as the
+    Hermitian Gram matrix D_ab = 1/2 sum_ijc t_ij^ac conj t_ij^bc."""
+    t2, _, _ = mp2_and_hbar(B, fock, o)
+    return (0.5 * einsum("ijac,ijbc->ab", t2, t2.conj())).numpy(), t2
+
+
 def fnspp_transform(B, fock, mu, o, omegas, thresh=1e-5, keep=0, omega_sign=+1.0):
     """Returns (U [v_full, v_kept], n (all occupations, sorted by |n| desc),
     new (B, fock, mu) in the truncated semicanonical basis)."""
     D, _ = fnspp_density(B, fock, mu, o, omegas, omega_sign)
+    return transform_from_density(D, B, fock, mu, o, thresh, keep)
+
+
+def fns_transform(B, fock, mu, o, thresh=1e-5, keep=0):
+    """The same steps with the ground-state MP2 density (FNS, Eqs. 40-44)."""
+    D, _ = fns_density(B, fock, o)
+    return transform_from_density(D, B, fock, mu, o, thresh, keep)
+
+
+def transform_from_density(D, B, fock, mu, o, thresh=1e-5, keep=0):
+    """Eqs. 41-44 from a vv density: natural spinors ordered by |n|, the kept
+    ones semicanonicalized, and B, fock, mu rotated into that basis."""
     D = 0.5 * (D + D.conj().T)
     n, V = np.linalg.eigh(D)
     order = np.argsort(-np.abs(n), kind="stable")

@@ -14,7 +14,8 @@ import torch
 from oracle.ccsd import Layout, energy_full, omega_full
 from oracle.derivs import jvp_contour, jvp_fwd, vjp_T, grad_T
 from oracle.detspace import cc_residual_bruteforce, fci_polarizability
-from oracle.fnspp import captured_norm, fnspp_transform, mp2_and_hbar, perturbed_amplitudes, fnspp_density
+from oracle.fnspp import (captured_norm, fns_density, fns_transform, fnspp_transform, mp2_and_hbar,
+                          perturbed_amplitudes, fnspp_density)
 from oracle.integrals import Blocks, eri_block, eri_full
 from oracle.response import (Problem, alpha_eq36, alpha_iso, alpha_uncoupled, bdot, eta, F_times,
                              left_sigma, lr_ccsd, right_sigma, solve_ground, solve_lambda, solve_x,
@@ -370,3 +371,24 @@ def test_mp2_level_alpha_agrees_with_lr_ccsd_to_first_order():
         ref = lr_ccsd(B, inp.fock, inp.mu, o, [0.13])
         d.append(np.abs(al - ref.alpha).max())
     assert 3.6 < d[0] / d[1] < 4.4
+
+
+# ---------------------------------------------------------------- FNS (ground-state natural spinors, Eq. 40)
+def test_fns_no_truncation_is_exact_and_captured_norm():
+    """Keeping every ground-state natural spinor reproduces alpha; the MP2
+    doubles norm carried by natural spinor k equals its occupation n_k."""
+    o, v = 3, 6
+    inp = make_inputs(o, v, 8, seed=12)
+    B = inp.B * 8.0
+    U, n, (Bn, fn, mun) = fns_transform(B, inp.fock, inp.mu, o, keep=v)
+    assert np.allclose(U.conj().T @ U, np.eye(v), atol=1e-12)
+    r0 = lr_ccsd(B, inp.fock, inp.mu, o, [0.05])
+    r1 = lr_ccsd(Bn, fn, mun, o, [0.05])
+    assert np.abs(r0.alpha - r1.alpha).max() < 1e-10 * np.abs(r0.alpha).max()
+    D, t2 = fns_density(B, inp.fock, o)
+    nn, V = np.linalg.eigh(0.5 * (D + D.conj().T))
+    assert np.allclose(captured_norm(None, t2.numpy(), V), nn, rtol=1e-10, atol=1e-18)
+    assert np.all(nn > -1e-18)
+    # and the truncated space keeps the largest occupations
+    _, n4, _ = fns_transform(B, inp.fock, inp.mu, o, keep=4)
+    assert np.allclose(np.sort(np.abs(n4))[::-1], np.abs(n4))
