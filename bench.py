@@ -97,6 +97,59 @@ def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None, quad
                 iters=[s["iterations"] for s in per], phases=ph)
 
 
+def truncation_curve(lrcc, inp, dev_in, ref_alpha, omega_idx, tol, fracs=(0.25, 0.5, 0.75)):
+    """Virtual-space truncation by ground-state natural spinors (FNS, Eq. 40)
+    and by perturbation-sensitive ones (FNS++, Eqs. 45-50) at several kept
+    fractions: error of the isotropic alpha against the full space, without
+    and with the MP2-level correction (Eqs. 53-54), plus the timings.  The
+    paper's Fig. 2 comparison, on the synthetic workload."""
+    import numpy as np
+    omegas = [float(inp.omegas[k]) for k in omega_idx]
+    ref = np.asarray(ref_alpha)[list(omega_idx)]
+    iso = lambda a: np.real(np.trace(a, axis1=-2, axis2=-1)) / 3.0
+
+    def ctx():
+        c = lrcc.Context(precision="mixed", tol=tol)
+        c.load_df(inp.o, inp.v, dev_in["B"])
+        c.load_fock(dev_in["fock"])
+        c.load_dipoles(dev_in["mu"])
+        return c
+
+    c = ctx()
+    t = time.perf_counter()
+    e_full, a_full = c.mp2_response(omegas)
+    t_mp2 = time.perf_counter() - t
+    c.close()
+    rows = []
+    for frac in fracs:
+        keep = max(2, int(round(frac * inp.v)))
+        for scheme in ("fns", "fnspp"):
+            c = ctx()
+            t = time.perf_counter()
+            if scheme == "fns":
+                c.fns_truncate(keep=keep)
+            else:
+                c.fnspp_truncate(omegas, keep=keep)
+            t_trunc = time.perf_counter() - t
+            e_tr, a_tr = c.mp2_response(omegas)
+            t = time.perf_counter()
+            e_cc, _ = c.solve_ground()
+            c.solve_lambda()
+            c.solve_response(omegas)
+            t_solve = time.perf_counter() - t
+            al = c.alpha(len(omegas))
+            c.close()
+            rows.append({"scheme": scheme, "kept_virtuals": keep, "kept_fraction": keep / inp.v,
+                         "alpha_iso_rel_err": [float(x) for x in np.abs(iso(al) - iso(ref)) / np.abs(iso(ref))],
+                         "alpha_iso_rel_err_mp2_corrected": [
+                             float(x) for x in np.abs(iso(al + a_full - a_tr) - iso(ref)) / np.abs(iso(ref))],
+                         "delta_e_mp2": float(np.real(e_full - e_tr)),
+                         "truncate_s": t_trunc, "solve_s": t_solve})
+            print(f"[bench] truncation {scheme} keep {keep}: alpha_iso err {rows[-1]['alpha_iso_rel_err']}",
+                  file=sys.stderr, flush=True)
+    return {"omegas": omegas, "mp2_full_space_s": t_mp2, "rows": rows}
+
+
 def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
     """The particle-particle ladder sum_{e<f} <ab||ef> tau_ij^ef of one batched
     sigma at o=40, v=400: C[(r,i<j)][a<b] = taup[(r,i<j)][e<f] W[a<b][e<f]
@@ -251,6 +304,7 @@ def main():
     ap.add_argument("--no-ladder-scale", action="store_true", help="skip the o=40, v=400 ladder measurement")
     ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
     ap.add_argument("--no-eq36", action="store_true", help="skip the Eq. 36 (X(w), X(-w)) pass")
+    ap.add_argument("--no-truncation", action="store_true", help="skip the FNS / FNS++ truncation curve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
@@ -365,6 +419,9 @@ def main():
                              "alpha_rel_diff_vs_eq35": float(np.abs(r36["alpha"] - last["alpha"]).max()
                                                              / np.abs(last["alpha"]).max())}
         print(f"[bench] eq36 route: {d36:.1f} s", file=sys.stderr, flush=True)
+    if not args.no_truncation:
+        nw = len(inp.omegas)
+        out["truncation_curve"] = truncation_curve(lrcc, inp, dev_in, last["alpha"], (0, nw // 2), args.tol)
     if not args.no_ladder_scale:
         out["ladder_o40_v400"] = ladder_at_scale(lrcc)
     if not args.no_sigma_table:

@@ -125,6 +125,12 @@ int lrcc_load_dipoles(lrcc_ctx *ctx, int ncomp, const void *mu, int where);
    original nvir, may be NULL) the occupations sorted by |n| descending. */
 int lrcc_fnspp_truncate(lrcc_ctx *ctx, const double *omegas, int nw, double thresh, int keep,
                         int *nvir_out, double *occ_out);
+/* Ground-state frozen natural spinors (FNS, Section II.B): the same
+   truncation with the MP2 density D_ab = 1/2 sum_ijc t_ij^ac conj t_ij^bc
+   (Eq. 40, read as a Hermitian Gram matrix) in place of the perturbed one;
+   the baseline FNS++ improves on.  Arguments and results as for
+   lrcc_fnspp_truncate (occupations n >= 0 here). */
+int lrcc_fns_truncate(lrcc_ctx *ctx, double thresh, int keep, int *nvir_out, double *occ_out);
 
 /* Ground state: solves Omega(t) = 0 from t = 0 (the first Jacobi step gives
    MP2).  ecorr[2] (host) receives the complex correlation energy. */

@@ -142,6 +142,10 @@ int lrcc_fnspp_truncate(lrcc_ctx* ctx, const double* omegas, int nw, double thre
   return guard(ctx, [&](Context& c) { c.fnspp_truncate(omegas, nw, thresh, keep, nvir_out, occ_out); });
 }
 
+int lrcc_fns_truncate(lrcc_ctx* ctx, double thresh, int keep, int* nvir_out, double* occ_out) {
+  return guard(ctx, [&](Context& c) { c.fns_truncate(thresh, keep, nvir_out, occ_out); });
+}
+
 int lrcc_solve_ground(lrcc_ctx* ctx, double ecorr[2], lrcc_stats* stats) {
   return guard(ctx, [&](Context& c) {
     lrcc::SolveStats s;

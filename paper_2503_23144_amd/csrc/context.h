@@ -98,6 +98,8 @@ struct Context {
   void load_fock(const void* F, int where);
   void load_dipoles(int nc, const void* m, int where);
   void fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out);
+  void fns_truncate(double thresh, int keep, int* nvir_out, double* occ_out);
+  void truncate_by_density(const void* Dm, double thresh, int keep, int* nvir_out, double* occ_out);
 
   // ---- solves
   void solve_ground(double ecorr_out[2], SolveStats& s);

@@ -153,19 +153,27 @@ void rotate(int64_t nq, int64_t nmo, int64_t m, const void* X, const void* C, vo
 
 }  // namespace
 
+// Step 1: MP2 doubles t[i][j][a][b] (Eq. 39) as a full tensor, written into
+// the input of the projection program (which reads it in step 3).
+static void* mp2_doubles(Context& c) {
+  const size_t n2f = (size_t)c.o * c.o * c.v * c.v;
+  DevBuf epsd;
+  epsd.ensure(c.nmo * 8);
+  HIP_CHECK(hipMemcpy(epsd.p, c.eps.data(), c.nmo * 8, hipMemcpyHostToDevice));
+  void* tm2 = c.x64->ptr(c.P.n_t2);
+  hipLaunchKernelGGL(mp2_kernel, dim3(grid_of(n2f)), dim3(256), 0, c.st, c.o, c.v,
+                     (const double2*)c.x64->ptr(c.P.m.find("gvvoo")), epsd.as<double>(), (double2*)tm2);
+  HIP_CHECK(hipGetLastError());
+  HIP_CHECK(hipStreamSynchronize(c.st));  // before epsd is released
+  return tm2;
+}
+
 // Steps 1-2: MP2 doubles (full [i][j][a][b] tensor, left in the projection
 // program's input) and the Hbar diagonals.
 void Context::hbar_diagonals(std::vector<double>& Hii, std::vector<double>& Haa) {
   const int64_t vv = v, oo = o;
   const size_t n2f = (size_t)oo * oo * vv * vv;
-  DevBuf epsd;
-  epsd.ensure(nmo * 8);
-  HIP_CHECK(hipMemcpy(epsd.p, eps.data(), nmo * 8, hipMemcpyHostToDevice));
-  // 1. MP2 doubles into the projection program's input
-  void* tm2 = x64->ptr(P.n_t2);
-  hipLaunchKernelGGL(mp2_kernel, dim3(grid_of(n2f)), dim3(256), 0, st, oo, vv,
-                     (const double2*)x64->ptr(P.m.find("gvvoo")), epsd.as<double>(), (double2*)tm2);
-  HIP_CHECK(hipGetLastError());
+  void* tm2 = mp2_doubles(*this);
   // 2. Hbar diagonals: per-i and per-a bilinear sums of t2 with <ij||ab>
   const void* goovv = x64->ptr(P.m.find("goovv"));
   DevBuf dots, wk, tA, gA;
@@ -237,11 +245,37 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
       launch_gemm<double>(false, true, vv, vv, oo, scale, 0.0, P1.p, oo, P1c.p, oo, 1.0, 0.0, Dm.p, vv, st);
     }
   }
+  truncate_by_density(Dm.p, thresh, keep, nvir_out, occ_out);
+}
+
+// FNS: steps 5-7 with the ground-state MP2 density D_ab = 1/2 sum_ijc
+// t_ij^ac conj t_ij^bc (Eq. 40, read as a Hermitian Gram matrix).
+void Context::fns_truncate(double thresh, int keep, int* nvir_out, double* occ_out) {
+  require_sizes();
+  LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
+  LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
+  const int64_t vv = v, oo = o;
+  const size_t n2f = (size_t)oo * oo * vv * vv;
+  DevBuf P2, P2c, Dm;
+  void* tm2 = mp2_doubles(*this);
+  P2.ensure(n2f * 16);
+  P2c.ensure(n2f * 16);
+  Dm.ensure(vv * vv * 16);
+  permute(tm2, P2.p, {vv, oo, oo, vv}, {vv, oo * vv * vv, vv * vv, 1}, st);  // [a][i][j][c]
+  conj_copy(n2f, P2.p, P2c.p, st);
+  launch_gemm<double>(false, true, vv, vv, oo * oo * vv, 0.5, 0.0, P2.p, oo * oo * vv, P2c.p, oo * oo * vv, 0.0, 0.0,
+                      Dm.p, vv, st);
+  truncate_by_density(Dm.p, thresh, keep, nvir_out, occ_out);
+}
+
+// Steps 5-7 from a Hermitian vv density on the device (row-major v x v).
+void Context::truncate_by_density(const void* Dmp, double thresh, int keep, int* nvir_out, double* occ_out) {
+  const int64_t vv = v;
   // 5. natural spinors, ordered by |n|
   Solver sol(st);
   std::vector<double> nocc;
   std::vector<cplx> Vn;
-  sol.eigh((int)vv, Dm.p, nocc, Vn, st);
+  sol.eigh((int)vv, Dmp, nocc, Vn, st);
   std::vector<int> order(vv);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return std::abs(nocc[a]) > std::abs(nocc[b]); });

@@ -64,6 +64,7 @@ _sig = {
     "lrcc_load_fock": (_i, [_vp, _vp, _i]),
     "lrcc_load_dipoles": (_i, [_vp, _i, _vp, _i]),
     "lrcc_fnspp_truncate": (_i, [_vp, _vp, _i, _d, _i, ctypes.POINTER(_i), _vp]),
+    "lrcc_fns_truncate": (_i, [_vp, _d, _i, ctypes.POINTER(_i), _vp]),
     "lrcc_solve_ground": (_i, [_vp, _vp, ctypes.POINTER(Stats)]),
     "lrcc_solve_lambda": (_i, [_vp, ctypes.POINTER(Stats)]),
     "lrcc_solve_response": (_i, [_vp, _i, _vp, _vp]),
@@ -236,6 +237,14 @@ class Context:
         occ = np.zeros(self.v, dtype=np.float64)
         self._check(lib.lrcc_fnspp_truncate(self._h, om.ctypes.data, om.size, thresh, keep, ctypes.byref(nv),
                                             occ.ctypes.data))
+        self.v = nv.value
+        return nv.value, occ
+
+    def fns_truncate(self, thresh=1e-5, keep=0):
+        """Ground-state natural spinors (FNS, Eq. 40)."""
+        nv = ctypes.c_int()
+        occ = np.zeros(self.v, dtype=np.float64)
+        self._check(lib.lrcc_fns_truncate(self._h, thresh, keep, ctypes.byref(nv), occ.ctypes.data))
         self.v = nv.value
         return nv.value, occ
 

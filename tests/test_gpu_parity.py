@@ -360,6 +360,27 @@ def test_fnspp_truncation_matches_oracle():
     assert _relerr(c.alpha(1), ref.alpha) < 1e-8
 
 
+def test_fns_truncation_matches_oracle():
+    """Ground-state natural spinors (Eq. 40): occupations, the truncated
+    space and alpha in it against the oracle."""
+    from oracle.fnspp import fns_transform
+    from oracle.response import lr_ccsd
+    o, v, keep = 3, 10, 6
+    inp = make_inputs(o, v, 12, seed=31)
+    inp.B = inp.B * 8.0
+    U, n_ref, (Bn, fn, mun) = fns_transform(inp.B, inp.fock, inp.mu, o, keep=keep)
+    c = _ctx(inp)
+    nk, occ = c.fns_truncate(keep=keep)
+    assert nk == keep
+    assert _relerr(occ, n_ref) < 1e-10
+    ref = lr_ccsd(Bn, fn, mun, o, [0.1], tol=1e-13)
+    e, _ = c.solve_ground()
+    assert abs(e - ref.ecorr) < 1e-10 * abs(ref.ecorr)
+    c.solve_lambda()
+    c.solve_response([0.1])
+    assert _relerr(c.alpha(1), ref.alpha) < 1e-8
+
+
 def test_fnspp_without_truncation_keeps_alpha():
     inp = make_inputs(3, 8, 10, seed=32)
     inp.B = inp.B * 8.0
