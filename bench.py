@@ -150,6 +150,33 @@ def truncation_curve(lrcc, inp, dev_in, ref_alpha, omega_idx, tol, fracs=(0.25, 
     return {"omegas": omegas, "mp2_full_space_s": t_mp2, "rows": rows}
 
 
+def _sampled_entries(A, W, C, dt, count=48):
+    """Parity of C = A W^T at full size on sampled entries: each entry is
+    recomputed on the host as a complex128 dot product of one row of A and
+    one row of W, and its error is compared with the dot-product rounding
+    scale eps * sum_k |A_ik| |W_jk| (eps of the GEMM's precision)."""
+    import numpy as np
+    import torch
+    g = np.random.default_rng(17)
+    ii = g.integers(0, A.shape[0], count)
+    jj = g.integers(0, W.shape[0], count)
+    ar = A[torch.as_tensor(ii, device=A.device)].cpu().numpy().astype(np.complex128)
+    wr = W[torch.as_tensor(jj, device=W.device)].cpu().numpy().astype(np.complex128)
+    got = C[torch.as_tensor(ii, device=C.device), torch.as_tensor(jj, device=C.device)].cpu().numpy()
+    ref = np.einsum("sk,sk->s", ar, wr)
+    scale = np.einsum("sk,sk->s", np.abs(ar), np.abs(wr))
+    eps = 2.0 ** -24 if dt == torch.complex64 else 2.0 ** -53
+    ratio = float(np.max(np.abs(got - ref) / (eps * scale)))
+    # rounding grows like sqrt(K) for random data; 4 sqrt(K) is far below the
+    # worst-case K and far above what a wrong index or a dropped term gives
+    bound = 4.0 * np.sqrt(A.shape[1])
+    ok = ratio <= bound
+    print(f"[bench]   sampled entries: max |err| / (eps sum|a||b|) = {ratio:.2f} (bound {bound:.0f})",
+          file=sys.stderr, flush=True)
+    assert ok, "ladder GEMM at scale disagrees with the host dot products"
+    return {"entries": count, "max_err_over_eps_scale": ratio, "bound": bound, "ok": bool(ok)}
+
+
 def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
     """The particle-particle ladder sum_{e<f} <ab||ef> tau_ij^ef of one batched
     sigma at o=40, v=400: C[(r,i<j)][a<b] = taup[(r,i<j)][e<f] W[a<b][e<f]
@@ -182,7 +209,8 @@ def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
         t = sorted(ts)[len(ts) // 2]
         tf = mult * M * N * K / t / 1e12
         out[name] = {"ms": 1e3 * t, "tflops": tf, "peak": peak, "frac": tf / peak,
-                     "w_gib": W.numel() * W.element_size() / 2**30}
+                     "w_gib": W.numel() * W.element_size() / 2**30,
+                     "sampled_check": _sampled_entries(A, W, C, dt)}
         print(f"[bench] ladder o={o} v={v} {name}: {1e3 * t:.1f} ms, {tf:.1f} TFLOP/s ({100 * tf / peak:.1f}% of peak)",
               file=sys.stderr, flush=True)
         del W, A, C

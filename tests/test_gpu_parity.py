@@ -220,6 +220,28 @@ def test_polarizability_fp64_matches_oracle(name, o, v, naux, scale, seed):
     assert _relerr(Y, ref.Y[(1, 2)].numpy()) < 1e-8
 
 
+@pytest.mark.parametrize("v", [2, 6])
+def test_two_electron_polarizability_is_exact_fci(v):
+    """Two electrons: CCSD is exact, so the GPU's E_corr and alpha(w) (all
+    3x3 complex components, both response routes) equal the FCI values and
+    the exact sum over states (Eq. 18).  v = 2 is the smallest space the
+    method has: one doubles amplitude."""
+    from oracle.detspace import fci_polarizability
+    from oracle.integrals import eri_full
+    inp = make_inputs(2, v, 8, seed=11 + v)
+    inp.B = inp.B * 10.0
+    omegas = [0.0, 0.12]
+    ref, efci, _ = fci_polarizability(inp.fock, eri_full(torch.as_tensor(inp.B)).numpy(), inp.mu, 2, omegas)
+    c = _ctx(inp, tol=1e-11)
+    assert c.n == 2 * v + v * (v - 1) // 2
+    e, _ = c.solve_ground()
+    assert abs(e - efci) < 1e-10 * abs(efci)
+    c.solve_lambda()
+    for quadratic in (False, True):
+        c.solve_response(omegas, quadratic=quadratic)
+        assert _relerr(c.alpha(len(omegas)), ref) < 1e-8, quadratic
+
+
 def test_polarizability_mixed_precision_close_to_fp64():
     inp = make_inputs(4, 16, 32, seed=0)
     inp.B = inp.B * 8.0
