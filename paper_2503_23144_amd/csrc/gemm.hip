@@ -531,20 +531,37 @@ static int forced_tile() {
 
 void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 3 ? tile : -1); }
 
-// Split-K for deep products with few output tiles: a 64 x 64 tile grid of
-// fewer than 256 workgroups leaves most CUs idle while each workgroup walks
-// all of K, so the depth is split until about 1024 workgroups run, keeping
-// at least 1024 of depth per split.
-int gemm_splits(int64_t m, int64_t n, int64_t k) {
+// Split-K for deep products whose 64 x 64 tile grid fills the chip poorly.
+// The chip holds `slots` resident 64 x 64 workgroups (four per CU in FP32,
+// two in FP64); a grid of w workgroups runs in ceil(w / slots) rounds, so
+// its efficiency is w / (rounds * slots).  The depth is split s ways (at
+// least 1024 deep each, at most 64 ways, partials of at most 256 MB) for
+// the smallest s within 3 % of the best efficiency, and only when that
+// gains at least 15 % over no split.
+int gemm_splits(int64_t m, int64_t n, int64_t k, bool fp64) {
+  if (k < 2048) return 1;
   const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-  if (tiles >= 256 || k < 2048) return 1;
-  int64_t s = std::min<int64_t>((1024 + tiles - 1) / tiles, k / 1024);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+  const int64_t slots = fp64 ? 512 : 1024;
+  const int64_t part = m * n * (fp64 ? 16 : 8);
+  const int64_t smax = std::min<int64_t>({64, k / 1024, std::max<int64_t>(1, (int64_t(256) << 20) / part)});
+  auto eff = [&](int64_t s) {
+    const int64_t w = tiles * s, rounds = (w + slots - 1) / slots;
+    return (double)w / (double)(rounds * slots);
+  };
+  double best = eff(1);
+  for (int64_t s = 2; s <= smax; ++s) best = std::max(best, eff(s));
+  int64_t pick = 1;
+  for (int64_t s = 1; s <= smax; ++s)
+    if (eff(s) >= 0.97 * best) {
+      pick = s;
+      break;
+    }
+  return eff(pick) >= 1.15 * eff(1) ? (int)pick : 1;
 }
 
 template <typename T>
 size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
-  const int s = gemm_splits(m, n, k);
+  const int s = gemm_splits(m, n, k, sizeof(T) == 8);
   return s > 1 ? (size_t)s * m * n * 2 * sizeof(T) : 0;
 }
 
@@ -555,7 +572,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   if (m <= 0 || n <= 0) return;
   const OutMap om = omap ? *omap : OutMap::plain(ldc);
   {
-    const int splits = gemm_splits(m, n, k);
+    const int splits = gemm_splits(m, n, k, sizeof(T) == 8);
     if (splits > 1 && ws && ws_bytes >= gemm_workspace_bytes<T>(m, n, k)) {
       if (trace_on())
         fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=0 splits=%d\n",
