@@ -177,6 +177,30 @@ def _sampled_entries(A, W, C, dt, count=48):
     return {"entries": count, "max_err_over_eps_scale": ratio, "bound": bound, "ok": bool(ok)}
 
 
+def gemm_probe(lrcc, o=20, v=150, nrhs=48, tile=0):
+    """C = A W^T with the shape of the o=20, v=150 ladder at full batch
+    (M = nrhs * o(o-1)/2, N = K = v(v-1)/2, complex64), three launches with
+    one pinned workgroup tile; prints each launch time."""
+    import torch
+    dev = torch.device("cuda:0")
+    po, pv = o * (o - 1) // 2, v * (v - 1) // 2
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    A = torch.randn(nrhs * po, pv, dtype=torch.complex64, device=dev, generator=g)
+    W = torch.randn(pv, pv, dtype=torch.complex64, device=dev, generator=g)
+    C = torch.empty(nrhs * po, pv, dtype=torch.complex64, device=dev)
+    lrcc.gemm_set_tile(tile)
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lrcc.gemm(A, W, C, transb=True)
+        e1.record()
+        torch.cuda.synchronize()
+        print(f"[bench] gemm probe {A.shape[0]} x {pv} x {pv} tile {tile}: {e0.elapsed_time(e1):.2f} ms",
+              file=sys.stderr, flush=True)
+    lrcc.gemm_set_tile(-1)
+
+
 def ladder_at_scale(lrcc, o=40, v=400, nrhs=4, reps=3):
     """The particle-particle ladder sum_{e<f} <ab||ef> tau_ij^ef of one batched
     sigma at o=40, v=400: C[(r,i<j)][a<b] = taup[(r,i<j)][e<f] W[a<b][e<f]
@@ -333,6 +357,9 @@ def main():
     ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
     ap.add_argument("--no-eq36", action="store_true", help="skip the Eq. 36 (X(w), X(-w)) pass")
     ap.add_argument("--no-truncation", action="store_true", help="skip the FNS / FNS++ truncation curve")
+    ap.add_argument("--gemm-probe", action="store_true",
+                    help="only launch the o=20, v=150 ladder GEMM (48 right-hand sides, FP32 3M, 64 x 64 tile) "
+                         "three times, for hardware counter runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
@@ -352,6 +379,9 @@ def main():
     from paper_2503_23144_amd.synth import CONFIGS, config_inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gemm_probe:
+        gemm_probe(lrcc)
+        return
     inp = config_inputs(args.workload)
     cfg = CONFIGS[args.workload]
     print(f"[bench] workload {args.workload}: o={inp.o} v={inp.v} naux={inp.naux} "
