@@ -5,6 +5,10 @@
 // thread mapping so that stores are coalesced.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+
 #include <cmath>
 
 #include "common.h"
@@ -58,6 +62,62 @@ __global__ void __launch_bounds__(256) permute_kernel(const typename cplx2<T>::t
   }
 }
 
+// Permutations whose input-contiguous dimension p is not the output's last
+// one: the naive kernel above then reads with a stride between neighbouring
+// lanes.  Here each 32 x 32 tile over (dim p, last dim) is read with lanes
+// along p (contiguous in the input), staged in LDS, and written with lanes
+// along the last dim (contiguous in the output).  The remaining dimensions
+// index the tiles; istride[p] must be 1.
+template <typename T>
+__global__ void __launch_bounds__(256) transpose_kernel(const typename cplx2<T>::type* __restrict__ in,
+                                                        typename cplx2<T>::type* __restrict__ out, PermDesc d,
+                                                        int p, int64_t ntiles, int64_t tp, int64_t tl, T are, T aim,
+                                                        T bre, T bim, int use_beta) {
+  using C = typename cplx2<T>::type;
+  __shared__ C tile[32][33];
+  const int L = d.rank - 1;
+  const int64_t np = d.dims[p], nl = d.dims[L], sl = d.istride[L];
+  int64_t ostr[kMaxRank];
+  ostr[L] = 1;
+  for (int k = L - 1; k >= 0; --k) ostr[k] = ostr[k + 1] * d.dims[k + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int64_t rest = t / (tp * tl);
+    const int64_t rem = t - rest * (tp * tl);
+    const int64_t ip0 = (rem / tl) * 32, il0 = (rem % tl) * 32;
+    int64_t ib = 0, ob = 0;
+    for (int k = L - 1; k >= 0; --k) {
+      if (k == p) continue;
+      const int64_t q = rest / d.dims[k];
+      const int64_t dk = rest - q * d.dims[k];
+      rest = q;
+      ib += dk * d.istride[k];
+      ob += dk * ostr[k];
+    }
+    for (int j = ty; j < 32; j += 8) {
+      const int64_t ip = ip0 + tx, il = il0 + j;
+      if (ip < np && il < nl) tile[j][tx] = in[ib + ip + il * sl];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+      const int64_t ip = ip0 + j, il = il0 + tx;
+      if (ip < np && il < nl) {
+        const C x = tile[tx][j];
+        T re = are * x.x - aim * x.y;
+        T im = are * x.y + aim * x.x;
+        C* o = out + ob + ip * ostr[p] + il;
+        if (use_beta) {
+          const C y = *o;
+          re += bre * y.x - bim * y.y;
+          im += bre * y.y + bim * y.x;
+        }
+        *o = C{re, im};
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 void launch_permute(const void* in, void* out, const PermDesc& d, double are, double aim, double bre, double bim,
                     hipStream_t st) {
@@ -66,6 +126,32 @@ void launch_permute(const void* in, void* out, const PermDesc& d, double are, do
   if (total == 0) return;
   using C = typename cplx2<T>::type;
   int ub = (bre != 0.0 || bim != 0.0) ? 1 : 0;
+  static const bool trace = [] {
+    const char* e = std::getenv("LRCC_TRACE_PERMUTE");
+    return e && e[0] == '1';
+  }();
+  if (trace) {  // LRCC_TRACE_PERMUTE=1: shape of every launch on stderr
+    fprintf(stderr, "[lrcc permute] %s beta=%d total=%lld dims", sizeof(T) == 8 ? "c128" : "c64", ub,
+            (long long)total);
+    for (int k = 0; k < d.rank; ++k) fprintf(stderr, " %lld", (long long)d.dims[k]);
+    fprintf(stderr, " istride");
+    for (int k = 0; k < d.rank; ++k) fprintf(stderr, " %lld", (long long)d.istride[k]);
+    fprintf(stderr, "\n");
+  }
+  // tiled transpose when the input-contiguous dimension is not the last one
+  int p = -1;
+  for (int k = 0; k < d.rank; ++k)
+    if (d.istride[k] == 1 && d.dims[k] > 1) p = k;
+  const int L = d.rank - 1;
+  if (p >= 0 && p != L && d.dims[L] > 1) {
+    const int64_t tp = (d.dims[p] + 31) / 32, tl = (d.dims[L] + 31) / 32;
+    const int64_t ntiles = total / (d.dims[p] * d.dims[L]) * tp * tl;
+    const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, int64_t(1) << 20);
+    hipLaunchKernelGGL(transpose_kernel<T>, dim3(blocks), dim3(256), 0, st, (const C*)in, (C*)out, d, p, ntiles,
+                       tp, tl, (T)are, (T)aim, (T)bre, (T)bim, ub);
+    LAUNCH_CHECK();
+    return;
+  }
   if (total < (int64_t(1) << 31))
     hipLaunchKernelGGL((permute_kernel<T, uint32_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)in,
                        (C*)out, d, (uint32_t)total, (T)are, (T)aim, (T)bre, (T)bim, ub);
