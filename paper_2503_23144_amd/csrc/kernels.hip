@@ -171,19 +171,22 @@ __device__ inline void decode_pair(int64_t P, int64_t& p, int64_t& q) {
 }
 
 // ---------------------------------------------------------------- pack
-template <typename T>
+// I: index type of the element decode (uint32_t when every size fits; the
+// 64-bit divisions otherwise dominate these memory-bound kernels).
+template <typename T, typename I>
 __global__ void __launch_bounds__(256) pack_kernel(const typename cplx2<T>::type* __restrict__ full,
                                                    typename cplx2<T>::type* __restrict__ packed, PackDesc d,
-                                                   int64_t total, T are, T aim, int acc) {
-  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total;
-       lin += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = lin, off = 0;
+                                                   I total, T are, T aim, int acc) {
+  for (I lin = (I)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += (I)gridDim.x * blockDim.x) {
+    I rem = lin;
+    int64_t off = 0;
     int np = 0;
     int64_t o1[2] = {0, 0}, o2[2] = {0, 0};
     int md[2] = {0, 0};
     for (int k = d.rank - 1; k >= 0; --k) {
-      int64_t q = rem / d.dims[k];
-      int64_t i = rem - q * d.dims[k];
+      const I dk = (I)d.dims[k];
+      const I q = rem / dk;
+      const int64_t i = (int64_t)(rem - q * dk);
       rem = q;
       if (d.pair[k]) {
         int64_t a, b;
@@ -225,17 +228,17 @@ __global__ void __launch_bounds__(256) pack_kernel(const typename cplx2<T>::type
   }
 }
 
-template <typename T>
+template <typename T, typename I>
 __global__ void __launch_bounds__(256) unpack_kernel(const typename cplx2<T>::type* __restrict__ packed,
                                                      typename cplx2<T>::type* __restrict__ full, PackDesc d,
-                                                     int64_t total, T are, T aim, int acc) {
-  for (int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; lin < total;
-       lin += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = lin;
+                                                     I total, T are, T aim, int acc) {
+  for (I lin = (I)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += (I)gridDim.x * blockDim.x) {
+    I rem = lin;
     int64_t pidx[kMaxRank], qidx[kMaxRank], plain[kMaxRank];
     for (int k = d.frank - 1; k >= 0; --k) {
-      int64_t q = rem / d.fdims[k];
-      int64_t i = rem - q * d.fdims[k];
+      const I dk = (I)d.fdims[k];
+      const I q = rem / dk;
+      const int64_t i = (int64_t)(rem - q * dk);
       rem = q;
       int j = d.fmap[k];
       if (d.fsec[k] < 0)
@@ -287,8 +290,12 @@ void launch_pack(const void* full, void* packed, const PackDesc& d, double are, 
   for (int k = 0; k < d.rank; ++k) total *= d.dims[k];
   if (total == 0) return;
   using C = typename cplx2<T>::type;
-  hipLaunchKernelGGL(pack_kernel<T>, dim3(nblocks(total)), dim3(256), 0, st, (const C*)full, (C*)packed, d, total,
-                     (T)are, (T)aim, acc ? 1 : 0);
+  if (total < (int64_t(1) << 31))
+    hipLaunchKernelGGL((pack_kernel<T, uint32_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)full,
+                       (C*)packed, d, (uint32_t)total, (T)are, (T)aim, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((pack_kernel<T, int64_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)full,
+                       (C*)packed, d, total, (T)are, (T)aim, acc ? 1 : 0);
   LAUNCH_CHECK();
 }
 
@@ -298,8 +305,12 @@ void launch_unpack(const void* packed, void* full, const PackDesc& d, double are
   int64_t total = d.full_elems;
   if (total == 0) return;
   using C = typename cplx2<T>::type;
-  hipLaunchKernelGGL(unpack_kernel<T>, dim3(nblocks(total)), dim3(256), 0, st, (const C*)packed, (C*)full, d,
-                     total, (T)are, (T)aim, acc ? 1 : 0);
+  if (total < (int64_t(1) << 31))
+    hipLaunchKernelGGL((unpack_kernel<T, uint32_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)packed,
+                       (C*)full, d, (uint32_t)total, (T)are, (T)aim, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((unpack_kernel<T, int64_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)packed,
+                       (C*)full, d, total, (T)are, (T)aim, acc ? 1 : 0);
   LAUNCH_CHECK();
 }
 
