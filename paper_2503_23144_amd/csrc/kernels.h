@@ -85,6 +85,16 @@ struct OutMap {
   __host__ __device__ static int64_t off(int64_t x, int nd, const int64_t* dim, const int64_t* str) {
     if (nd == 1) return x * str[0];
     int64_t o = 0;
+    if (x < INT32_MAX) {  // 32-bit digit decode: far cheaper than 64-bit division on the GPU
+      uint32_t y = (uint32_t)x;
+      for (int k = nd - 1; k >= 0; --k) {
+        const uint32_t dk = dim[k] > (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)dim[k];
+        const uint32_t q = y / dk;
+        o += (int64_t)(y - q * dk) * str[k];
+        y = q;
+      }
+      return o;
+    }
     for (int k = nd - 1; k >= 0; --k) {
       const int64_t q = x / dim[k];
       o += (x - q * dim[k]) * str[k];
