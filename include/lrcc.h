@@ -84,6 +84,11 @@ typedef struct lrcc_config {
   int graphs;            /* 1: replay the Jacobian-product programs as HIP graphs (captured on the
                             second identical call, replayed from the third); default 1, or 0 when
                             the environment variable LRCC_GRAPHS is "0" */
+  int ladder_direct;     /* 1: keep no vvvv matrix W[P(a,b)][P(e,f)] = <ab||ef> in device memory
+                            (v^4/4 complex elements per precision); every ladder contraction
+                            rebuilds W's rows in chunks from the density-fitting factors,
+                            (ae|bf) = sum_Q B^Q_ae B^Q_bf, at naux v^4 / 2 extra complex MACs per
+                            ladder.  Results agree with the resident W to rounding.  Default 0. */
 } lrcc_config;
 
 typedef struct lrcc_stats {

@@ -72,6 +72,7 @@ struct Context {
   std::unique_ptr<Executor<float>> x32;
 
   DevBuf B, fock, mu, D;     // FP64 inputs; D = real denominators [n]
+  DevBuf L64, L32;           // DF-direct ladder: virtual-virtual block of B [naux][v][v] per precision
   std::vector<double> eps;   // Fock diagonal (host)
   int ncomp = 0;
   bool have_fock = false;

@@ -154,6 +154,11 @@ void launch_s2d(int64_t n, const void* in, void* out, hipStream_t st);
 // (row (a-a0)*v + e, column (b-b0)*v + f, row length (v-b0)*v).
 template <typename T>
 void launch_pack_vvvv(int64_t v, int64_t a0, int64_t a1, int64_t b0, const void* C, void* W, hipStream_t st);
+// Rows of the same W for b in [b0, b1): Wc[P(a,b) - P(0,b0)][P(e,f)] =
+// C[b-b0][f][a][e] - C[b-b0][e][a][f], where C[(b-b0)*v + f][a*v + e] = (ae|bf)
+// (row length b1*v).
+template <typename T>
+void launch_pack_wrows(int64_t v, int64_t b0, int64_t b1, const void* C, void* Wc, hipStream_t st);
 // dst[x][p][r] = src[x][p0 + p][r0 + r] (sub-block gather), p < np, r < nr
 void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
                          const void* src, void* dst, hipStream_t st);

@@ -619,6 +619,35 @@ void launch_pack_vvvv(int64_t v, int64_t a0, int64_t a1, int64_t b0, const void*
   LAUNCH_CHECK();
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) pack_wrows_kernel(int64_t v, int64_t b0, int64_t b1,
+                                                         const typename cplx2<T>::type* __restrict__ C,
+                                                         typename cplx2<T>::type* __restrict__ Wc) {
+  // grid.y: row offset from P(0, b0); grid.x * 256: E = P(e, f)
+  const int64_t V = v * (v - 1) / 2;
+  int64_t a, b;
+  decode_pair(b0 * (b0 - 1) / 2 + blockIdx.y, a, b);
+  const int64_t ld = b1 * v;
+  const auto* Cr = C + (b - b0) * v * ld + a * v;  // (ae|bf) at Cr[f * ld + e]
+  for (int64_t E = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; E < V; E += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e, f;
+    decode_pair(E, e, f);
+    const auto x = Cr[f * ld + e];
+    const auto y = Cr[e * ld + f];
+    Wc[(int64_t)blockIdx.y * V + E] = {x.x - y.x, x.y - y.y};
+  }
+}
+
+template <typename T>
+void launch_pack_wrows(int64_t v, int64_t b0, int64_t b1, const void* C, void* Wc, hipStream_t st) {
+  const int64_t V = v * (v - 1) / 2, nr = b1 * (b1 - 1) / 2 - b0 * (b0 - 1) / 2;
+  if (V == 0 || nr <= 0) return;
+  using Cx = typename cplx2<T>::type;
+  hipLaunchKernelGGL(pack_wrows_kernel<T>, dim3(nblocks(V, 256, 64), (unsigned)nr), dim3(256), 0, st, v, b0, b1,
+                     (const Cx*)C, (Cx*)Wc);
+  LAUNCH_CHECK();
+}
+
 __global__ void gather_block_kernel(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
                                     const double2* __restrict__ src, double2* __restrict__ dst) {
   int64_t total = naux * np * nr;
@@ -650,7 +679,8 @@ void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int6
   template void launch_residual<T>(int64_t, int64_t, const void*, const double*, const void*, const void*,   \
                                    int64_t, void*, hipStream_t, const double*);                              \
   template void launch_zero_diag<T>(void*, int64_t, hipStream_t);                                            \
-  template void launch_pack_vvvv<T>(int64_t, int64_t, int64_t, int64_t, const void*, void*, hipStream_t);
+  template void launch_pack_vvvv<T>(int64_t, int64_t, int64_t, int64_t, const void*, void*, hipStream_t);    \
+  template void launch_pack_wrows<T>(int64_t, int64_t, int64_t, const void*, void*, hipStream_t);
 INST(double)
 INST(float)
 

@@ -80,6 +80,16 @@ class Executor {
   void set_timing(bool on) { timing_ = on; }
   void collect_times(KernelTimes& kt);  // synchronizes; accumulates and clears pending events
   int ladder_const = -1;                // tensor id whose contractions count as the ladder
+  // DF-direct ladder: with the virtual-virtual block of the density-fitting
+  // factors L[Q][a][e] (naux x v x v, precision T, owned by the caller) set,
+  // a contraction with the ladder constant W[P(a,b)][P(e,f)] = <ab||ef>
+  // rebuilds W's rows chunk by chunk from L instead of reading a resident W.
+  void set_direct_ladder(const void* L, int64_t naux, int64_t v) {
+    dl_L_ = L;
+    dl_naux_ = naux;
+    dl_v_ = v;
+  }
+  static constexpr size_t kDirectChunkBytes = size_t(512) << 20;  // per scratch buffer of the rebuild
 
   // HIP graph replay.  With graphs on, a run whose program, batch and every
   // buffer address match an earlier (eager) run is captured into HIP graphs
@@ -93,6 +103,9 @@ class Executor {
   int64_t graph_captures() const { return captures_; }
 
  private:
+  void ladder_direct(const Op& op);
+  const void* dl_L_ = nullptr;
+  int64_t dl_naux_ = 0, dl_v_ = 0;
   struct GemmArgs {
     bool ta, tb;
     int64_t M, N, K;

@@ -39,8 +39,10 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   cap_.assign(n, 0);
   bound_.assign(n, 0);
   pooled_.assign(n, 0);
-  scr_.assign(7, nullptr);  // 0-2 permutations, 3 unused, 4 split-K partials, 5-6 cached permutations
-  scr_cap_.assign(7, 0);
+  // 0-2 permutations, 3 unused, 4 split-K partials, 5-6 cached permutations,
+  // 7-8 DF-direct ladder: (ae|bf) block and rebuilt rows of W
+  scr_.assign(9, nullptr);
+  scr_cap_.assign(9, 0);
   dot_out_ = dev_alloc(64);
   dot_work_ = dev_alloc(1024 * 16);
 }
@@ -384,6 +386,7 @@ int Executor<T>::cached_permute(int id, const std::string& src, const std::strin
 template <typename T>
 void Executor<T>::contract(const Op& op, int nb) {
   (void)nb;
+  if (dl_L_ && (op.a == ladder_const || op.b == ladder_const)) return ladder_direct(op);
   std::string a = letters(op.a, op.ai), b = letters(op.b, op.bi), c = letters(op.out, op.oi);
   const void* pa = ptr(op.a);
   const void* pb = ptr(op.b);
@@ -533,6 +536,64 @@ void Executor<T>::contract(const Op& op, int nb) {
     void* t = scratch(2, (size_t)Ms * Ns * sizeof(T) * 2);
     gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, 0.0, t, Ns, scratch_elems(2), ladder);
     permute_into(t, scratch_elems(2), Mc + Nc, pc, cc, c, 1, 0, acc ? 1 : 0, 0);
+  }
+}
+
+// Ladder contraction without a resident W (DF-direct).  W's rows P(a,b)
+// (b-major, so the rows of b in [b0, b1) are contiguous) are rebuilt in
+// chunks: one GEMM over the auxiliary index gives (ae|bf) for b in the
+// chunk and every a < b1, a pack kernel antisymmetrizes it into
+// W[P(a,b)][P(e,f)] = (ae|bf) - (af|be), and the ladder GEMM consumes the
+// rows: X[M][K=ef] W^T (contraction over W's column index: the chunk fills
+// columns R0..R1 of the output) or X[M][K=ab] W (over W's row index: the
+// chunk adds its K-range).  Extra work per ladder: naux v^4 / 2 complex MACs.
+template <typename T>
+void Executor<T>::ladder_direct(const Op& op) {
+  const bool w_is_a = op.a == ladder_const;
+  const int idx = w_is_a ? op.b : op.a;
+  const std::string w = letters(ladder_const, w_is_a ? op.ai : op.bi), x = letters(idx, w_is_a ? op.bi : op.ai),
+                    c = letters(op.out, op.oi);
+  LRCC_REQUIRE(w.size() == 2 && x.size() >= 2, LRCC_E_INTERNAL, "DF-direct ladder: unexpected operands");
+  const char kl = x.back();
+  LRCC_REQUIRE(w.find(kl) != std::string::npos && c.find(kl) == std::string::npos, LRCC_E_INTERNAL,
+               "DF-direct ladder: operand X must end with the contracted index");
+  const bool over_col = w[1] == kl;  // X W^T (else X W)
+  const std::string Mc = x.substr(0, x.size() - 1);
+  LRCC_REQUIRE(c == Mc + (over_col ? w[0] : w[1]), LRCC_E_INTERNAL, "DF-direct ladder: unsupported output order");
+  int64_t M = 1;
+  for (char ch : Mc) M *= ch == '#' ? g_nb : dim(ch);
+  const int64_t v = dl_v_, nq = dl_naux_, V = v * (v - 1) / 2;
+  LRCC_REQUIRE(dim(kl) == V && dim(over_col ? w[0] : w[1]) == V, LRCC_E_INTERNAL, "DF-direct ladder: sizes");
+  const void* X = ptr(idx);
+  void* C = ptr(op.out);
+  const int64_t capX = capacity(idx), capC = capacity(op.out), capL = nq * v * v;
+  LRCC_REQUIRE(M * V <= capX && M * V <= capC, LRCC_E_INTERNAL, "DF-direct ladder: operand larger than its buffer");
+  const size_t es = 2 * sizeof(T);
+  const size_t budget = kDirectChunkBytes;
+  bool first = true;
+  for (int64_t b0 = 1; b0 < v;) {
+    auto fits = [&](int64_t bb) {
+      return (size_t)((bb - b0) * v) * (size_t)(bb * v) * es <= budget &&
+             (size_t)(bb * (bb - 1) / 2 - b0 * (b0 - 1) / 2) * (size_t)V * es <= budget;
+    };
+    int64_t b1 = b0 + 1;
+    while (b1 < v && fits(b1 + 1)) ++b1;
+    const int64_t R0 = b0 * (b0 - 1) / 2, nr = b1 * (b1 - 1) / 2 - R0;
+    LRCC_REQUIRE(nr <= 65535, LRCC_E_INTERNAL, "DF-direct ladder: chunk too tall");
+    void* Cb = scratch(7, (size_t)((b1 - b0) * v) * (size_t)(b1 * v) * es);
+    void* Wc = scratch(8, (size_t)nr * (size_t)V * es);
+    // (ae|bf): rows (b, f) for b in [b0, b1), columns (a, e) for a < b1
+    gemm(true, false, (b1 - b0) * v, b1 * v, nq, 1.0, 0.0, (const char*)dl_L_ + b0 * v * es, v * v, capL - b0 * v,
+         dl_L_, v * v, capL, 0.0, Cb, b1 * v, scratch_elems(7), false);
+    launch_pack_wrows<T>(v, b0, b1, Cb, Wc, st_);
+    if (over_col)
+      gemm(false, true, M, nr, V, op.are, op.aim, X, V, capX, Wc, V, scratch_elems(8), op.acc ? 1.0 : 0.0,
+           (char*)C + R0 * es, V, capC - R0, true);
+    else
+      gemm(false, false, M, V, nr, op.are, op.aim, (const char*)X + R0 * es, V, capX - R0, Wc, V, scratch_elems(8),
+           (first && !op.acc) ? 0.0 : 1.0, C, V, capC, true);
+    first = false;
+    b0 = b1;
   }
 }
 

@@ -72,6 +72,13 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   x64->ladder_const = P.m.find("W");
   x64->set_timing(timing);
   x64->set_graphs(cfg.graphs != 0);
+  L64.release();
+  L32.release();
+  if (cfg.ladder_direct) {  // W is never stored; the ladder rebuilds its rows from B_vv
+    L64.ensure((size_t)naux * v * v * 16);
+    launch_gather_block(naux, nmo, o, v, o, v, B.p, L64.p, st);
+    x64->set_direct_ladder(L64.p, naux, v);
+  }
   build_integrals();
   have_fock = false;
   ncomp = 0;
@@ -80,7 +87,7 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
 
 void Context::build_integrals() {
   for (auto& b : kBlocks) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
-  build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
+  if (!cfg.ladder_direct) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
   pack_last_pair(x64->ptr(P.m.find("govvv")), o, v, v, x64->ptr(P.m.find("govvp")), st);
   const double one[2] = {1.0, 0.0};
   HIP_CHECK(hipMemcpyAsync(x64->ptr(P.one), one, 16, hipMemcpyHostToDevice, st));
@@ -91,8 +98,10 @@ static void ensure_x32(Context& c) {
   if (c.x32) return;
   {  // the FP32 copies of the constants; make room from FP64 batch storage if needed
     int64_t need = 0;
+    const int W = c.P.m.find("W");
     for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
       Role r = c.P.m[(int)id].role;
+      if (c.cfg.ladder_direct && (int)id == W) continue;
       if (r == Role::Const || r == Role::Scalar1 || r == Role::Fock) need += c.x64->elems((int)id, 1) * 8;
     }
     if ((double)dev_available() < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
@@ -103,8 +112,14 @@ static void ensure_x32(Context& c) {
   c.x32->set_graphs(c.cfg.graphs != 0);
   for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
     Role r = c.P.m[(int)id].role;
+    if (c.cfg.ladder_direct && (int)id == c.x32->ladder_const) continue;
     if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))
       launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
+  }
+  if (c.cfg.ladder_direct) {
+    c.L32.ensure((size_t)c.naux * c.v * c.v * 8);
+    launch_d2s(c.naux * c.v * c.v, c.L64.p, c.L32.p, c.st);
+    c.x32->set_direct_ladder(c.L32.p, c.naux, c.v);
   }
   if (c.have_fock) {
     launch_zero_diag<float>(c.x32->ptr(c.P.foo), c.o, c.st);
@@ -746,7 +761,8 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
   auto executor = [&](double elem, const std::vector<std::pair<const OpList*, int>>& runs) {
     double b = 0;
     for (size_t id = 0; id < m.tensors.size(); ++id)
-      if (!m.tensors[id].batched) b += elem * (double)tensor_elems(m, d, (int)id, 1);
+      if (!m.tensors[id].batched && !(cfg.ladder_direct && (int)id == m.find("W")))
+        b += elem * (double)tensor_elems(m, d, (int)id, 1);
     std::vector<int64_t> pool;
     std::vector<char> pooled(m.tensors.size(), 0), used(m.tensors.size(), 0);
     int64_t big = 0;
@@ -766,7 +782,8 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
     for (size_t id = 0; id < m.tensors.size(); ++id)
       if (used[id] && !pooled[id]) b += elem * (double)tensor_elems(m, d, (int)id, nb);
     b += elem * 4.0 * (double)big;  // three permutation slots and one tile-timing output
-    return b + 96.0 * (1 << 20);     // split-K partials and small buffers
+    if (cfg.ladder_direct) b += 2.0 * (double)Executor<double>::kDirectChunkBytes;  // W rebuild chunks
+    return b + 320.0 * (1 << 20);    // split-K partials (at most 256 MB) and small buffers
   };
   bytes += executor(16.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 3}, {&P.eta0, 1},
                            {&P.gradL, 1}, {&P.hvp, nb}});

@@ -43,7 +43,7 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("ladder_direct", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -176,7 +176,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True, graphs=None):
+                 verbose=0, autotune=True, graphs=None, ladder_direct=False):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -193,6 +193,7 @@ class Context:
         cfg.verbose = verbose
         if graphs is not None:  # else the library default (LRCC_GRAPHS)
             cfg.graphs = int(graphs)
+        cfg.ladder_direct = int(ladder_direct)
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:
