@@ -126,13 +126,14 @@ def build_info() -> str:
     return lib.lrcc_build_info().decode()
 
 
-def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8):
+def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder_direct=False):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
     lib.lrcc_default_config(ctypes.byref(cfg))
     cfg.precision = {"fp64": FP64, "mixed": MIXED}[precision]
     cfg.diis_size = diis
+    cfg.ladder_direct = int(ladder_direct)
     return int(lib.lrcc_workspace_bytes(ctypes.byref(cfg), o, v, naux, nrhs))
 
 
