@@ -41,6 +41,16 @@ def host_info():
     return info
 
 
+def gemm_source_hash():
+    """First 16 hex digits of the SHA-256 of the GEMM kernel's sources
+    (gemm.hip, then kernels.h, which holds the epilogue's address maps)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_2503_23144_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(workload):
     """HBM bytes per ladder launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken for this workload and the GEMM source
@@ -50,9 +60,8 @@ def measured_traffic(workload):
     path = os.path.join(ROOT, "profiles", "ladder_o20_v150_hbm_traffic.md")
     if workload != "c3" or not os.path.exists(path):
         return None
-    m = re.search(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_hip_sha256_16=([0-9a-f]{16})", open(path).read())
-    src = os.path.join(ROOT, "paper_2503_23144_amd", "csrc", "gemm.hip")
-    if not m or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(3):
+    m = re.search(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_src_sha256_16=([0-9a-f]{16})", open(path).read())
+    if not m or gemm_source_hash() != m.group(3):
         return None
     return {"bytes_per_launch": int(m.group(1)), "tile": m.group(2), "source": os.path.relpath(path, ROOT)}
 
