@@ -74,14 +74,14 @@ def resident(inp):
     return {k: torch.as_tensor(getattr(inp, k)).to(dev) for k in ("B", "fock", "mu")}
 
 
-def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None, quadratic=False, ladder_direct=False):
+def run_pass(lrcc, inp, precision, tol, timing=False, chunk=0, dev_in=None, quadratic=False, ladder="full"):
     """One pass of the hot path; returns counts, alpha and phase times.
     dev_in: the inputs already on the device (resident(inp)).  quadratic:
     alpha by the Eq. 36 route (X(w) and X(-w)) instead of Eq. 35 (X and Y)."""
     ph = {}
     src = dev_in if dev_in is not None else {"B": inp.B, "fock": inp.fock, "mu": inp.mu}
     t = time.perf_counter()
-    c = lrcc.Context(precision=precision, tol=tol, rhs_chunk=chunk, ladder_direct=ladder_direct)
+    c = lrcc.Context(precision=precision, tol=tol, rhs_chunk=chunk, ladder=ladder)
     c.set_timing(timing)
     c.load_df(inp.o, inp.v, src["B"])
     c.load_fock(src["fock"])
@@ -366,7 +366,8 @@ def main():
     ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
     ap.add_argument("--no-eq36", action="store_true", help="skip the Eq. 36 (X(w), X(-w)) pass")
     ap.add_argument("--no-truncation", action="store_true", help="skip the FNS / FNS++ truncation curve")
-    ap.add_argument("--no-direct", action="store_true", help="skip the pass with the DF-direct ladder")
+    ap.add_argument("--no-ladder-modes", action="store_true",
+                    help="skip the passes with the DF-direct and the triangle-stored ladder")
     ap.add_argument("--gemm-probe", action="store_true",
                     help="only launch the o=20, v=150 ladder GEMM (48 right-hand sides, FP32 3M, 64 x 64 tile) "
                          "three times, for hardware counter runs")
@@ -487,26 +488,32 @@ def main():
                              "alpha_rel_diff_vs_eq35": float(np.abs(r36["alpha"] - last["alpha"]).max()
                                                              / np.abs(last["alpha"]).max())}
         print(f"[bench] eq36 route: {d36:.1f} s", file=sys.stderr, flush=True)
-    if not args.no_direct:
-        # the same mixed pass without a resident vvvv matrix (rebuilt from the
-        # DF factors in every ladder contraction)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        rd = run_pass(lrcc, inp, "mixed", args.tol, timing=True, dev_in=dev_in, ladder_direct=True)
-        torch.cuda.synchronize()
-        dd = time.perf_counter() - t1
-        ld = rd["ladder"]
+    if not args.no_ladder_modes:
+        # the same mixed pass without the full resident vvvv matrix: rebuilt
+        # from the DF factors in every ladder contraction ("direct"), or held
+        # as its upper triangle in row blocks ("triangle")
         nr = 3 * len(inp.omegas)
-        out["ladder_direct"] = {
-            "sigma_evals_per_s": rd["sigma_evals"] / dd, "seconds": dd,
-            "ladder_ms": ld[0], "ladder_launches": ld[1],
-            "alpha_rel_diff_vs_resident_w": float(np.abs(rd["alpha"] - last["alpha"]).max()
+        out["ladder_storage"] = {}
+        for mode in ("direct", "triangle"):
+            run_pass(lrcc, inp, "mixed", args.tol, dev_in=dev_in, ladder=mode)  # warm-up: tiles of the new shapes
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rd = run_pass(lrcc, inp, "mixed", args.tol, timing=True, dev_in=dev_in, ladder=mode)
+            torch.cuda.synchronize()
+            dd = time.perf_counter() - t1
+            ld = rd["ladder"]
+            out["ladder_storage"][mode] = {
+                "sigma_evals_per_s": rd["sigma_evals"] / dd, "seconds": dd,
+                "ladder_ms": ld[0], "ladder_launches": ld[1],
+                "alpha_rel_diff_vs_full_w": float(np.abs(rd["alpha"] - last["alpha"]).max()
                                                   / np.abs(last["alpha"]).max()),
-            "workspace_estimate_gib": lrcc.workspace_bytes(inp.o, inp.v, inp.naux, nr, "mixed",
-                                                           ladder_direct=True) / 2**30,
-            "workspace_estimate_resident_w_gib": lrcc.workspace_bytes(inp.o, inp.v, inp.naux, nr, "mixed") / 2**30,
-            "note": "ladder_ms covers the ladder GEMMs only; the W rebuild GEMMs and packs count in seconds"}
-        print(f"[bench] DF-direct ladder pass: {dd:.1f} s", file=sys.stderr, flush=True)
+                "workspace_estimate_gib": lrcc.workspace_bytes(inp.o, inp.v, inp.naux, nr, "mixed",
+                                                               ladder=mode) / 2**30}
+            print(f"[bench] ladder storage {mode}: {dd:.1f} s", file=sys.stderr, flush=True)
+        out["ladder_storage"]["full_workspace_estimate_gib"] = lrcc.workspace_bytes(
+            inp.o, inp.v, inp.naux, nr, "mixed") / 2**30
+        out["ladder_storage"]["note"] = ("ladder_ms covers the ladder GEMMs (for 'direct' not the W rebuild); "
+                                         "W at this size is 1 GB (FP32) + 2 GB (FP64)")
     if not args.no_truncation:
         nw = len(inp.omegas)
         out["truncation_curve"] = truncation_curve(lrcc, inp, dev_in, last["alpha"], (0, nw // 2), args.tol)

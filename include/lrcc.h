@@ -84,12 +84,20 @@ typedef struct lrcc_config {
   int graphs;            /* 1: replay the Jacobian-product programs as HIP graphs (captured on the
                             second identical call, replayed from the third); default 1, or 0 when
                             the environment variable LRCC_GRAPHS is "0" */
-  int ladder_direct;     /* 1: keep no vvvv matrix W[P(a,b)][P(e,f)] = <ab||ef> in device memory
-                            (v^4/4 complex elements per precision); every ladder contraction
-                            rebuilds W's rows in chunks from the density-fitting factors,
-                            (ae|bf) = sum_Q B^Q_ae B^Q_bf, at naux v^4 / 2 extra complex MACs per
-                            ladder.  Results agree with the resident W to rounding.  Default 0. */
+  int ladder_mode;       /* storage of the vvvv matrix W[P(a,b)][P(e,f)] = <ab||ef> (v^4/4 complex
+                            elements per precision) that the ladder contracts with:
+                            LRCC_LADDER_FULL (default) the whole matrix;
+                            LRCC_LADDER_DIRECT none: every ladder contraction rebuilds W's rows in
+                            chunks from the density-fitting factors, (ae|bf) = sum_Q B^Q_ae
+                            B^Q_bf, at naux v^4 / 2 extra complex MACs per ladder;
+                            LRCC_LADDER_TRIANGLE the upper triangle in row blocks (about half);
+                            the lower part is read as conj(W^T), W being Hermitian.
+                            Results agree with the full W to rounding. */
 } lrcc_config;
+
+#define LRCC_LADDER_FULL 0
+#define LRCC_LADDER_DIRECT 1
+#define LRCC_LADDER_TRIANGLE 2
 
 typedef struct lrcc_stats {
   int iterations;        /* iterations taken */

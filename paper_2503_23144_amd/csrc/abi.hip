@@ -85,6 +85,8 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
     lrcc_default_config(&c);
     if (cfg) c = *cfg;
     LRCC_REQUIRE(c.precision == LRCC_FP64 || c.precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
+    LRCC_REQUIRE(c.ladder_mode >= LRCC_LADDER_FULL && c.ladder_mode <= LRCC_LADDER_TRIANGLE, LRCC_E_INVALID,
+                 "bad ladder_mode");
     LRCC_REQUIRE(c.tol_residual > 0 && c.maxit > 0 && c.diis_size >= 0 && c.diis_size <= 32 && c.rhs_chunk >= 0,
                  LRCC_E_INVALID, "bad tolerance, iteration limit, DIIS size or chunk");
     int ndev = 0;

@@ -73,6 +73,10 @@ struct Context {
 
   DevBuf B, fock, mu, D;     // FP64 inputs; D = real denominators [n]
   DevBuf L64, L32;           // DF-direct ladder: virtual-virtual block of B [naux][v][v] per precision
+  DevBuf Tri64, Tri32;       // Hermitian-triangle ladder: row blocks of W's upper triangle per precision
+  std::vector<int64_t> tri_bnd, tri_offs;  // block boundaries (over b) and offsets (complex elements)
+  template <typename T>
+  std::vector<typename Executor<T>::TriBlock> tri_blocks(const void* base) const;
   std::vector<double> eps;   // Fock diagonal (host)
   int ncomp = 0;
   bool have_fock = false;

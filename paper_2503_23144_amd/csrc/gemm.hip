@@ -1,6 +1,7 @@
 // Complex GEMM on CDNA4 matrix cores (gfx950).
 //
-//   C = alpha op(A) op(B) + beta C,  op = identity or transpose (no conjugate)
+//   C = alpha op(A) op(B) + beta C,  op = identity or transpose; B may be
+//   conjugated (its imaginary plane is negated when staged)
 //
 // FP64: complex product by 4 real products on v_mfma_f64_16x16x4_f64,
 //       (Ar + i Ai)(Br + i Bi) = (ArBr - AiBi) + i (ArBi + AiBr).
@@ -136,7 +137,7 @@ __global__ void __launch_bounds__(64 * NW) zgemm_kernel(int64_t M, int64_t N, in
                                                   const typename cpx<T>::type* __restrict__ A, int64_t lda,
                                                   const typename cpx<T>::type* __restrict__ B, int64_t ldb, T bre,
                                                   T bim, typename cpx<T>::type* __restrict__ C, OutMap om,
-                                                  int64_t kchunk, int64_t cstride) {
+                                                  int64_t kchunk, int64_t cstride, T bsgn) {
   using V2 = typename cpx<T>::type;
   constexpr int NT = 64 * NW;
   {
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(64 * NW) zgemm_kernel(int64_t M, int64_t N, in
       const int o = b_out + LB::STEP * q;
       const int x = TB ? TB_::at(o, b_in) : TB_::at(b_in, o);
       Bs[s][0][x] = rb[q].x;
-      Bs[s][1][x] = rb[q].y;
+      Bs[s][1][x] = rb[q].y * bsgn;  // bsgn = -1: conj(B)
     }
   };
 
@@ -380,7 +381,7 @@ __global__ void splitk_reduce_kernel(int64_t m, int64_t n, int splits, const typ
 template <typename T, int KIND, int BM, int BN, int WGM, int NW = 4>
 static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A, int64_t lda,
                const void* B, int64_t ldb, double bre, double bim, void* C, const OutMap& om, hipStream_t st,
-               int splits = 1, void* ws = nullptr) {
+               int splits = 1, void* ws = nullptr, bool conjb = false) {
   using V2 = typename cpx<T>::type;
   // deeper slabs for the FP32 128 x 128 tiles (one workgroup per CU: fewer
   // barriers and a longer prefetch distance)
@@ -402,7 +403,7 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 #define GO_(TA_, TB_)                                                                                        \
   hipLaunchKernelGGL((zgemm_kernel<T, TA_, TB_, KIND, BM, BN, WGM, BK, NW>), dim3((unsigned)nb, (unsigned)splits), dim3(NT), \
                      0, st, m, n, k, (T)ar, (T)ai, (const V2*)A, lda, (const V2*)B, ldb, (T)br, (T)bi, (V2*)out, mo,  \
-                     kchunk, cstride)
+                     kchunk, cstride, (T)(conjb ? -1.0 : 1.0))
   if (!ta && !tb)
     GO_(false, false);
   else if (!ta && tb)
@@ -434,15 +435,19 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 template <typename T, int KIND>
 static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
                      const void* A, int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C,
-                     const OutMap& om, hipStream_t st) {
+                     const OutMap& om, hipStream_t st, bool conjb) {
   if constexpr (sizeof(T) == 4) {  // 4 wavefronts of 64 x 64 FP64 would not fit the register file
-    if (cfgid == 2) return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
+    if (cfgid == 2)
+      return go<T, KIND, 128, 128, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr,
+                                      conjb);
   }
-  if (cfgid == 3) return go<T, KIND, 128, 128, 2, 8>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
+  if (cfgid == 3)
+    return go<T, KIND, 128, 128, 2, 8>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr,
+                                       conjb);
   if (cfgid >= 1)
-    go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
+    go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr, conjb);
   else
-    go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st);
+    go<T, KIND, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr, conjb);
 }
 
 namespace {
@@ -568,7 +573,7 @@ size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st, int kind, void* ws, size_t ws_bytes, const OutMap* omap) {
+                 hipStream_t st, int kind, void* ws, size_t ws_bytes, const OutMap* omap, bool conj_b) {
   if (m <= 0 || n <= 0) return;
   const OutMap om = omap ? *omap : OutMap::plain(ldc);
   {
@@ -579,9 +584,9 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
                 sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k,
                 splits);
       if (kind == 1)
-        go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws);
+        go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
       else
-        go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws);
+        go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
       return;
     }
   }
@@ -589,13 +594,13 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     if (probe) {  // plain layout into the scratch output
       const OutMap pm = OutMap::plain(n);
       if (kind == 1)
-        dispatch<T, 3>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st);
+        dispatch<T, 3>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st, conj_b);
       else
-        dispatch<T, 2>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st);
+        dispatch<T, 2>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, pm, st, conj_b);
     } else if (kind == 1) {
-      dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st);
+      dispatch<T, 1>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st, conj_b);
     } else {
-      dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st);
+      dispatch<T, 0>(cfg, ta, tb, m, n, k, are, aim, A, lda, B, ldb, br, bi, Cout, om, st, conj_b);
     }
   };
   int cfg = heuristic_tile<T>(m, n);
@@ -660,10 +665,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                   const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                  size_t, const OutMap*);
+                                  size_t, const OutMap*, bool);
 template void launch_gemm<float>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                 size_t, const OutMap*);
+                                 size_t, const OutMap*, bool);
 template size_t gemm_workspace_bytes<double>(int64_t, int64_t, int64_t);
 template size_t gemm_workspace_bytes<float>(int64_t, int64_t, int64_t);
 

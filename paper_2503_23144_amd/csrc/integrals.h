@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -15,6 +16,12 @@ void build_block(const void* Bdev, int64_t naux, int64_t o, int64_t v, const std
                  hipStream_t st);
 // W[P(a,b)][P(e,f)] = <ab||ef>, a<b, e<f (FP64).
 void build_packed_vvvv(const void* Bdev, int64_t naux, int64_t o, int64_t v, void* W, hipStream_t st);
+// Upper triangle of W in row blocks (FP64): block j holds rows [R(b_j),
+// R(b_{j+1})) and columns [R(b_j), V) of W, R(b) = b(b-1)/2, row length
+// V - R(b_j), at offs[j] complex elements into `dst`.  bnd: b_0 = 1 < ... <
+// b_nb = v.  Lvv: the virtual-virtual block of B, [naux][v][v].
+void build_vvvv_triangle(const void* Lvv, int64_t naux, int64_t v, const std::vector<int64_t>& bnd,
+                         const std::vector<int64_t>& offs, void* dst, hipStream_t st);
 // packed[x][y][P(e,f)] = full[x][y][e][f] for e < f (FP64).
 void pack_last_pair(const void* full, int64_t n0, int64_t n1, int64_t n, void* packed, hipStream_t st);
 

@@ -88,6 +88,34 @@ void build_packed_vvvv(const void* Bdev, int64_t naux, int64_t o, int64_t v, voi
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
+void build_vvvv_triangle(const void* Lvv, int64_t naux, int64_t v, const std::vector<int64_t>& bnd,
+                         const std::vector<int64_t>& offs, void* dst, hipStream_t st) {
+  const int64_t V = v * (v - 1) / 2;
+  auto R = [](int64_t b) { return b * (b - 1) / 2; };
+  DevTmp C(kChunkBytes), Wc(kChunkBytes);
+  for (size_t j = 0; j + 1 < bnd.size(); ++j) {
+    const int64_t r0 = R(bnd[j]), ld = V - r0;
+    for (int64_t c0 = bnd[j]; c0 < bnd[j + 1];) {
+      // rows of b in [c0, c1): the (ae|bf) block and the rows of W must fit a chunk
+      int64_t c1 = c0 + 1;
+      auto fits = [&](int64_t cc) {
+        return (size_t)((cc - c0) * v) * (size_t)(cc * v) * 16 <= kChunkBytes &&
+               (size_t)(R(cc) - R(c0)) * (size_t)V * 16 <= kChunkBytes;
+      };
+      LRCC_REQUIRE(fits(c1), LRCC_E_NOMEM, "vvvv row chunk exceeds budget (v too large)");
+      while (c1 < bnd[j + 1] && fits(c1 + 1)) ++c1;
+      // (ae|bf): rows (b, f) for b in [c0, c1), columns (a, e) for a < c1
+      launch_gemm<double>(true, false, (c1 - c0) * v, c1 * v, naux, 1.0, 0.0, (const char*)Lvv + c0 * v * 16, v * v,
+                          Lvv, v * v, 0.0, 0.0, C.p, c1 * v, st);
+      launch_pack_wrows<double>(v, c0, c1, C.p, Wc.p, st);
+      launch_copy_rows<double, double>(R(c1) - R(c0), ld, (const char*)Wc.p + r0 * 16, V,
+                                       (char*)dst + (offs[j] + (R(c0) - r0) * ld) * 16, ld, st);
+      c0 = c1;
+    }
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 void pack_last_pair(const void* full, int64_t n0, int64_t n1, int64_t n, void* packed, hipStream_t st) {
   // packed[x][y][P(e,f)] = full[x][y][e][f], e < f
   PackDesc d{};

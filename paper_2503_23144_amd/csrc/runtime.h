@@ -90,6 +90,14 @@ class Executor {
     dl_v_ = v;
   }
   static constexpr size_t kDirectChunkBytes = size_t(512) << 20;  // per scratch buffer of the rebuild
+  // Hermitian-triangle ladder: W held as row blocks, block j covering rows
+  // [r0, r1) and columns [r0, V) (row length V - r0, precision T, owned by
+  // the caller); the entries left of each block follow from W = W^H.
+  struct TriBlock {
+    int64_t r0, r1;
+    const void* p;
+  };
+  void set_triangle_ladder(const std::vector<TriBlock>& blocks) { tri_ = blocks; }
 
   // HIP graph replay.  With graphs on, a run whose program, batch and every
   // buffer address match an earlier (eager) run is captured into HIP graphs
@@ -103,7 +111,16 @@ class Executor {
   int64_t graph_captures() const { return captures_; }
 
  private:
+  struct LadderOperands {  // X[M][V] (contracted index last), output C[M][V]
+    const void* X;
+    void* C;
+    int64_t M, V, capX, capC;
+    bool over_col;  // C = X W^T (contraction over W's column index), else C = X W
+  };
+  LadderOperands ladder_operands(const Op& op);
   void ladder_direct(const Op& op);
+  void ladder_triangle(const Op& op);
+  std::vector<TriBlock> tri_;
   const void* dl_L_ = nullptr;
   int64_t dl_naux_ = 0, dl_v_ = 0;
   struct GemmArgs {
@@ -122,6 +139,7 @@ class Executor {
     size_t wsb;
     OutMap om;  // output layout when mapped
     bool mapped;
+    bool conjb;  // use conj(B)
   };
   struct RunKey {
     const OpList* ops;
@@ -166,7 +184,7 @@ class Executor {
   std::string letters(int id, const std::string& idx) const;
   void gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
             int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C, int64_t ldc,
-            int64_t capC, bool ladder, const OutMap* om = nullptr);
+            int64_t capC, bool ladder, const OutMap* om = nullptr, bool conjb = false);
   bool output_map(const std::string& Mc, const std::string& Nc, const std::string& cl, OutMap& om) const;
   int cached_permute(int id, const std::string& src, const std::string& dst, const void* p, int64_t cap);
   static constexpr int kPermSlot = 5;

@@ -281,7 +281,7 @@ void Executor<T>::permute_into(const void* src, int64_t src_cap, const std::stri
 template <typename T>
 void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double are, double aim, const void* A,
                        int64_t lda, int64_t capA, const void* B, int64_t ldb, int64_t capB, double bre, void* C,
-                       int64_t ldc, int64_t capC, bool ladder, const OutMap* om) {
+                       int64_t ldc, int64_t capC, bool ladder, const OutMap* om, bool conjb) {
   if (M > 0 && N > 0 && K > 0) {
     int64_t spanA = ta ? (K - 1) * lda + M : (M - 1) * lda + K;
     int64_t spanB = tb ? (N - 1) * ldb + K : (K - 1) * ldb + N;
@@ -293,7 +293,7 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
   }
   const size_t wsb = gemm_workspace_bytes<T>(M, N, K);
   void* ws = wsb ? scratch(4, wsb) : nullptr;
-  GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder, ws, wsb, OutMap(), om != nullptr};
+  GemmArgs g{ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, C, ldc, ladder, ws, wsb, OutMap(), om != nullptr, conjb};
   if (om) g.om = *om;
   if (capturing_) {
     if (timing_ && ladder) {  // leave the graph: the ladder is timed between segments
@@ -302,7 +302,8 @@ void Executor<T>::gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double
       launch_timed(g);
       HIP_CHECK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
     } else {
-      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0, ws, wsb, om);
+      launch_gemm<T>(ta, tb, M, N, K, are, aim, A, lda, B, ldb, bre, 0.0, C, ldc, st_, ladder ? 1 : 0, ws, wsb, om,
+                     conjb);
     }
     return;
   }
@@ -317,7 +318,7 @@ void Executor<T>::launch_timed(const GemmArgs& g) {
     HIP_CHECK(hipEventRecord(e0, st_));
   }
   launch_gemm<T>(g.ta, g.tb, g.M, g.N, g.K, g.are, g.aim, g.A, g.lda, g.B, g.ldb, g.bre, 0.0, g.C, g.ldc, st_,
-                 g.ladder ? 1 : 0, g.ws, g.wsb, g.mapped ? &g.om : nullptr);
+                 g.ladder ? 1 : 0, g.ws, g.wsb, g.mapped ? &g.om : nullptr, g.conjb);
   if (timing_) {
     e1 = get_event();
     HIP_CHECK(hipEventRecord(e1, st_));
@@ -387,6 +388,7 @@ template <typename T>
 void Executor<T>::contract(const Op& op, int nb) {
   (void)nb;
   if (dl_L_ && (op.a == ladder_const || op.b == ladder_const)) return ladder_direct(op);
+  if (!tri_.empty() && (op.a == ladder_const || op.b == ladder_const)) return ladder_triangle(op);
   std::string a = letters(op.a, op.ai), b = letters(op.b, op.bi), c = letters(op.out, op.oi);
   const void* pa = ptr(op.a);
   const void* pb = ptr(op.b);
@@ -548,26 +550,40 @@ void Executor<T>::contract(const Op& op, int nb) {
 // columns R0..R1 of the output) or X[M][K=ab] W (over W's row index: the
 // chunk adds its K-range).  Extra work per ladder: naux v^4 / 2 complex MACs.
 template <typename T>
-void Executor<T>::ladder_direct(const Op& op) {
+typename Executor<T>::LadderOperands Executor<T>::ladder_operands(const Op& op) {
   const bool w_is_a = op.a == ladder_const;
   const int idx = w_is_a ? op.b : op.a;
   const std::string w = letters(ladder_const, w_is_a ? op.ai : op.bi), x = letters(idx, w_is_a ? op.bi : op.ai),
                     c = letters(op.out, op.oi);
-  LRCC_REQUIRE(w.size() == 2 && x.size() >= 2, LRCC_E_INTERNAL, "DF-direct ladder: unexpected operands");
+  LRCC_REQUIRE(w.size() == 2 && x.size() >= 2, LRCC_E_INTERNAL, "ladder: unexpected operands");
   const char kl = x.back();
   LRCC_REQUIRE(w.find(kl) != std::string::npos && c.find(kl) == std::string::npos, LRCC_E_INTERNAL,
-               "DF-direct ladder: operand X must end with the contracted index");
-  const bool over_col = w[1] == kl;  // X W^T (else X W)
+               "ladder: operand X must end with the contracted index");
+  LadderOperands L;
+  L.over_col = w[1] == kl;
   const std::string Mc = x.substr(0, x.size() - 1);
-  LRCC_REQUIRE(c == Mc + (over_col ? w[0] : w[1]), LRCC_E_INTERNAL, "DF-direct ladder: unsupported output order");
-  int64_t M = 1;
-  for (char ch : Mc) M *= ch == '#' ? g_nb : dim(ch);
-  const int64_t v = dl_v_, nq = dl_naux_, V = v * (v - 1) / 2;
-  LRCC_REQUIRE(dim(kl) == V && dim(over_col ? w[0] : w[1]) == V, LRCC_E_INTERNAL, "DF-direct ladder: sizes");
-  const void* X = ptr(idx);
-  void* C = ptr(op.out);
-  const int64_t capX = capacity(idx), capC = capacity(op.out), capL = nq * v * v;
-  LRCC_REQUIRE(M * V <= capX && M * V <= capC, LRCC_E_INTERNAL, "DF-direct ladder: operand larger than its buffer");
+  LRCC_REQUIRE(c == Mc + (L.over_col ? w[0] : w[1]), LRCC_E_INTERNAL, "ladder: unsupported output order");
+  L.M = 1;
+  for (char ch : Mc) L.M *= ch == '#' ? g_nb : dim(ch);
+  L.V = dim(kl);
+  LRCC_REQUIRE(dim(L.over_col ? w[0] : w[1]) == L.V, LRCC_E_INTERNAL, "ladder: sizes");
+  L.X = ptr(idx);
+  L.C = ptr(op.out);
+  L.capX = capacity(idx);
+  L.capC = capacity(op.out);
+  LRCC_REQUIRE(L.M * L.V <= L.capX && L.M * L.V <= L.capC, LRCC_E_INTERNAL, "ladder: operand larger than its buffer");
+  return L;
+}
+
+template <typename T>
+void Executor<T>::ladder_direct(const Op& op) {
+  const LadderOperands L = ladder_operands(op);
+  const bool over_col = L.over_col;
+  const int64_t M = L.M, v = dl_v_, nq = dl_naux_, V = v * (v - 1) / 2;
+  LRCC_REQUIRE(L.V == V, LRCC_E_INTERNAL, "DF-direct ladder: sizes");
+  const void* X = L.X;
+  void* C = L.C;
+  const int64_t capX = L.capX, capC = L.capC, capL = nq * v * v;
   const size_t es = 2 * sizeof(T);
   const size_t budget = kDirectChunkBytes;
   bool first = true;
@@ -594,6 +610,49 @@ void Executor<T>::ladder_direct(const Op& op) {
            (first && !op.acc) ? 0.0 : 1.0, C, V, capC, true);
     first = false;
     b0 = b1;
+  }
+}
+
+// Ladder contraction with W held as its upper triangle in row blocks
+// (block l: rows [r0, r1), columns [r0, V), S_l[i][c] = W[r0 + i][r0 + c]).
+// W = W^H gives the entries left of each block: W[n][k] = conj(W[k][n]).
+//   C = X W^T:  C[:, r0:r1]  = X[:, r0:] S_l^T              (every block first)
+//               C[:, r1:]   += X[:, r0:r1] conj(S_l[:, r1-r0:])
+//   C = X W:    C[:, r0:]   += X[:, r0:r1] S_l              (block 0 sets C)
+//               C[:, r0:r1] += X[:, r1:] conj(S_l[:, r1-r0:])^T
+template <typename T>
+void Executor<T>::ladder_triangle(const Op& op) {
+  const LadderOperands L = ladder_operands(op);
+  const int64_t M = L.M, V = L.V;
+  const size_t es = 2 * sizeof(T);
+  const double beta0 = op.acc ? 1.0 : 0.0;
+  LRCC_REQUIRE(!tri_.empty() && tri_.front().r0 == 0 && tri_.back().r1 == V, LRCC_E_INTERNAL,
+               "triangle ladder: blocks do not cover W");
+  if (L.over_col) {
+    for (const TriBlock& b : tri_) {
+      const int64_t ld = V - b.r0, nr = b.r1 - b.r0;
+      gemm(false, true, M, nr, V - b.r0, op.are, op.aim, (const char*)L.X + b.r0 * es, V, L.capX - b.r0, b.p, ld,
+           nr * ld, beta0, (char*)L.C + b.r0 * es, V, L.capC - b.r0, true);
+    }
+    for (const TriBlock& b : tri_) {
+      const int64_t ld = V - b.r0, nr = b.r1 - b.r0;
+      if (b.r1 == V) continue;
+      gemm(false, false, M, V - b.r1, nr, op.are, op.aim, (const char*)L.X + b.r0 * es, V, L.capX - b.r0,
+           (const char*)b.p + nr * es, ld, nr * ld - nr, 1.0, (char*)L.C + b.r1 * es, V, L.capC - b.r1, true,
+           nullptr, true);
+    }
+    return;
+  }
+  bool first = true;
+  for (const TriBlock& b : tri_) {
+    const int64_t ld = V - b.r0, nr = b.r1 - b.r0;
+    gemm(false, false, M, V - b.r0, nr, op.are, op.aim, (const char*)L.X + b.r0 * es, V, L.capX - b.r0, b.p, ld,
+         nr * ld, first ? beta0 : 1.0, (char*)L.C + b.r0 * es, V, L.capC - b.r0, true);
+    first = false;
+    if (b.r1 == V) continue;
+    gemm(false, true, M, nr, V - b.r1, op.are, op.aim, (const char*)L.X + b.r1 * es, V, L.capX - b.r1,
+         (const char*)b.p + nr * es, ld, nr * ld - nr, 1.0, (char*)L.C + b.r0 * es, V, L.capC - b.r0, true, nullptr,
+         true);
   }
 }
 

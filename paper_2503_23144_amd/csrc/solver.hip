@@ -74,11 +74,13 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   x64->set_graphs(cfg.graphs != 0);
   L64.release();
   L32.release();
-  if (cfg.ladder_direct) {  // W is never stored; the ladder rebuilds its rows from B_vv
+  Tri64.release();
+  Tri32.release();
+  if (cfg.ladder_mode != LRCC_LADDER_FULL) {  // the virtual-virtual block of B builds W's rows
     L64.ensure((size_t)naux * v * v * 16);
     launch_gather_block(naux, nmo, o, v, o, v, B.p, L64.p, st);
-    x64->set_direct_ladder(L64.p, naux, v);
   }
+  if (cfg.ladder_mode == LRCC_LADDER_DIRECT) x64->set_direct_ladder(L64.p, naux, v);
   build_integrals();
   have_fock = false;
   ncomp = 0;
@@ -87,11 +89,39 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
 
 void Context::build_integrals() {
   for (auto& b : kBlocks) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
-  if (!cfg.ladder_direct) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
+  if (cfg.ladder_mode == LRCC_LADDER_FULL) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
+  if (cfg.ladder_mode == LRCC_LADDER_TRIANGLE) {
+    // row blocks of about equal size (rows grow as b^2): b_j = 1 + (v - 1) sqrt(j / nb)
+    const int nb = (int)std::min<int64_t>(8, v - 1);
+    tri_bnd.assign(1, 1);
+    for (int j = 1; j <= nb; ++j) {
+      int64_t b = j == nb ? v : (int64_t)std::llround(1.0 + (double)(v - 1) * std::sqrt((double)j / nb));
+      b = std::min<int64_t>(v - (nb - j), std::max<int64_t>(b, tri_bnd.back() + 1));
+      tri_bnd.push_back(b);
+    }
+    const int64_t V = dims.V;
+    tri_offs.assign(1, 0);
+    for (size_t j = 0; j + 1 < tri_bnd.size(); ++j) {
+      const int64_t r0 = tri_bnd[j] * (tri_bnd[j] - 1) / 2, r1 = tri_bnd[j + 1] * (tri_bnd[j + 1] - 1) / 2;
+      tri_offs.push_back(tri_offs.back() + (r1 - r0) * (V - r0));
+    }
+    Tri64.ensure((size_t)tri_offs.back() * 16);
+    build_vvvv_triangle(L64.p, naux, v, tri_bnd, tri_offs, Tri64.p, st);
+    x64->set_triangle_ladder(tri_blocks<double>(Tri64.p));
+  }
   pack_last_pair(x64->ptr(P.m.find("govvv")), o, v, v, x64->ptr(P.m.find("govvp")), st);
   const double one[2] = {1.0, 0.0};
   HIP_CHECK(hipMemcpyAsync(x64->ptr(P.one), one, 16, hipMemcpyHostToDevice, st));
   sync();
+}
+
+template <typename T>
+std::vector<typename Executor<T>::TriBlock> Context::tri_blocks(const void* base) const {
+  std::vector<typename Executor<T>::TriBlock> out;
+  for (size_t j = 0; j + 1 < tri_bnd.size(); ++j)
+    out.push_back({tri_bnd[j] * (tri_bnd[j] - 1) / 2, tri_bnd[j + 1] * (tri_bnd[j + 1] - 1) / 2,
+                   (const char*)base + tri_offs[j] * 2 * sizeof(T)});
+  return out;
 }
 
 static void ensure_x32(Context& c) {
@@ -101,7 +131,7 @@ static void ensure_x32(Context& c) {
     const int W = c.P.m.find("W");
     for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
       Role r = c.P.m[(int)id].role;
-      if (c.cfg.ladder_direct && (int)id == W) continue;
+      if (c.cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == W) continue;
       if (r == Role::Const || r == Role::Scalar1 || r == Role::Fock) need += c.x64->elems((int)id, 1) * 8;
     }
     if ((double)dev_available() < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
@@ -112,14 +142,19 @@ static void ensure_x32(Context& c) {
   c.x32->set_graphs(c.cfg.graphs != 0);
   for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
     Role r = c.P.m[(int)id].role;
-    if (c.cfg.ladder_direct && (int)id == c.x32->ladder_const) continue;
+    if (c.cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == c.x32->ladder_const) continue;
     if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))
       launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
   }
-  if (c.cfg.ladder_direct) {
+  if (c.cfg.ladder_mode == LRCC_LADDER_DIRECT) {
     c.L32.ensure((size_t)c.naux * c.v * c.v * 8);
     launch_d2s(c.naux * c.v * c.v, c.L64.p, c.L32.p, c.st);
     c.x32->set_direct_ladder(c.L32.p, c.naux, c.v);
+  }
+  if (c.cfg.ladder_mode == LRCC_LADDER_TRIANGLE) {
+    c.Tri32.ensure((size_t)c.tri_offs.back() * 8);
+    launch_d2s(c.tri_offs.back(), c.Tri64.p, c.Tri32.p, c.st);
+    c.x32->set_triangle_ladder(c.tri_blocks<float>(c.Tri32.p));
   }
   if (c.have_fock) {
     launch_zero_diag<float>(c.x32->ptr(c.P.foo), c.o, c.st);
@@ -761,8 +796,10 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
   auto executor = [&](double elem, const std::vector<std::pair<const OpList*, int>>& runs) {
     double b = 0;
     for (size_t id = 0; id < m.tensors.size(); ++id)
-      if (!m.tensors[id].batched && !(cfg.ladder_direct && (int)id == m.find("W")))
+      if (!m.tensors[id].batched && !(cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == m.find("W")))
         b += elem * (double)tensor_elems(m, d, (int)id, 1);
+    if (cfg.ladder_mode == LRCC_LADDER_TRIANGLE)  // row blocks of the upper triangle: about (V^2 + V^2 / nb) / 2
+      b += elem * 0.5625 * (double)d.V * (double)d.V;
     std::vector<int64_t> pool;
     std::vector<char> pooled(m.tensors.size(), 0), used(m.tensors.size(), 0);
     int64_t big = 0;
@@ -782,7 +819,7 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
     for (size_t id = 0; id < m.tensors.size(); ++id)
       if (used[id] && !pooled[id]) b += elem * (double)tensor_elems(m, d, (int)id, nb);
     b += elem * 4.0 * (double)big;  // three permutation slots and one tile-timing output
-    if (cfg.ladder_direct) b += 2.0 * (double)Executor<double>::kDirectChunkBytes;  // W rebuild chunks
+    if (cfg.ladder_mode == LRCC_LADDER_DIRECT) b += 2.0 * (double)Executor<double>::kDirectChunkBytes;
     return b + 320.0 * (1 << 20);    // split-K partials (at most 256 MB) and small buffers
   };
   bytes += executor(16.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 3}, {&P.eta0, 1},

@@ -43,7 +43,7 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("graphs", ctypes.c_int), ("ladder_direct", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("ladder_mode", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -126,14 +126,17 @@ def build_info() -> str:
     return lib.lrcc_build_info().decode()
 
 
-def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder_direct=False):
+LADDER_FULL, LADDER_DIRECT, LADDER_TRIANGLE = 0, 1, 2
+
+
+def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full"):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
     lib.lrcc_default_config(ctypes.byref(cfg))
     cfg.precision = {"fp64": FP64, "mixed": MIXED}[precision]
     cfg.diis_size = diis
-    cfg.ladder_direct = int(ladder_direct)
+    cfg.ladder_mode = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}[ladder]
     return int(lib.lrcc_workspace_bytes(ctypes.byref(cfg), o, v, naux, nrhs))
 
 
@@ -177,7 +180,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True, graphs=None, ladder_direct=False):
+                 verbose=0, autotune=True, graphs=None, ladder="full"):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -194,7 +197,9 @@ class Context:
         cfg.verbose = verbose
         if graphs is not None:  # else the library default (LRCC_GRAPHS)
             cfg.graphs = int(graphs)
-        cfg.ladder_direct = int(ladder_direct)
+        # storage of the vvvv matrix: "full", "direct" (rebuilt from the DF
+        # factors in every ladder) or "triangle" (upper triangle only)
+        cfg.ladder_mode = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}[ladder]
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:

@@ -479,18 +479,20 @@ def test_c3_matches_stored_oracle():
 
 
 # ------------------------------------------------------------------ DF-direct ladder (no resident W)
+@pytest.mark.parametrize("mode", ["direct", "triangle"])
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
-def test_ladder_direct_matches_oracle(name, o, v, naux, scale, seed):
-    """With lrcc_config.ladder_direct the vvvv matrix is rebuilt from the DF
-    factors inside every ladder contraction (both the X W^T and the X W
-    forms): Omega, A X, X A and the FP64 alpha still match the oracle."""
+def test_ladder_storage_modes_match_oracle(name, o, v, naux, scale, seed, mode):
+    """Without a full resident vvvv matrix: rebuilt from the DF factors inside
+    every ladder contraction ("direct"), or held as its upper triangle in row
+    blocks with the rest read as conj(W^T) ("triangle"); both the X W^T and
+    the X W forms.  Omega, A X, X A and alpha still match the oracle."""
     from oracle.response import left_sigma, lr_ccsd, right_sigma
     inp = make_inputs(o, v, naux, seed=seed)
     inp.B = inp.B * scale
     P = _oracle_problem(inp)
     rng = np.random.default_rng(seed + 7)
     t = _rand(rng, P.lay.n, scale=0.05)
-    c = _ctx(inp, ladder_direct=True)
+    c = _ctx(inp, ladder=mode)
     assert _relerr(c.sigma("residual", t), P.omega(torch.as_tensor(t)).numpy()) < 1e-12
     c.set_amplitudes(_lrcc().AMP_T, t)
     X = _rand(rng, 2, P.lay.n)
@@ -503,7 +505,7 @@ def test_ladder_direct_matches_oracle(name, o, v, naux, scale, seed):
     omegas = [0.0, 0.11]
     ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
     for prec, tol in (("fp64", 1e-8), ("mixed", 1e-6)):
-        c = _ctx(inp, precision=prec, tol=1e-11 if prec == "fp64" else 1e-10, ladder_direct=True)
+        c = _ctx(inp, precision=prec, tol=1e-11 if prec == "fp64" else 1e-10, ladder=mode)
         e, _ = c.solve_ground()
         assert abs(e - ref.ecorr) < 1e-9 * abs(ref.ecorr)
         c.solve_lambda()
@@ -512,15 +514,16 @@ def test_ladder_direct_matches_oracle(name, o, v, naux, scale, seed):
         c.close()
 
 
-def test_ladder_direct_c3_products_match_stored_oracle():
-    """The DF-direct ladder at o=20, v=150, where the rebuild runs in several
-    row chunks: Omega, A X and X A at the probe vectors (in a 48-vector
-    batch) against the stored oracle entries, FP64 and mixed."""
+@pytest.mark.parametrize("mode", ["direct", "triangle"])
+def test_ladder_storage_modes_c3_match_stored_oracle(mode):
+    """The DF-direct ladder (several rebuild chunks) and the triangle ladder
+    (eight row blocks) at o=20, v=150: Omega, A X and X A at the probe vectors
+    (in a 48-vector batch) against the stored oracle entries, FP64 and mixed."""
     import os
     from paper_2503_23144_amd.synth import config_inputs, probe_vectors
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c3.npz"))
     inp = config_inputs("c3")
-    c = _ctx(inp, tol=1e-11, ladder_direct=True)
+    c = _ctx(inp, tol=1e-11, ladder=mode)
     t, X, idx = probe_vectors(c.n, int(ref["sig_seed"]))
     R = c.sigma("residual", t)
     assert _relerr(R[idx], ref["sig_residual"]) < 1e-12
