@@ -541,14 +541,9 @@ void Executor<T>::contract(const Op& op, int nb) {
   }
 }
 
-// Ladder contraction without a resident W (DF-direct).  W's rows P(a,b)
-// (b-major, so the rows of b in [b0, b1) are contiguous) are rebuilt in
-// chunks: one GEMM over the auxiliary index gives (ae|bf) for b in the
-// chunk and every a < b1, a pack kernel antisymmetrizes it into
-// W[P(a,b)][P(e,f)] = (ae|bf) - (af|be), and the ladder GEMM consumes the
-// rows: X[M][K=ef] W^T (contraction over W's column index: the chunk fills
-// columns R0..R1 of the output) or X[M][K=ab] W (over W's row index: the
-// chunk adds its K-range).  Extra work per ladder: naux v^4 / 2 complex MACs.
+// Operands of a ladder contraction: the other operand X (contracted index
+// last) and the output, both [M][V] row-major, and which index of W is
+// contracted.
 template <typename T>
 typename Executor<T>::LadderOperands Executor<T>::ladder_operands(const Op& op) {
   const bool w_is_a = op.a == ladder_const;
@@ -575,6 +570,14 @@ typename Executor<T>::LadderOperands Executor<T>::ladder_operands(const Op& op) 
   return L;
 }
 
+// Ladder contraction without a resident W (DF-direct).  W's rows P(a,b)
+// (b-major, so the rows of b in [b0, b1) are contiguous) are rebuilt in
+// chunks: one GEMM over the auxiliary index gives (ae|bf) for b in the
+// chunk and every a < b1, a pack kernel antisymmetrizes it into
+// W[P(a,b)][P(e,f)] = (ae|bf) - (af|be), and the ladder GEMM consumes the
+// rows: X[M][K=ef] W^T (contraction over W's column index: the chunk fills
+// columns R0..R1 of the output) or X[M][K=ab] W (over W's row index: the
+// chunk adds its K-range).  Extra work per ladder: naux v^4 / 2 complex MACs.
 template <typename T>
 void Executor<T>::ladder_direct(const Op& op) {
   const LadderOperands L = ladder_operands(op);
