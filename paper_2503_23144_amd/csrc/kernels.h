@@ -159,6 +159,9 @@ void launch_pack_vvvv(int64_t v, int64_t a0, int64_t a1, int64_t b0, const void*
 // (row length b1*v).
 template <typename T>
 void launch_pack_wrows(int64_t v, int64_t b0, int64_t b1, const void* C, void* Wc, hipStream_t st);
+// part[2b], part[2b+1] (b < nparts): maxima of |X[q][p][r] - conj X[q][r][p]|
+// and of |X[q][p][r]| over nq complex FP64 n x n matrices, per block b
+void launch_herm_defect(int64_t nq, int64_t n, const void* X, void* part, int nparts, hipStream_t st);
 // dst[x][p][r] = src[x][p0 + p][r0 + r] (sub-block gather), p < np, r < nr
 void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
                          const void* src, void* dst, hipStream_t st);

@@ -648,6 +648,40 @@ void launch_pack_wrows(int64_t v, int64_t b0, int64_t b1, const void* C, void* W
   LAUNCH_CHECK();
 }
 
+// Per-block maxima of |X[q][p][r] - conj X[q][r][p]| and |X[q][p][r]| over
+// nq square n x n complex matrices (Hermiticity check of the DF factors).
+__global__ void __launch_bounds__(256) herm_defect_kernel(int64_t nq, int64_t n, const double2* __restrict__ X,
+                                                          double* __restrict__ part) {
+  const int64_t total = nq * n * n;
+  double dmax = 0, amax = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i % n, t = i / n, p = t % n, q = t / n;
+    const double2 x = X[i], y = X[(q * n + r) * n + p];
+    dmax = fmax(dmax, hypot(x.x - y.x, x.y + y.y));
+    amax = fmax(amax, hypot(x.x, x.y));
+  }
+  __shared__ double sd[256], sa[256];
+  sd[threadIdx.x] = dmax;
+  sa[threadIdx.x] = amax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+      sa[threadIdx.x] = fmax(sa[threadIdx.x], sa[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sd[0];
+    part[2 * blockIdx.x + 1] = sa[0];
+  }
+}
+
+void launch_herm_defect(int64_t nq, int64_t n, const void* X, void* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(herm_defect_kernel, dim3(nparts), dim3(256), 0, st, nq, n, (const double2*)X, (double*)part);
+  LAUNCH_CHECK();
+}
+
 __global__ void gather_block_kernel(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int64_t r0, int64_t nr,
                                     const double2* __restrict__ src, double2* __restrict__ dst) {
   int64_t total = naux * np * nr;

@@ -400,9 +400,9 @@ void Executor<T>::contract(const Op& op, int nb) {
     return p;
   };
   bool ladder = (op.a == ladder_const || op.b == ladder_const);
-  int ida = op.a;
+  int ida = op.a, idb = op.b;
   if (m_[op.b].batched && !m_[op.a].batched) {
-    ida = op.b;
+    std::swap(ida, idb);
     std::swap(a, b);
     std::swap(pa, pb);
     std::swap(ca, cb);
@@ -450,6 +450,7 @@ void Executor<T>::contract(const Op& op, int nb) {
 
   bool direct = (c == Mc + Nc);
   if (!direct && c == Nc + Mc && a.find('#') == std::string::npos) {
+    std::swap(ida, idb);
     std::swap(a, b);
     std::swap(pa, pb);
     std::swap(ca, cb);
@@ -498,10 +499,18 @@ void Executor<T>::contract(const Op& op, int nb) {
   }
   // FP32 GEMMs run 3-7 % faster with B stored [N][K] (measured on the ring
   // and ladder shapes), so an unbatched B in [K][N] order is transposed
-  // once when the product is large enough to repay the copy.
+  // once when the product is large enough to repay the copy.  The vvvv
+  // matrix needs no copy: it is Hermitian (W[x][y] = conj W[y][x], the DF
+  // factors being Hermitian), so its [K][N] use is conj of its [N][K] use.
+  const bool w_conj = sizeof(T) == 4 && idb == ladder_const && b == Kx + Nc && Ns == Ks;
   const bool b_to_nt = sizeof(T) == 4 && b == Kx + Nc && b.find('#') == std::string::npos && !ladder &&
                        Ms >= 16384 && Ns >= 64 && Ks >= 64;
-  if (b == Kx + Nc && !b_to_nt) {
+  bool conjb = false;
+  if (w_conj) {
+    tb = true;
+    ldb = Ks;
+    conjb = true;
+  } else if (b == Kx + Nc && !b_to_nt) {
     tb = false;
     ldb = Ns;
   } else if (b_to_nt) {
@@ -531,12 +540,15 @@ void Executor<T>::contract(const Op& op, int nb) {
   }
   OutMap om;
   if (direct) {
-    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder);
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder,
+         nullptr, conjb);
   } else if (output_map(Mc, Nc, c, om)) {  // the epilogue writes straight into c's index order
-    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder, &om);
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, acc ? 1.0 : 0.0, pc, Ns, cc, ladder, &om,
+         conjb);
   } else {
     void* t = scratch(2, (size_t)Ms * Ns * sizeof(T) * 2);
-    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, 0.0, t, Ns, scratch_elems(2), ladder);
+    gemm(ta, tb, Ms, Ns, Ks, op.are, op.aim, A, lda, capA, B, ldb, capB, 0.0, t, Ns, scratch_elems(2), ladder,
+         nullptr, conjb);
     permute_into(t, scratch_elems(2), Mc + Nc, pc, cc, c, 1, 0, acc ? 1 : 0, 0);
   }
 }

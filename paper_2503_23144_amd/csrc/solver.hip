@@ -68,6 +68,24 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   n = n1 + n2;
   B.ensure(naux * nmo * nmo * 16);
   copy_in(B.p, Bp, naux * nmo * nmo * 16, where, st);
+  {  // the method (and the ladder's use of W = W^H) needs B^Q Hermitian for every Q
+    constexpr int kParts = 1024;
+    DevBuf part;
+    part.ensure(2 * kParts * 8);
+    launch_herm_defect(naux, nmo, B.p, part.p, kParts, st);
+    std::vector<double> h(2 * kParts);
+    HIP_CHECK(hipMemcpyAsync(h.data(), part.p, h.size() * 8, hipMemcpyDeviceToHost, st));
+    sync();
+    double dmax = 0, amax = 0;
+    for (int b = 0; b < kParts; ++b) dmax = std::max(dmax, h[2 * b]), amax = std::max(amax, h[2 * b + 1]);
+    if (!(dmax <= 1e-10 * std::max(amax, 1e-300))) {
+      o = v = naux = nmo = n1 = n2 = n = 0;  // nothing loaded
+      have_fock = false;
+      ncomp = 0;
+      reset_solutions();
+      throw Error(LRCC_E_INVALID, "density-fitting factors are not Hermitian (B[Q][p][r] != conj B[Q][r][p])");
+    }
+  }
   x64.reset(new Executor<double>(P.m, dims, st));
   x64->ladder_const = P.m.find("W");
   x64->set_timing(timing);

@@ -638,6 +638,10 @@ def test_error_codes_and_solve_statistics():
     c = lrcc.Context(tol=1e-10)
     assert code(lambda: c.solve_ground()) == lrcc.E_STATE          # nothing loaded
     assert code(lambda: c.load_df(1, 9, inp.B)) == lrcc.E_INVALID  # nocc < 2
+    badB = inp.B.copy()
+    badB[1, 0, 2] += 0.01  # B^Q not Hermitian
+    assert code(lambda: c.load_df(inp.o, inp.v, badB)) == lrcc.E_INVALID
+    assert code(lambda: c.solve_ground()) == lrcc.E_STATE          # the failed load left nothing loaded
     c.load_df(inp.o, inp.v, inp.B)
     bad = inp.fock.copy()
     bad[0, 1] = 0.3  # not Hermitian
