@@ -43,10 +43,10 @@ def host_info():
 
 def gemm_source_hash():
     """First 16 hex digits of the SHA-256 of the GEMM kernel's sources
-    (gemm.hip, then kernels.h, which holds the epilogue's address maps)."""
+    (gemm.hip, then outmap.h, the epilogue's address maps)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("gemm.hip", "kernels.h"):
+    for f in ("gemm.hip", "outmap.h"):
         h.update(open(os.path.join(ROOT, "paper_2503_23144_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
