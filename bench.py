@@ -289,6 +289,25 @@ def _product_rates(lrcc, inp, nvec, graphs, stream, min_s=0.5):
             rates[label] = k * nb / (time.perf_counter() - t0)
             print(f"[bench]   o={inp.o} v={inp.v} {label}{'' if graphs else ' (no graphs)'}: {rates[label]:.4g} /s",
                   file=sys.stderr, flush=True)
+        if graphs:
+            # parity at this size by properties that hold at any size, in the
+            # batched launch configuration timed above: the adjoint identity
+            # u.(A v) = (u A).v in FP64, and the mixed product against FP64
+            c.sigma("right", X, precision="fp64", out=out)
+            r64 = out[:2].clone()
+            c.sigma("right", X, precision="mixed", out=out)
+            r32 = out[:2].clone()
+            lt = torch.empty_like(X[:1])
+            c.sigma("left", X[1:2], precision="fp64", out=lt)
+            stream.synchronize()
+            lhs, rhs = complex((X[1] * r64[0]).sum()), complex((lt[0] * X[0]).sum())
+            rates["check_adjoint_identity_rel"] = abs(lhs - rhs) / abs(lhs)
+            rates["check_mixed_vs_fp64_rel"] = float((r32 - r64).abs().max() / r64.abs().max())
+            print(f"[bench]   o={inp.o} v={inp.v} checks: adjoint identity {rates['check_adjoint_identity_rel']:.1e}, "
+                  f"mixed vs FP64 {rates['check_mixed_vs_fp64_rel']:.1e}", file=sys.stderr, flush=True)
+            assert rates["check_adjoint_identity_rel"] < 1e-10 and rates["check_mixed_vs_fp64_rel"] < 2e-5, \
+                "Jacobian products at this size fail their property checks"
+            del r64, r32, lt
         c.close()
     del X, out
     lrcc.trim_memory()
