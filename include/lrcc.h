@@ -215,7 +215,11 @@ int lrcc_set_amplitudes(lrcc_ctx *ctx, int which, int idx, const void *in, int w
    transa/transb: 0 = as stored, 1 = transposed (no conjugation).
    precision LRCC_FP64: 4 real products per complex product on FP64 MFMA;
    LRCC_MIXED: FP32 data, 3 real products (Gauss) on FP32 MFMA, FP32 accumulate.
-   alpha, beta: host complex {re, im}.  stream: hipStream_t or NULL. */
+   alpha, beta: host complex {re, im}.  stream: hipStream_t or NULL.
+   Returns LRCC_E_INVALID for a null pointer, a negative size, a leading
+   dimension shorter than a row or an unknown precision (message in
+   lrcc_last_error(NULL)); asynchronous on `stream` unless the product is
+   split over K, in which case it returns after the product is done. */
 int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k,
               const double alpha[2], const void *A, int64_t lda, const void *B, int64_t ldb,
               const double beta[2], void *C, int64_t ldc, void *stream);

@@ -358,6 +358,7 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
               void* stream) {
   try {
     LRCC_REQUIRE(alpha && beta && A && B && C, LRCC_E_INVALID, "null argument");
+    LRCC_REQUIRE(precision == LRCC_FP64 || precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
     LRCC_REQUIRE(m >= 0 && n >= 0 && k >= 0, LRCC_E_INVALID, "negative size");
     LRCC_REQUIRE(lda >= (transa ? m : k) && ldb >= (transb ? k : n) && ldc >= n, LRCC_E_INVALID, "leading dimension");
     // deep products with few output tiles are split over K into a temporary workspace

@@ -53,6 +53,37 @@ def test_create_without_device_fails_cleanly():
     assert lrcc.lib.lrcc_amplitude_length(None) == 0
 
 
+def test_argument_checks_come_before_any_device_work():
+    """Invalid arguments are rejected with LRCC_E_INVALID and a message
+    before the library touches a device, so these run on any host."""
+    lrcc = _lrcc()
+    lib = lrcc.lib
+    one = (ctypes.c_double * 2)(1.0, 0.0)
+    dummy = ctypes.c_void_p(64)  # never dereferenced: every call below fails its checks first
+    cases = [
+        (7, 0, 0, 4, 4, 4, 4, 4, 4),     # unknown precision
+        (lrcc.FP64, 0, 0, -1, 4, 4, 4, 4, 4),  # negative size
+        (lrcc.FP64, 0, 0, 4, 4, 8, 4, 4, 4),   # lda shorter than a row of A (k = 8)
+        (lrcc.MIXED, 0, 1, 4, 4, 8, 8, 4, 4),  # ldb shorter than a row of B^T (k = 8)
+        (lrcc.MIXED, 0, 0, 4, 8, 4, 4, 8, 4),  # ldc shorter than a row of C (n = 8)
+    ]
+    for prec, ta, tb, m, n, k, lda, ldb, ldc in cases:
+        rc = lib.lrcc_gemm(prec, ta, tb, m, n, k, one, dummy, lda, dummy, ldb, one, dummy, ldc, None)
+        assert rc == lrcc.E_INVALID, (prec, m, n, k, lda, ldb, ldc)
+        assert len(lib.lrcc_last_error(None)) > 0
+    assert lib.lrcc_gemm(lrcc.FP64, 0, 0, 4, 4, 4, one, None, 4, dummy, 4, one, dummy, 4, None) == lrcc.E_INVALID
+    assert lib.lrcc_gemm_set_tile(4) == lrcc.E_INVALID and lib.lrcc_gemm_set_tile(-2) == lrcc.E_INVALID
+    for field, bad in (("precision", 5), ("ladder_mode", 3), ("tol_residual", 0.0), ("maxit", 0),
+                       ("diis_size", 33), ("rhs_chunk", -1)):
+        c = lrcc.Config()
+        lib.lrcc_default_config(ctypes.byref(c))
+        setattr(c, field, bad)
+        h = ctypes.c_void_p()
+        assert lib.lrcc_create(ctypes.byref(h), ctypes.byref(c)) == lrcc.E_INVALID, field
+        assert h.value is None
+    assert lib.lrcc_set_workspace(None, dummy, 1 << 30) == lrcc.E_INVALID
+
+
 def test_program_text_is_well_formed():
     lrcc = _lrcc()
     for which in range(9):
