@@ -285,13 +285,14 @@ __global__ void __launch_bounds__(256) unpack_kernel(const typename cplx2<T>::ty
 
 // Unpack of the common layout: the packed tensor's last dim is a pair
 // (a < b) whose two full dims are the full tensor's last two, an n x n
-// row-major block per outer row.  A workgroup (32 x 8 threads) writes one
-// 32 x 32 tile of a block.  The packed entries P(a,b) = b(b-1)/2 + a run
-// along a, so a tile's a < b entries are staged in LDS as [b][a]: the packed
-// reads (along a) and the full writes (along b) are both coalesced.  The
-// a > b entries, -P(b,a) when the pair is antisymmetric (mode 1), run along b
-// and are read directly; the diagonal and, for mode 0, the a > b part are 0.
-constexpr int UT = 32;
+// row-major block per outer row.  A workgroup (32 x 8 threads) writes up to
+// TPB consecutive 32 x 32 tiles of one outer row's block.  The packed entries
+// P(a,b) = b(b-1)/2 + a run along a, so a tile's a < b entries are staged in
+// LDS as [b][a]: the packed reads (along a) and the full writes (along b) are
+// both coalesced.  The a > b entries, -P(b,a) when the pair is antisymmetric
+// (mode 1), run along b and are read directly; the diagonal and, for mode 0,
+// the a > b part are 0.
+constexpr int UT = 32, TPB = 4, PTPB = 1;  // tile edge; tiles per workgroup (unpack, pack)
 
 template <typename T, typename I>
 __global__ void __launch_bounds__(256) unpack_tail_pair_kernel(const typename cplx2<T>::type* __restrict__ packed,
@@ -299,45 +300,38 @@ __global__ void __launch_bounds__(256) unpack_tail_pair_kernel(const typename cp
                                                                PackDesc d, I rows, int n, int nt, T are, T aim,
                                                                int acc) {
   using C = typename cplx2<T>::type;
+  constexpr int NY = 256 / UT;
   __shared__ C tile[UT][UT + 1];
   const int in = d.rank - 1;
   const int mode = d.mode[in];
   const int tx = threadIdx.x % UT, ty = threadIdx.x / UT;
-  const int64_t per_row = (int64_t)nt * nt, ntiles = (int64_t)rows * per_row;
-  for (int64_t blk = blockIdx.x; blk < ntiles; blk += gridDim.x) {
-    const I r = (I)(blk / per_row);
-    const int t = (int)(blk % per_row), ta = t / nt, tb = t % nt;
-    // packed offset and sign of outer row r (outer full dims 0 .. frank-3)
+  const int tiles = nt * nt, chunks = (tiles + TPB - 1) / TPB;
+  const int64_t nblk = (int64_t)rows * chunks;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const I r = (I)(blk / chunks);
+    const int c = (int)(blk % chunks);
+    // packed offset and sign of outer row r, in one pass over the outer full
+    // dims (the second index of a pair is the dim right after its first)
     I rem = r;
-    int64_t pidx[kMaxRank], qidx[kMaxRank], plain[kMaxRank];
+    int64_t off = 0, qsec = 0;
+    T s = 1;
+    bool zero = false;
     for (int k = d.frank - 3; k >= 0; --k) {
       const I dk = (I)d.fdims[k];
       const I q = rem / dk;
       const int64_t i = (int64_t)(rem - q * dk);
       rem = q;
       const int j = d.fmap[k];
-      if (d.fsec[k] < 0)
-        plain[j] = i;
-      else if (d.fsec[k] == 0)
-        pidx[j] = i;
-      else
-        qidx[j] = i;
-    }
-    int64_t off = 0;
-    T s = 1;
-    bool zero = false;
-    for (int j = 0; j < in; ++j) {
-      if (!d.pair[j]) {
-        off += plain[j] * d.pstride[j];
-        continue;
-      }
-      const int64_t p = pidx[j], q = qidx[j];
-      if (p == q) {
+      if (d.fsec[k] < 0) {
+        off += i * d.pstride[j];
+      } else if (d.fsec[k] == 1) {
+        qsec = i;
+      } else if (i == qsec) {
         zero = true;
-      } else if (p < q) {
-        off += (q * (q - 1) / 2 + p) * d.pstride[j];
+      } else if (i < qsec) {
+        off += (qsec * (qsec - 1) / 2 + i) * d.pstride[j];
       } else if (d.mode[j]) {
-        off += (p * (p - 1) / 2 + q) * d.pstride[j];
+        off += (i * (i - 1) / 2 + qsec) * d.pstride[j];
         s = -s;
       } else {
         zero = true;
@@ -345,51 +339,55 @@ __global__ void __launch_bounds__(256) unpack_tail_pair_kernel(const typename cp
     }
     const C* prow = packed + off;
     C* frow = full + (int64_t)r * n * n;
-    const int a0 = ta * UT, b0 = tb * UT;
-    if (!zero && ta <= tb) {
-      for (int y = ty; y < UT; y += 256 / UT) {
-        const int b = b0 + y, a = a0 + tx;
-        if (b < n && a < b) tile[y][tx] = prow[(int64_t)b * (b - 1) / 2 + a];
+    const int t1 = min(tiles, (c + 1) * TPB);
+    for (int t = c * TPB; t < t1; ++t) {
+      const int ta = t / nt, tb = t % nt;
+      const int a0 = ta * UT, b0 = tb * UT;
+      if (!zero && ta <= tb) {
+        for (int y = ty; y < UT; y += NY) {
+          const int b = b0 + y, a = a0 + tx;
+          if (b < n && a < b) tile[y][tx] = prow[(int64_t)b * (b - 1) / 2 + a];
+        }
       }
-    }
-    __syncthreads();
-    for (int y = ty; y < UT; y += 256 / UT) {
-      const int a = a0 + y, b = b0 + tx;
-      if (a < n && b < n) {
-        T re = 0, im = 0;
-        if (!zero && a != b && (a < b || mode)) {
-          C x;
-          T sg = s;
-          if (a < b) {
-            x = tile[b - b0][a - a0];
-          } else {
-            x = prow[(int64_t)a * (a - 1) / 2 + b];
-            sg = -sg;
+      __syncthreads();
+      for (int y = ty; y < UT; y += NY) {
+        const int a = a0 + y, b = b0 + tx;
+        if (a < n && b < n) {
+          T re = 0, im = 0;
+          if (!zero && a != b && (a < b || mode)) {
+            C x;
+            T sg = s;
+            if (a < b) {
+              x = tile[b - b0][a - a0];
+            } else {
+              x = prow[(int64_t)a * (a - 1) / 2 + b];
+              sg = -sg;
+            }
+            re = sg * (are * x.x - aim * x.y);
+            im = sg * (are * x.y + aim * x.x);
           }
-          re = sg * (are * x.x - aim * x.y);
-          im = sg * (are * x.y + aim * x.x);
+          C* f = frow + (int64_t)a * n + b;
+          if (acc) {
+            const C yv = *f;
+            re += yv.x;
+            im += yv.y;
+          }
+          *f = C{re, im};
         }
-        C* f = frow + (int64_t)a * n + b;
-        if (acc) {
-          const C yv = *f;
-          re += yv.x;
-          im += yv.y;
-        }
-        *f = C{re, im};
       }
+      __syncthreads();  // the tile is rewritten for the next one
     }
-    __syncthreads();  // the tile is rewritten for the next block
   }
 }
 
 // Pack of the same layout (the last packed dim a pair (a < b) over the full
-// tensor's last two dims, fp = n, fq = 1).  A workgroup forms the packed
-// entries of one 32 x 32 tile ta <= tb of the n x n block of one outer
-// packed row: for each combination of outer pair orders (summed in the order
-// of pack_kernel), full[a][b] is staged in LDS as [a][b] (read along b) and
-// read back along a, and -full[b][a] (mode 1) is read along a directly, so
-// the packed writes P(a,b) = b(b-1)/2 + a (along a) and every read are
-// coalesced.
+// tensor's last two dims, fp = n, fq = 1; at most two outer pairs).  A
+// workgroup forms the packed entries of up to PTPB tiles ta <= tb of the n x n
+// block of one outer packed row.  For each order of the outer pairs (summed
+// in the order of pack_kernel), full[a][b] is staged in LDS as [a][b] (read
+// along b) and read back along a, and -full[b][a] (mode 1) is read along a
+// directly, so the packed writes P(a,b) = b(b-1)/2 + a (along a) and every
+// read are coalesced.
 template <typename T, typename I>
 __global__ void __launch_bounds__(256) pack_tail_pair_kernel(const typename cplx2<T>::type* __restrict__ full,
                                                              typename cplx2<T>::type* __restrict__ packed,
@@ -401,22 +399,15 @@ __global__ void __launch_bounds__(256) pack_tail_pair_kernel(const typename cplx
   const int in = d.rank - 1;
   const int mode = d.mode[in];
   const int tx = threadIdx.x % UT, ty = threadIdx.x / UT;
-  const int64_t per_row = (int64_t)nt * (nt + 1) / 2, ntiles = (int64_t)rows * per_row;
-  const int64_t npk = (int64_t)n * (n - 1) / 2;
-  for (int64_t blk = blockIdx.x; blk < ntiles; blk += gridDim.x) {
-    const I r = (I)(blk / per_row);
-    // tile t -> (ta <= tb), t = tb (tb + 1) / 2 + ta
-    const int64_t t = blk % per_row;
-    int tb = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while ((int64_t)tb * (tb + 1) / 2 > t) --tb;
-    while ((int64_t)(tb + 1) * (tb + 2) / 2 <= t) ++tb;
-    const int ta = (int)(t - (int64_t)tb * (tb + 1) / 2);
-    // outer packed row r: plain offset and the two orders of each outer pair
+  const int tiles = nt * (nt + 1) / 2, chunks = (tiles + PTPB - 1) / PTPB;
+  const int64_t npk = (int64_t)n * (n - 1) / 2, nblk = (int64_t)rows * chunks;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const I r = (I)(blk / chunks);
+    const int c = (int)(blk % chunks);
+    // outer packed row r: plain offset and both orders of each outer pair
     I rem = r;
-    int64_t off = 0;
-    int np = 0;
-    int64_t o1[kMaxRank], o2[kMaxRank];
-    int md[kMaxRank];
+    int64_t off = 0, o1a = 0, o2a = 0, o1b = 0, o2b = 0;
+    int np = 0, mda = 0, mdb = 0;
     for (int k = in - 1; k >= 0; --k) {
       const I dk = (I)d.dims[k];
       const I q = rem / dk;
@@ -425,67 +416,79 @@ __global__ void __launch_bounds__(256) pack_tail_pair_kernel(const typename cplx
       if (d.pair[k]) {
         int64_t pa, pb;
         decode_pair(i, pa, pb);
-        o1[np] = pa * d.fp[k] + pb * d.fq[k];
-        o2[np] = pb * d.fp[k] + pa * d.fq[k];
-        md[np] = d.mode[k];
+        const int64_t x1 = pa * d.fp[k] + pb * d.fq[k], x2 = pb * d.fp[k] + pa * d.fq[k];
+        if (np == 0) {
+          o1a = x1, o2a = x2, mda = d.mode[k];
+        } else {
+          o1b = x1, o2b = x2, mdb = d.mode[k];
+        }
         ++np;
       } else {
         off += i * d.fstride[k];
       }
     }
-    const int a0 = ta * UT, b0 = tb * UT;
-    T re[EPT], im[EPT];
+    // order mo: bit 0 swaps the first outer pair found (innermost), bit 1 the second
+    int64_t co[4];
+    T cs[4];
+    bool cok[4];
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) re[e] = im[e] = 0;
-    for (int mo = 0; mo < (1 << np); ++mo) {
-      bool ok = true;
-      int64_t o = off;
-      T s = 1;
-      for (int j = 0; j < np; ++j) {
-        if (mo & (1 << j)) {
-          if (!md[j]) ok = false;
-          o += o2[j];
-          s = -s;
-        } else {
-          o += o1[j];
+    for (int mo = 0; mo < 4; ++mo) {
+      const bool ba = (mo & 1) != 0, bb = (mo & 2) != 0;
+      cok[mo] = mo < (1 << np) && (!ba || mda) && (!bb || mdb);
+      co[mo] = off + (np > 0 ? (ba ? o2a : o1a) : 0) + (np > 1 ? (bb ? o2b : o1b) : 0);
+      cs[mo] = (ba != bb) ? T(-1) : T(1);
+    }
+    C* prow = packed + (int64_t)r * npk;
+    const int t1 = min(tiles, (c + 1) * PTPB);
+    for (int t = c * PTPB; t < t1; ++t) {
+      // tile t -> (ta <= tb), t = tb (tb + 1) / 2 + ta
+      int tb = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while (tb * (tb + 1) / 2 > t) --tb;
+      while ((tb + 1) * (tb + 2) / 2 <= t) ++tb;
+      const int ta = t - tb * (tb + 1) / 2;
+      const int a0 = ta * UT, b0 = tb * UT;
+      T re[EPT], im[EPT];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) re[e] = im[e] = 0;
+#pragma unroll
+      for (int mo = 0; mo < 4; ++mo) {
+        if (!cok[mo]) continue;  // uniform over the workgroup
+        const C* fb = full + co[mo];
+        const T sm = cs[mo];
+        for (int y = ty; y < UT; y += NY) {  // full[a][b] for a = a0 + y, along b
+          const int a = a0 + y, b = b0 + tx;
+          if (a < n && b < n) tile[y][tx] = fb[(int64_t)a * n + b];
         }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int a = a0 + tx, b = b0 + ty + NY * e;
+          if (a < b && b < n) {
+            const C x = tile[tx][b - b0];
+            re[e] += sm * x.x;
+            im[e] += sm * x.y;
+            if (mode) {
+              const C z = fb[(int64_t)b * n + a];
+              re[e] += -sm * z.x;
+              im[e] += -sm * z.y;
+            }
+          }
+        }
+        __syncthreads();  // the tile is rewritten for the next order
       }
-      if (!ok) continue;  // uniform over the workgroup
-      const C* fb = full + o;
-      for (int y = ty; y < UT; y += NY) {  // full[a][b] for a = a0 + y, along b
-        const int a = a0 + y, b = b0 + tx;
-        if (a < n && b < n) tile[y][tx] = fb[(int64_t)a * n + b];
-      }
-      __syncthreads();
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int a = a0 + tx, b = b0 + ty + NY * e;
         if (a < b && b < n) {
-          const C x = tile[tx][b - b0];
-          re[e] += s * x.x;
-          im[e] += s * x.y;
-          if (mode) {
-            const C z = fb[(int64_t)b * n + a];
-            re[e] += -s * z.x;
-            im[e] += -s * z.y;
+          T rr = are * re[e] - aim * im[e], ii = are * im[e] + aim * re[e];
+          C* pp = prow + (int64_t)b * (b - 1) / 2 + a;
+          if (acc) {
+            const C yv = *pp;
+            rr += yv.x;
+            ii += yv.y;
           }
+          *pp = C{rr, ii};
         }
-      }
-      __syncthreads();  // the tile is rewritten for the next order
-    }
-    C* prow = packed + (int64_t)r * npk;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int a = a0 + tx, b = b0 + ty + NY * e;
-      if (a < b && b < n) {
-        T rr = are * re[e] - aim * im[e], ii = are * im[e] + aim * re[e];
-        C* pp = prow + (int64_t)b * (b - 1) / 2 + a;
-        if (acc) {
-          const C yv = *pp;
-          rr += yv.x;
-          ii += yv.y;
-        }
-        *pp = C{rr, ii};
       }
     }
   }
@@ -499,10 +502,13 @@ void launch_pack(const void* full, void* packed, const PackDesc& d, double are, 
   if (total == 0) return;
   using C = typename cplx2<T>::type;
   const int in = d.rank - 1;
+  int outer_pairs = 0;
+  for (int k = 0; k < in; ++k) outer_pairs += d.pair[k] ? 1 : 0;
   if (in >= 0 && d.pair[in] && d.npair[in] >= 2 && d.npair[in] < 46341 && d.fp[in] == d.npair[in] &&
-      d.fq[in] == 1) {
+      d.fq[in] == 1 && outer_pairs <= 2) {
     const int64_t n = d.npair[in], rows = total / d.dims[in], nt = (n + UT - 1) / UT;
-    const int64_t blocks = std::min<int64_t>(rows * (nt * (nt + 1) / 2), int64_t(1) << 24);
+    const int64_t chunks = (nt * (nt + 1) / 2 + PTPB - 1) / PTPB;
+    const int64_t blocks = std::min<int64_t>(rows * chunks, int64_t(1) << 24);
     if (total < (int64_t(1) << 31))
       hipLaunchKernelGGL((pack_tail_pair_kernel<T, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, st,
                          (const C*)full, (C*)packed, d, (uint32_t)rows, (int)n, (int)nt, (T)are, (T)aim,
@@ -529,12 +535,16 @@ void launch_unpack(const void* packed, void* full, const PackDesc& d, double are
   if (total == 0) return;
   using C = typename cplx2<T>::type;
   const int in = d.rank - 1;
-  if (in >= 0 && d.frank >= 2 && d.pair[in] && d.fmap[d.frank - 2] == in && d.fsec[d.frank - 2] == 0 &&
+  // every pair's second full dim must follow its first (one-pass row decode)
+  bool adjacent = true;
+  for (int k = 0; k < d.frank; ++k)
+    if (d.fsec[k] == 0) adjacent = adjacent && k + 1 < d.frank && d.fsec[k + 1] == 1 && d.fmap[k + 1] == d.fmap[k];
+  if (in >= 0 && d.frank >= 2 && adjacent && d.pair[in] && d.fmap[d.frank - 2] == in && d.fsec[d.frank - 2] == 0 &&
       d.fmap[d.frank - 1] == in && d.fsec[d.frank - 1] == 1 && d.pstride[in] == 1) {
     const int64_t n = d.npair[in];
     if (n >= 2 && n < 46341 && d.fdims[d.frank - 2] == n && d.fdims[d.frank - 1] == n) {
       const int64_t rows = total / (n * n), nt = (n + UT - 1) / UT;
-      const int64_t blocks = std::min<int64_t>(rows * nt * nt, int64_t(1) << 24);
+      const int64_t blocks = std::min<int64_t>(rows * ((nt * nt + TPB - 1) / TPB), int64_t(1) << 24);
       if (total < (int64_t(1) << 31))
         hipLaunchKernelGGL((unpack_tail_pair_kernel<T, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, st,
                            (const C*)packed, (C*)full, d, (uint32_t)rows, (int)n, (int)nt, (T)are, (T)aim,
