@@ -226,11 +226,12 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
 
 /* Workgroup tile of every later unsplit GEMM launch, process-wide:
    -1 = automatic (the autotuner when a context enables it, else a size
-   heuristic); 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 with 4 wavefronts
-   (FP32 only; FP64 runs tile 1), 3 = 128 x 128 with 8 wavefronts.  Every
-   tile computes the same product (results agree to rounding); the choice
-   only changes speed.  Returns LRCC_E_INVALID outside -1..3.  The
-   environment variable LRCC_GEMM_TILE gives the initial value. */
+   heuristic; products at most 32 wide take tile 4); 0 = 64 x 64, 1 = 128 x
+   64, 2 = 128 x 128 with 4 wavefronts (FP32 only; FP64 runs tile 1), 3 =
+   128 x 128 with 8 wavefronts, 4 = 128 x 32.  Every tile computes the same
+   product (results agree to rounding); the choice only changes speed.
+   Products split over K ignore it.  Returns LRCC_E_INVALID outside -1..4.
+   The environment variable LRCC_GEMM_TILE gives the initial value. */
 int lrcc_gemm_set_tile(int tile);
 
 /* Text of the derived operation lists (host-only, no GPU needed):

@@ -384,8 +384,8 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
 }
 
 int lrcc_gemm_set_tile(int tile) {
-  if (tile < -1 || tile > 3) {
-    g_create_error = "tile must be -1..3";
+  if (tile < -1 || tile > 4) {
+    g_create_error = "tile must be -1..4";
     return LRCC_E_INVALID;
   }
   lrcc::set_gemm_tile(tile);

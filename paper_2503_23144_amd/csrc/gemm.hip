@@ -12,7 +12,9 @@
 //
 // Tiling: a workgroup of 4 wavefronts of 64 lanes (2 x 2) owns a BM x BN
 // tile of C (64 x 64, 128 x 64, or 128 x 128 for FP32), or 8 wavefronts
-// (2 x 4) own a 128 x 128 tile; the autotuner picks per shape.  Each
+// (2 x 4) own a 128 x 128 tile, or, for products at most 32 wide, 4
+// wavefronts stacked along M own a 128 x 32 tile; the autotuner picks per
+// shape.  Each
 // wavefront owns a block of 16 x 16 MFMA outputs.  K advances in 16-deep
 // slabs (32 for the FP32 128 x 128 tiles) staged in LDS as two real planes
 // (re, im; the Gauss sums are formed in registers) whose layout follows the
@@ -87,6 +89,8 @@ constexpr int PADR = 16;
 // fastest: 32 consecutive tiles on one XCD cover 8 x 4 tiles, so A and B
 // panels are both shared in that XCD's L2.
 constexpr int64_t GM = 8;
+// Products at most this wide (n) use the 128 x 32 tile.
+constexpr int64_t kNarrow = 32;
 __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& tm, int64_t& tn) {
   const int64_t total = nbm * nbn;
   int64_t id = bid;
@@ -426,7 +430,10 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 // ---------------------------------------------------------------- tile choice
 // Candidate workgroup tiles: 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 (FP32),
 // all with 4 wavefronts of (BM/2) x (BN/2); 3 = 128 x 128 with 8 wavefronts
-// of 64 x 32 (two wavefronts per SIMD where tile 2 has one).
+// of 64 x 32 (two wavefronts per SIMD where tile 2 has one); 4 = 128 x 32
+// with 4 wavefronts of 32 x 32 stacked along M, for products at most
+// kNarrow wide, where a 64-wide tile would spend most of its matrix-core
+// work on padding (N = 1 or o).
 // The autotuner times every candidate once per GEMM shape (into a scratch
 // output, so accumulating calls are not disturbed) and keeps the fastest;
 // without it a size heuristic decides.  Results can persist in a text cache
@@ -444,6 +451,9 @@ static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t 
   if (cfgid == 3)
     return go<T, KIND, 128, 128, 2, 8>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr,
                                        conjb);
+  if (cfgid == 4)
+    return go<T, KIND, 128, 32, 4>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr,
+                                   conjb);
   if (cfgid >= 1)
     go<T, KIND, 128, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, 1, nullptr, conjb);
   else
@@ -504,7 +514,9 @@ template <typename T>
 static int heuristic_tile(int64_t m, int64_t n) {
   // Measured on MI355X: in FP32 the 64 x 64 tile (four workgroups per CU) is
   // the fastest on every large shape; in FP64 the 8-wavefront 128 x 128 tile
-  // is, once it still gives every CU several workgroups.
+  // is, once it still gives every CU several workgroups.  Narrow products
+  // take the 128 x 32 tile.
+  if (n <= kNarrow) return 4;
   const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
   if (sizeof(T) == 8 && big_tiles >= 2048) return 3;
   return 0;
@@ -519,7 +531,7 @@ static bool trace_on() {
   return on;
 }
 
-// A forced workgroup tile (0..3, -1 = automatic) for every unsplit launch,
+// A forced workgroup tile (0..4, -1 = automatic) for every unsplit launch,
 // so that each tile can be tested and measured on its own; tile 2 runs as
 // tile 1 in FP64.  The initial value comes from LRCC_GEMM_TILE.
 static std::atomic<int> g_forced_tile{-2};
@@ -527,26 +539,28 @@ static int forced_tile() {
   int t = g_forced_tile.load(std::memory_order_relaxed);
   if (t == -2) {
     const char* e = std::getenv("LRCC_GEMM_TILE");
-    t = (e && e[0] >= '0' && e[0] <= '3' && e[1] == 0) ? e[0] - '0' : -1;
+    t = (e && e[0] >= '0' && e[0] <= '4' && e[1] == 0) ? e[0] - '0' : -1;
     int expect = -2;
     if (!g_forced_tile.compare_exchange_strong(expect, t)) t = expect;
   }
   return t;
 }
 
-void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 3 ? tile : -1); }
+void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 4 ? tile : -1); }
 
-// Split-K for deep products whose 64 x 64 tile grid fills the chip poorly.
-// The chip holds `slots` resident 64 x 64 workgroups (four per CU in FP32,
-// two in FP64); a grid of w workgroups runs in ceil(w / slots) rounds, so
-// its efficiency is w / (rounds * slots).  The depth is split s ways (at
+// Split-K for deep products whose tile grid (64 x 64, or 128 x 32 for
+// narrow products) fills the chip poorly.  The chip holds `slots` resident
+// workgroups (64 x 64: four per CU in FP32, two in FP64; 128 x 32: three in
+// FP32, two in FP64); a grid of w workgroups runs in ceil(w / slots) rounds,
+// so its efficiency is w / (rounds * slots).  The depth is split s ways (at
 // least 1024 deep each, at most 64 ways, partials of at most 256 MB) for
 // the smallest s within 3 % of the best efficiency, and only when that
 // gains at least 15 % over no split.
 int gemm_splits(int64_t m, int64_t n, int64_t k, bool fp64) {
   if (k < 2048) return 1;
-  const int64_t tiles = ((m + 63) / 64) * ((n + 63) / 64);
-  const int64_t slots = fp64 ? 512 : 1024;
+  const bool nar = n <= kNarrow;
+  const int64_t tiles = nar ? ((m + 127) / 128) * ((n + 31) / 32) : ((m + 63) / 64) * ((n + 63) / 64);
+  const int64_t slots = nar ? (fp64 ? 512 : 768) : (fp64 ? 512 : 1024);
   const int64_t part = m * n * (fp64 ? 16 : 8);
   const int64_t smax = std::min<int64_t>({64, k / 1024, std::max<int64_t>(1, (int64_t(256) << 20) / part)});
   auto eff = [&](int64_t s) {
@@ -580,13 +594,19 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     const int splits = gemm_splits(m, n, k, sizeof(T) == 8);
     if (splits > 1 && ws && ws_bytes >= gemm_workspace_bytes<T>(m, n, k)) {
       if (trace_on())
-        fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=0 splits=%d\n",
+        fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=%d splits=%d\n",
                 sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k,
-                splits);
-      if (kind == 1)
+                n <= kNarrow ? 4 : 0, splits);
+      if (n <= kNarrow) {
+        if (kind == 1)
+          go<T, 1, 128, 32, 4>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
+        else
+          go<T, 0, 128, 32, 4>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
+      } else if (kind == 1) {
         go<T, 1, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
-      else
+      } else {
         go<T, 0, 64, 64, 2>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
+      }
       return;
     }
   }
@@ -623,9 +643,9 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   }
   const bool small = (double)m * n * k < 1e8;  // not worth timing
   if (tune && !small) {
-    static const int cand32[] = {0, 1, 2, 3}, cand64[] = {0, 1, 3};
+    static const int cand32[] = {0, 1, 2, 3, 4}, cand64[] = {0, 1, 3, 4};
     const int* cand = sizeof(T) == 4 ? cand32 : cand64;
-    const int ncand = sizeof(T) == 4 ? 4 : 3;
+    const int ncand = (sizeof(T) == 4 ? 4 : 3) + (n <= kNarrow ? 1 : 0);  // the narrow tile for narrow products
     void* scratch = nullptr;
     scratch = dev_alloc((size_t)m * n * 2 * sizeof(T));
     hipEvent_t e0, e1;

@@ -168,7 +168,7 @@ def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
 
 
 def gemm_set_tile(tile):
-    """Force the GEMM workgroup tile (0..3) of later launches; -1 restores
+    """Force the GEMM workgroup tile (0..4) of later launches; -1 restores
     the automatic choice."""
     rc = lib.lrcc_gemm_set_tile(int(tile))
     if rc != OK:

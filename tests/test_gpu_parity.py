@@ -54,7 +54,8 @@ def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
-@pytest.mark.parametrize("m,n,k", [(37, 53, 5000), (64, 64, 20011), (1, 7, 3000), (200, 10, 4100), (130, 3, 70000)])
+@pytest.mark.parametrize("m,n,k", [(37, 53, 5000), (64, 64, 20011), (1, 7, 3000), (200, 10, 4100), (130, 3, 70000),
+                                   (300, 32, 9000), (1000, 1, 3000)])
 def test_gemm_split_depth_matches_host_matmul(dtype, ta, tb, m, n, k):
     """Deep products with few output tiles run split over K (partial tiles
     reduced in a second kernel); alpha and beta apply after the reduction."""
@@ -76,7 +77,7 @@ def test_gemm_split_depth_matches_host_matmul(dtype, ta, tb, m, n, k):
     assert np.abs(got - ref).max() <= 20 * eps * scale * np.sqrt(k)
 
 
-@pytest.mark.parametrize("tile", [-1, 2, 3])
+@pytest.mark.parametrize("tile", [-1, 2, 3, 4])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_ragged_depth_repeated(forced_tile, tile, dtype, ta, tb):
@@ -86,7 +87,7 @@ def test_gemm_ragged_depth_repeated(forced_tile, tile, dtype, ta, tb):
     lrcc = _lrcc()
     forced_tile(tile)
     dev = torch.device("cuda:0")
-    for m, n, k in [(70, 90, 1), (37, 53, 29), (130, 129, 17), (300, 260, 45), (64, 64, 15)]:
+    for m, n, k in [(70, 90, 1), (37, 53, 29), (130, 129, 17), (300, 260, 45), (64, 64, 15), (300, 20, 45)]:
         rng = np.random.default_rng(m + n + k)
         A = _rand(rng, *((k, m) if ta else (m, k)))
         B = _rand(rng, *((n, k) if tb else (k, n)))
@@ -110,7 +111,7 @@ def forced_tile():
     lrcc.gemm_set_tile(-1)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 def test_gemm_each_tile(forced_tile, tile, dtype, ta, tb):
@@ -120,7 +121,8 @@ def test_gemm_each_tile(forced_tile, tile, dtype, ta, tb):
     lrcc = _lrcc()
     forced_tile(tile)
     dev = torch.device("cuda:0")
-    for m, n, k in [(37, 53, 29), (200, 130, 257), (260, 300, 45), (129, 385, 70), (1, 5, 7)]:
+    for m, n, k in [(37, 53, 29), (200, 130, 257), (260, 300, 45), (129, 385, 70), (1, 5, 7), (300, 20, 45),
+                    (257, 1, 70), (129, 33, 19)]:
         rng = np.random.default_rng(1000 * tile + m + n + k)
         A = _rand(rng, *((k, m) if ta else (m, k)))
         B = _rand(rng, *((n, k) if tb else (k, n)))
@@ -141,8 +143,9 @@ def test_gemm_each_tile(forced_tile, tile, dtype, ta, tb):
 
 def test_gemm_tile_choice_rejects_bad_values():
     lrcc = _lrcc()
-    with pytest.raises(lrcc.LrccError):
-        lrcc.gemm_set_tile(4)
+    for bad in (5, -2):
+        with pytest.raises(lrcc.LrccError):
+            lrcc.gemm_set_tile(bad)
     lrcc.gemm_set_tile(-1)
 
 

@@ -72,7 +72,7 @@ def test_argument_checks_come_before_any_device_work():
         assert rc == lrcc.E_INVALID, (prec, m, n, k, lda, ldb, ldc)
         assert len(lib.lrcc_last_error(None)) > 0
     assert lib.lrcc_gemm(lrcc.FP64, 0, 0, 4, 4, 4, one, None, 4, dummy, 4, one, dummy, 4, None) == lrcc.E_INVALID
-    assert lib.lrcc_gemm_set_tile(4) == lrcc.E_INVALID and lib.lrcc_gemm_set_tile(-2) == lrcc.E_INVALID
+    assert lib.lrcc_gemm_set_tile(5) == lrcc.E_INVALID and lib.lrcc_gemm_set_tile(-2) == lrcc.E_INVALID
     for field, bad in (("precision", 5), ("ladder_mode", 3), ("tol_residual", 0.0), ("maxit", 0),
                        ("diis_size", 33), ("rhs_chunk", -1)):
         c = lrcc.Config()
