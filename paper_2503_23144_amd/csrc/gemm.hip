@@ -431,9 +431,10 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 // Candidate workgroup tiles: 0 = 64 x 64, 1 = 128 x 64, 2 = 128 x 128 (FP32),
 // all with 4 wavefronts of (BM/2) x (BN/2); 3 = 128 x 128 with 8 wavefronts
 // of 64 x 32 (two wavefronts per SIMD where tile 2 has one); 4 = 128 x 32
-// with 4 wavefronts of 32 x 32 stacked along M, for products at most
-// kNarrow wide, where a 64-wide tile would spend most of its matrix-core
-// work on padding (N = 1 or o).
+// with 4 wavefronts of 32 x 32 stacked along M, the heuristic's choice for
+// products at most kNarrow wide, where a 64-wide tile would spend most of
+// its matrix-core work on padding (N = 1 or o), and a candidate for any
+// width (less padding when N is not a multiple of 64).
 // The autotuner times every candidate once per GEMM shape (into a scratch
 // output, so accumulating calls are not disturbed) and keeps the fastest;
 // without it a size heuristic decides.  Results can persist in a text cache
@@ -645,7 +646,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   if (tune && !small) {
     static const int cand32[] = {0, 1, 2, 3, 4}, cand64[] = {0, 1, 3, 4};
     const int* cand = sizeof(T) == 4 ? cand32 : cand64;
-    const int ncand = (sizeof(T) == 4 ? 4 : 3) + (n <= kNarrow ? 1 : 0);  // the narrow tile for narrow products
+    const int ncand = sizeof(T) == 4 ? 5 : 4;
     void* scratch = nullptr;
     scratch = dev_alloc((size_t)m * n * 2 * sizeof(T));
     hipEvent_t e0, e1;
