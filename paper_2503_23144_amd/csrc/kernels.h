@@ -55,6 +55,19 @@ void launch_unpack(const void* packed, void* full, const PackDesc& d, double are
 template <typename T>
 void launch_fill_zero(void* p, int64_t n, hipStream_t st);
 
+// out[r][p][q] = (acc ? out : 0) + sum_s alpha_s * src_s[r][p][q] (swap[s] == 0)
+// or alpha_s * src_s[r][q][p] (swap[s] == 1), in source order, r < rows,
+// p < np, q < nq: a run of accumulations into one tensor whose sources are
+// in its own index order or with its last two indices exchanged.
+struct SumSources {
+  int n;  // 1 .. 4
+  const void* p[4];
+  int swap[4];
+  double re[4], im[4];
+};
+template <typename T>
+void launch_sum_swap(const SumSources& s, void* out, bool acc, int64_t rows, int64_t np, int64_t nq, hipStream_t st);
+
 // out[r] = sum_k opx(x[r*ldx + k]) * y[r*ldy + k], r < nvec (FP64 result
 // {re, im} in device memory).  conjx: conjugate x.  `work` holds at least
 // nvec * 1024 * 16 bytes.

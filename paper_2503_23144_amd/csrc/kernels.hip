@@ -565,6 +565,102 @@ void launch_unpack(const void* packed, void* full, const PackDesc& d, double are
   LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- summed permutes
+// One workgroup per 32 x 32 tile of the trailing p x q block of one row r;
+// each thread owns four outputs (p = p0 + ty + 8e, q = q0 + tx).  Sources in
+// the output's order are read along q directly; exchanged sources are staged
+// through LDS (read along p) so that every global access is coalesced.
+struct SumArgs {
+  int n;
+  const void* p[4];
+  int swap[4];
+  double re[4], im[4];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) sum_swap_kernel(SumArgs s, typename cplx2<T>::type* __restrict__ out,
+                                                       int acc, int64_t rows, int np, int nq, int ntp, int ntq) {
+  using C = typename cplx2<T>::type;
+  constexpr int NY = 256 / UT, EPT = UT / NY;
+  __shared__ C tile[UT][UT + 1];
+  const int tx = threadIdx.x % UT, ty = threadIdx.x / UT;
+  const int64_t per_row = (int64_t)ntp * ntq, nblk = rows * per_row, blk_elems = (int64_t)np * nq;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r = blk / per_row;
+    const int t = (int)(blk % per_row), p0 = (t / ntq) * UT, q0 = (t % ntq) * UT;
+    const int64_t base = r * blk_elems;
+    T re[EPT], im[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int p = p0 + ty + NY * e, q = q0 + tx;
+      re[e] = im[e] = 0;
+      if (acc && p < np && q < nq) {
+        const C y = out[base + (int64_t)p * nq + q];
+        re[e] = y.x;
+        im[e] = y.y;
+      }
+    }
+    for (int k = 0; k < s.n; ++k) {  // uniform over the workgroup
+      const C* src = (const C*)s.p[k];
+      const T ar = (T)s.re[k], ai = (T)s.im[k];
+      if (!s.swap[k]) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int p = p0 + ty + NY * e, q = q0 + tx;
+          if (p < np && q < nq) {
+            const C x = src[base + (int64_t)p * nq + q];
+            re[e] += ar * x.x - ai * x.y;
+            im[e] += ar * x.y + ai * x.x;
+          }
+        }
+      } else {
+        for (int y = ty; y < UT; y += NY) {  // src[r][q][p], rows q, along p
+          const int q = q0 + y, p = p0 + tx;
+          if (q < nq && p < np) tile[y][tx] = src[base + (int64_t)q * np + p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int p = p0 + ty + NY * e, q = q0 + tx;
+          if (p < np && q < nq) {
+            const C x = tile[tx][ty + NY * e];
+            re[e] += ar * x.x - ai * x.y;
+            im[e] += ar * x.y + ai * x.x;
+          }
+        }
+        __syncthreads();  // the tile is rewritten by the next exchanged source
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int p = p0 + ty + NY * e, q = q0 + tx;
+      if (p < np && q < nq) out[base + (int64_t)p * nq + q] = C{re[e], im[e]};
+    }
+  }
+}
+
+template <typename T>
+void launch_sum_swap(const SumSources& s, void* out, bool acc, int64_t rows, int64_t np, int64_t nq,
+                     hipStream_t st) {
+  if (rows <= 0 || np <= 0 || nq <= 0) return;
+  LRCC_REQUIRE(s.n >= 1 && s.n <= 4 && np < (int64_t(1) << 30) && nq < (int64_t(1) << 30), LRCC_E_INTERNAL,
+               "summed permute: bad sources or sizes");
+  SumArgs a{};
+  a.n = s.n;
+  for (int k = 0; k < s.n; ++k) {
+    a.p[k] = s.p[k];
+    a.swap[k] = s.swap[k];
+    a.re[k] = s.re[k];
+    a.im[k] = s.im[k];
+  }
+  const int64_t ntp = (np + UT - 1) / UT, ntq = (nq + UT - 1) / UT;
+  const int64_t blocks = std::min<int64_t>(rows * ntp * ntq, int64_t(1) << 24);
+  using C = typename cplx2<T>::type;
+  hipLaunchKernelGGL(sum_swap_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, a, (C*)out, acc ? 1 : 0, rows,
+                     (int)np, (int)nq, (int)ntp, (int)ntq);
+  LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------- fill
 template <typename T>
 __global__ void fill_zero_kernel(typename cplx2<T>::type* p, int64_t n) {
@@ -959,6 +1055,7 @@ void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int6
   template void launch_pack<T>(const void*, void*, const PackDesc&, double, double, bool, hipStream_t);      \
   template void launch_unpack<T>(const void*, void*, const PackDesc&, double, double, bool, hipStream_t);    \
   template void launch_fill_zero<T>(void*, int64_t, hipStream_t);                                            \
+  template void launch_sum_swap<T>(const SumSources&, void*, bool, int64_t, int64_t, int64_t, hipStream_t);   \
   template void launch_batched_dot<T>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, bool,    \
                                       void*, void*, hipStream_t);                                            \
   template void launch_residual<T>(int64_t, int64_t, const void*, const double*, const void*, const void*,   \

@@ -173,6 +173,7 @@ class Executor {
 
   void contract(const Op& op, int nb);
   void add(const Op& op, int nb);
+  size_t fused_adds(const OpList& ops, size_t i);
   void pack(const Op& op, int nb);
   void unpack(const Op& op, int nb);
   void permute_into(const void* src, int64_t src_cap, const std::string& sl, void* dst, int64_t dst_cap,

@@ -679,6 +679,53 @@ void Executor<T>::add(const Op& op, int nb) {
   permute_into(ptr(op.a), capacity(op.a), a, ptr(op.out), capacity(op.out), c, op.are, op.aim, op.acc ? 1 : 0, 0);
 }
 
+// A run of Add ops ops[i..j) into one tensor, the first one plain or
+// accumulating and the rest accumulating, whose sources are in the output's
+// index order or have its last two indices exchanged (the dressed doubles
+// t2 + t1 t1 - (t1 t1) with a <-> b, and the like), runs as one summed
+// permute: every source is read once and the output written once instead of
+// once per op.  Returns j (i when no run of at least two ops starts at i).
+template <typename T>
+size_t Executor<T>::fused_adds(const OpList& ops, size_t i) {
+  const Op& o0 = ops[i];
+  const std::string c = letters(o0.out, o0.oi);
+  const size_t L = c.size();
+  if (L < 2 || c[L - 1] == '#' || c[L - 2] == '#') return i;
+  std::string cs = c;
+  std::swap(cs[L - 1], cs[L - 2]);
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  const int64_t np = dimof(c[L - 2]), nq = dimof(c[L - 1]);
+  int64_t total = 1;
+  for (char l : c) total *= dimof(l);
+  SumSources s{};
+  size_t j = i;
+  while (j < ops.size() && s.n < 4) {
+    const Op& o = ops[j];
+    if (o.kind != OpKind::Add || o.out != o0.out || o.a == o.out || (j > i && !o.acc)) break;
+    if (letters(o.out, o.oi) != c || m_[o.a].batched != m_[o.out].batched) break;
+    const std::string a = letters(o.a, o.ai);
+    int sw;
+    if (a == c)
+      sw = 0;
+    else if (a == cs)
+      sw = 1;
+    else
+      break;
+    s.p[s.n] = ptr(o.a);
+    s.swap[s.n] = sw;
+    s.re[s.n] = o.are;
+    s.im[s.n] = o.aim;
+    ++s.n;
+    ++j;
+  }
+  if (j < i + 2) return i;
+  for (size_t k = i; k < j; ++k)
+    LRCC_REQUIRE(total <= capacity(ops[k].a), LRCC_E_INTERNAL, "summed permute exceeds a source buffer");
+  LRCC_REQUIRE(total <= capacity(o0.out), LRCC_E_INTERNAL, "summed permute exceeds its output buffer");
+  launch_sum_swap<T>(s, ptr(o0.out), o0.acc, total / (np * nq), np, nq, st_);
+  return j;
+}
+
 // Align packed letters `pk` with full letters `fl`: for each packed position,
 // the first full position it covers and whether it is a pair.
 static void align(const std::string& pk, const std::string& fl, std::vector<int>& fpos, std::vector<int>& ispair) {
@@ -906,10 +953,18 @@ void Executor<T>::prepare(const OpList& ops, int nb, const std::vector<int>& kee
 template <typename T>
 void Executor<T>::run_ops(const OpList& ops, int nb) {
   pcache_[0] = pcache_[1] = PermEntry();
-  for (const Op& op : ops) {
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const Op& op = ops[i];
     switch (op.kind) {
       case OpKind::Contract: contract(op, nb); break;
-      case OpKind::Add: add(op, nb); break;
+      case OpKind::Add: {
+        const size_t j = fused_adds(ops, i);
+        if (j > i)
+          i = j - 1;
+        else
+          add(op, nb);
+        break;
+      }
       case OpKind::Pack: pack(op, nb); break;
       case OpKind::Unpack: unpack(op, nb); break;
       case OpKind::Zero:
