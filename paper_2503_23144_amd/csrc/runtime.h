@@ -173,7 +173,8 @@ class Executor {
 
   void contract(const Op& op, int nb);
   void add(const Op& op, int nb);
-  size_t fused_adds(const OpList& ops, size_t i);
+  bool fuse_adds(const OpList& ops, const std::vector<size_t>& idx);
+  size_t run_adds(const OpList& ops, size_t i, int nb);
   void pack(const Op& op, int nb);
   void unpack(const Op& op, int nb);
   void permute_into(const void* src, int64_t src_cap, const std::string& sl, void* dst, int64_t dst_cap,

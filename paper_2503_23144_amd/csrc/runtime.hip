@@ -679,51 +679,98 @@ void Executor<T>::add(const Op& op, int nb) {
   permute_into(ptr(op.a), capacity(op.a), a, ptr(op.out), capacity(op.out), c, op.are, op.aim, op.acc ? 1 : 0, 0);
 }
 
-// A run of Add ops ops[i..j) into one tensor, the first one plain or
-// accumulating and the rest accumulating, whose sources are in the output's
-// index order or have its last two indices exchanged (the dressed doubles
-// t2 + t1 t1 - (t1 t1) with a <-> b, and the like), runs as one summed
-// permute: every source is read once and the output written once instead of
-// once per op.  Returns j (i when no run of at least two ops starts at i).
+// Permute-accumulates into one tensor whose sources are in its index order
+// or have its last two indices exchanged (the dressed doubles t2 + t1 t1 -
+// (t1 t1) with a <-> b, their adjoints, and the like) run as one summed
+// permute: every source is read once and the output written once, not once
+// per op.  ops[idx[0]] may be plain or accumulating, the rest must
+// accumulate.  Returns false, launching nothing, when the ops do not fit.
 template <typename T>
-size_t Executor<T>::fused_adds(const OpList& ops, size_t i) {
-  const Op& o0 = ops[i];
-  const std::string c = letters(o0.out, o0.oi);
-  const size_t L = c.size();
-  if (L < 2 || c[L - 1] == '#' || c[L - 2] == '#') return i;
-  std::string cs = c;
-  std::swap(cs[L - 1], cs[L - 2]);
+bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx) {
+  if (idx.size() < 2) return false;
+  const Op& o0 = ops[idx[0]];
+  const int L = (int)letters(o0.out, o0.oi).size();
+  if (L < 2) return false;
   auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
-  const int64_t np = dimof(c[L - 2]), nq = dimof(c[L - 1]);
+  const std::string c0 = letters(o0.out, o0.oi);
+  if (c0[L - 1] == '#' || c0[L - 2] == '#') return false;
+  const int64_t np = dimof(c0[L - 2]), nq = dimof(c0[L - 1]);
   int64_t total = 1;
-  for (char l : c) total *= dimof(l);
-  SumSources s{};
-  size_t j = i;
-  while (j < ops.size() && s.n < 4) {
-    const Op& o = ops[j];
-    if (o.kind != OpKind::Add || o.out != o0.out || o.a == o.out || (j > i && !o.acc)) break;
-    if (letters(o.out, o.oi) != c || m_[o.a].batched != m_[o.out].batched) break;
-    const std::string a = letters(o.a, o.ai);
-    int sw;
-    if (a == c)
-      sw = 0;
-    else if (a == cs)
-      sw = 1;
-    else
-      break;
-    s.p[s.n] = ptr(o.a);
-    s.swap[s.n] = sw;
-    s.re[s.n] = o.are;
-    s.im[s.n] = o.aim;
-    ++s.n;
-    ++j;
+  for (char l : c0) total *= dimof(l);
+  std::vector<int> sw(idx.size());
+  for (size_t g = 0; g < idx.size(); ++g) {
+    const Op& o = ops[idx[g]];
+    if (o.kind != OpKind::Add || o.out != o0.out || o.a == o.out || (g > 0 && !o.acc)) return false;
+    if (m_[o.a].batched != m_[o.out].batched) return false;
+    const std::string c = letters(o.out, o.oi), a = letters(o.a, o.ai);
+    if ((int)c.size() != L || (int)a.size() != L) return false;
+    // source position of each output position
+    bool ident = true, swap = true;
+    for (int k = 0; k < L; ++k) {
+      const size_t p = a.find(c[k]);
+      if (p == std::string::npos) return false;
+      ident = ident && (int)p == k;
+      swap = swap && (int)p == (k < L - 2 ? k : (k == L - 2 ? L - 1 : L - 2));
+    }
+    if (!ident && !swap) return false;
+    sw[g] = ident ? 0 : 1;
+    if (total > capacity(o.a)) return false;
   }
-  if (j < i + 2) return i;
-  for (size_t k = i; k < j; ++k)
-    LRCC_REQUIRE(total <= capacity(ops[k].a), LRCC_E_INTERNAL, "summed permute exceeds a source buffer");
   LRCC_REQUIRE(total <= capacity(o0.out), LRCC_E_INTERNAL, "summed permute exceeds its output buffer");
-  launch_sum_swap<T>(s, ptr(o0.out), o0.acc, total / (np * nq), np, nq, st_);
-  return j;
+  for (size_t g0 = 0; g0 < idx.size(); g0 += 4) {  // at most four sources per launch
+    SumSources s{};
+    for (size_t g = g0; g < idx.size() && g < g0 + 4; ++g) {
+      const Op& o = ops[idx[g]];
+      s.p[s.n] = ptr(o.a);
+      s.swap[s.n] = sw[g];
+      s.re[s.n] = o.are;
+      s.im[s.n] = o.aim;
+      ++s.n;
+    }
+    launch_sum_swap<T>(s, ptr(o0.out), g0 == 0 ? o0.acc : true, total / (np * nq), np, nq, st_);
+  }
+  return true;
+}
+
+// Runs the Add ops from ops[i] to the next op of another kind; returns the
+// index after them.  When no op of the run reads a tensor that another op of
+// the run writes, and no tensor is first written after ops[i] within the run
+// (so no buffer of the liveness pool changes hands inside it), the ops are
+// regrouped by output tensor, each group keeping its order, and every group
+// that fits runs as one summed permute; otherwise consecutive ops into one
+// tensor are grouped.
+template <typename T>
+size_t Executor<T>::run_adds(const OpList& ops, size_t i, int nb) {
+  size_t w = i;
+  while (w < ops.size() && ops[w].kind == OpKind::Add) ++w;
+  bool regroup = w - i >= 2;
+  for (size_t k = i; k < w && regroup; ++k) {
+    for (size_t q = i; q < w && regroup; ++q)
+      if (q != k && ops[k].a == ops[q].out) regroup = false;
+    if (k > i) {
+      bool written_before = false;
+      for (size_t q = 0; q < k && !written_before; ++q) written_before = ops[q].out == ops[k].out;
+      if (!written_before) regroup = false;
+    }
+  }
+  std::vector<std::vector<size_t>> groups;
+  if (regroup) {
+    for (size_t k = i; k < w; ++k) {
+      size_t g = 0;
+      while (g < groups.size() && ops[groups[g][0]].out != ops[k].out) ++g;
+      if (g == groups.size()) groups.emplace_back();
+      groups[g].push_back(k);
+    }
+  } else {
+    for (size_t k = i; k < w; ++k) {
+      if (groups.empty() || ops[groups.back()[0]].out != ops[k].out) groups.emplace_back();
+      groups.back().push_back(k);
+    }
+  }
+  for (const auto& g : groups)
+    if (!fuse_adds(ops, g))
+      for (size_t k : g) add(ops[k], nb);
+  return w;
 }
 
 // Align packed letters `pk` with full letters `fl`: for each packed position,
@@ -957,14 +1004,7 @@ void Executor<T>::run_ops(const OpList& ops, int nb) {
     const Op& op = ops[i];
     switch (op.kind) {
       case OpKind::Contract: contract(op, nb); break;
-      case OpKind::Add: {
-        const size_t j = fused_adds(ops, i);
-        if (j > i)
-          i = j - 1;
-        else
-          add(op, nb);
-        break;
-      }
+      case OpKind::Add: i = run_adds(ops, i, nb) - 1; break;
       case OpKind::Pack: pack(op, nb); break;
       case OpKind::Unpack: unpack(op, nb); break;
       case OpKind::Zero:
