@@ -107,9 +107,12 @@ void launch_residual(int64_t nvec, int64_t n, const void* sig, const double* shi
 // p[i*(n+1)] = 0 for i < n (diagonal of an n x n complex matrix)
 template <typename T>
 void launch_zero_diag(void* p, int64_t n, hipStream_t st);
-// Xn = X - R / (D + s_r);  E = Xn - X  (either output may be null)
+// Xn = X - R / (D + s_r);  E = Xn - X  (either output may be null).  With
+// out_rows (device, nvec entries) row r of Xn and E is their row out_rows[r]
+// (e.g. a slot of a history ring); E2, when given, receives E at row r too.
 void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X,
-                   const void* R, void* Xn, void* E, hipStream_t st);
+                   const void* R, void* Xn, void* E, hipStream_t st, const int* out_rows = nullptr,
+                   void* E2 = nullptr);
 // X[r] = sum_k c[r*m + k] * H[(r*hs + k)*n + ...]
 void launch_combine(int64_t nvec, int m, int64_t n, const void* c, const void* H, int64_t hs, void* X,
                     hipStream_t st);

@@ -820,24 +820,27 @@ void launch_zero_diag(void* p, int64_t n, hipStream_t st) {
 __global__ void __launch_bounds__(256) jacobi_kernel(int64_t n, const double* __restrict__ D,
                                                      const double* __restrict__ shift, const double2* __restrict__ X,
                                                      const double2* __restrict__ R, double2* __restrict__ Xn,
-                                                     double2* __restrict__ E) {
-  int64_t r = blockIdx.y;
+                                                     double2* __restrict__ E, const int* __restrict__ out_rows,
+                                                     double2* __restrict__ E2) {
+  const int64_t r = blockIdx.y;
+  const int64_t ro = out_rows ? (int64_t)out_rows[r] : r;
   double s = shift ? shift[r] : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    int64_t k = r * n + i;
+    const int64_t k = r * n + i, ko = ro * n + i;
     double inv = 1.0 / (D[i] + s);
     double2 d = {-R[k].x * inv, -R[k].y * inv};
-    if (Xn) Xn[k] = X ? double2{X[k].x + d.x, X[k].y + d.y} : d;
-    if (E) E[k] = d;
+    if (Xn) Xn[ko] = X ? double2{X[k].x + d.x, X[k].y + d.y} : d;
+    if (E) E[ko] = d;
+    if (E2) E2[k] = d;
   }
 }
 
 void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X, const void* R,
-                   void* Xn, void* E, hipStream_t st) {
+                   void* Xn, void* E, hipStream_t st, const int* out_rows, void* E2) {
   if (nvec <= 0) return;
   unsigned gx = nblocks(n, 256, 4096);
   hipLaunchKernelGGL(jacobi_kernel, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, D, shift_dev, (const double2*)X,
-                     (const double2*)R, (double2*)Xn, (double2*)E);
+                     (const double2*)R, (double2*)Xn, (double2*)E, out_rows, (double2*)E2);
   LAUNCH_CHECK();
 }
 

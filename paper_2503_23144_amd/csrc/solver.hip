@@ -475,10 +475,10 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
   const int m = std::max(0, c.cfg.diis_size);
   const size_t vb = n * 16;
   double t0 = now_s();
-  DevBuf Xw, Bw, Rw, Xn, En, Hx, He, shift, coef, gram, dots, work;
+  DevBuf Xw, Bw, Rw, Xn, En, Hx, He, shift, hrows, coef, gram, dots, work;
   Xw.ensure(nb * vb);
   Rw.ensure(nb * vb);
-  Xn.ensure(nb * vb);
+  if (m == 0) Xn.ensure(nb * vb);  // with a history, the update goes straight into it
   En.ensure(nb * vb);
   if (b) {
     Bw.ensure(nb * vb);
@@ -491,6 +491,7 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
     launch_fill_zero<double>(Hx.p, (int64_t)nb * m * n, c.st);
     coef.ensure(nb * m * 16);
     gram.ensure(nb * m * 16);
+    hrows.ensure(nb * sizeof(int));
   }
   shift.ensure(nb * 8);
   dots.ensure(nb * 16);
@@ -500,6 +501,7 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
   if (shifts_host) sh.assign(shifts_host, shifts_host + nb);
   std::vector<SlotMeta> meta(nb);
   std::vector<cplx> hd(nb), hg((size_t)nb * std::max(m, 1)), hc((size_t)nb * std::max(m, 1));
+  std::vector<int> hr(nb);
   if (b) {
     launch_batched_dot<double>(nb, n, Bw.p, n, Bw.p, n, true, dots.p, work.p, c.st);
     HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, nb * 16, hipMemcpyDeviceToHost, c.st));
@@ -572,17 +574,17 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
     }
     if (na == 0 || it == maxit) break;
     HIP_CHECK(hipMemcpyAsync(shift.p, sh.data(), na * 8, hipMemcpyHostToDevice, c.st));
-    launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Xn.p, En.p, c.st);
     for (int s = 0; s < na; ++s) meta[s].iters += 1;
     if (m == 0) {
+      launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Xn.p, En.p, c.st);
       HIP_CHECK(hipMemcpyAsync(Xw.p, Xn.p, na * vb, hipMemcpyDeviceToDevice, c.st));
       continue;
     }
-    for (int s = 0; s < na; ++s) {
-      int p = meta[s].next;
-      HIP_CHECK(hipMemcpyAsync(hist_ptr(Hx, s, p), slot_ptr(Xn, s), vb, hipMemcpyDeviceToDevice, c.st));
-      HIP_CHECK(hipMemcpyAsync(hist_ptr(He, s, p), slot_ptr(En, s), vb, hipMemcpyDeviceToDevice, c.st));
-    }
+    // the update and its step go straight into each slot's next history
+    // row (hist_ptr(Hx/He, s, next)); the step also into En for the Gram rows
+    for (int s = 0; s < na; ++s) hr[s] = s * m + meta[s].next;
+    HIP_CHECK(hipMemcpyAsync(hrows.p, hr.data(), na * sizeof(int), hipMemcpyHostToDevice, c.st));
+    launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Hx.p, He.p, c.st, hrows.as<int>(), En.p);
     launch_gram(na, m, n, He.p, m, En.p, gram.p, work.p, c.st);
     HIP_CHECK(hipMemcpyAsync(hg.data(), gram.p, (size_t)na * m * 16, hipMemcpyDeviceToHost, c.st));
     c.sync();
