@@ -58,12 +58,22 @@ void launch_fill_zero(void* p, int64_t n, hipStream_t st);
 // out[r][p][q] = (acc ? out : 0) + sum_s alpha_s * src_s[r][p][q] (swap[s] == 0)
 // or alpha_s * src_s[r][q][p] (swap[s] == 1), in source order, r < rows,
 // p < np, q < nq: a run of accumulations into one tensor whose sources are
-// in its own index order or with its last two indices exchanged.
+// in its own index order or with its last two indices exchanged.  A source
+// with virt[s] set is no tensor but the sum of outer products
+// tt[b][i][j][p][q] = sum_c beta_c U_c[b][i][p] V_c[b][j][q], row r = (b ni + i) nj + j
+// (U_c, V_c row-major, batch strides ustride/vstride elements, 0 = shared).
 struct SumSources {
   int n;  // 1 .. 4
   const void* p[4];
   int swap[4];
+  int virt[4];
   double re[4], im[4];
+  int nouter;  // 0 .. 2 outer products
+  const void* U[2];
+  const void* V[2];
+  int64_t ustride[2], vstride[2];
+  double ore[2], oim[2];
+  int64_t ni, nj;
 };
 template <typename T>
 void launch_sum_swap(const SumSources& s, void* out, bool acc, int64_t rows, int64_t np, int64_t nq, hipStream_t st);

@@ -574,21 +574,34 @@ struct SumArgs {
   int n;
   const void* p[4];
   int swap[4];
+  int virt[4];
   double re[4], im[4];
+  int nouter;
+  const void* U[2];
+  const void* V[2];
+  int64_t ustride[2], vstride[2];
+  double ore[2], oim[2];
+  int64_t ni, nj;
 };
 
-template <typename T>
+template <typename T, typename I>
 __global__ void __launch_bounds__(256) sum_swap_kernel(SumArgs s, typename cplx2<T>::type* __restrict__ out,
-                                                       int acc, int64_t rows, int np, int nq, int ntp, int ntq) {
+                                                       int acc, I rows, int np, int nq, int ntp, int ntq) {
   using C = typename cplx2<T>::type;
   constexpr int NY = 256 / UT, EPT = UT / NY;
   __shared__ C tile[UT][UT + 1];
+  __shared__ C fac[2][4][UT];  // outer-product factors of in-place sources
+  static_assert(2 * 4 * UT == 256, "one factor entry per thread");
   const int tx = threadIdx.x % UT, ty = threadIdx.x / UT;
-  const int64_t per_row = (int64_t)ntp * ntq, nblk = rows * per_row, blk_elems = (int64_t)np * nq;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t r = blk / per_row;
-    const int t = (int)(blk % per_row), p0 = (t / ntq) * UT, q0 = (t % ntq) * UT;
+  const I per_row = (I)ntp * (I)ntq, nblk = rows * per_row;
+  const int64_t blk_elems = (int64_t)np * nq;
+  const I nj = (I)s.nj, ni = (I)s.ni;
+  for (I blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const I r = blk / per_row;
+    const int t = (int)(blk - r * per_row), p0 = (t / ntq) * UT, q0 = (t % ntq) * UT;
     const int64_t base = r * blk_elems;
+    bool hv = false;
+    for (int k = 0; k < s.n; ++k) hv = hv || s.virt[k] != 0;
     T re[EPT], im[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -600,10 +613,48 @@ __global__ void __launch_bounds__(256) sum_swap_kernel(SumArgs s, typename cplx2
         im[e] = y.y;
       }
     }
+    // Outer-product factors of this tile for in-place sources, staged in
+    // LDS by one load per thread (beta folded into U): fac[c][0] = beta
+    // U_c[b][i][p0 + x], [1] = V_c[b][j][p0 + x], [2] = beta U_c[b][i][q0 + x],
+    // [3] = V_c[b][j][q0 + x], x < 32.
+    if (hv) {
+      const I rj = r / nj, rb = rj / ni;
+      const int64_t j = (int64_t)(r - rj * nj), i = (int64_t)(rj - rb * ni), b = (int64_t)rb;
+      const int cc = threadIdx.x / (4 * UT), w = (threadIdx.x / UT) % 4, x = threadIdx.x % UT;
+      const int idx = (w < 2 ? p0 : q0) + x;
+      C val = C{0, 0};
+      if (cc < s.nouter && idx < np) {
+        if (w % 2 == 0) {
+          const C u = ((const C*)s.U[cc])[b * s.ustride[cc] + i * np + idx];
+          const T br = (T)s.ore[cc], bi = (T)s.oim[cc];
+          val = C{br * u.x - bi * u.y, br * u.y + bi * u.x};
+        } else {
+          val = ((const C*)s.V[cc])[b * s.vstride[cc] + j * nq + idx];
+        }
+      }
+      fac[cc][w][x] = val;
+      __syncthreads();
+    }
     for (int k = 0; k < s.n; ++k) {  // uniform over the workgroup
       const C* src = (const C*)s.p[k];
       const T ar = (T)s.re[k], ai = (T)s.im[k];
-      if (!s.swap[k]) {
+      if (s.virt[k]) {
+        // tt[p][q] = sum_c beta_c U_c[i][p] V_c[j][q]; exchanged: tt[q][p]
+        const bool sw = s.swap[k] != 0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          T tr = 0, ti = 0;
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            const C u = sw ? fac[cc][2][tx] : fac[cc][0][ty + NY * e];
+            const C v = sw ? fac[cc][1][ty + NY * e] : fac[cc][3][tx];
+            tr += u.x * v.x - u.y * v.y;
+            ti += u.x * v.y + u.y * v.x;
+          }
+          re[e] += ar * tr - ai * ti;
+          im[e] += ar * ti + ai * tr;
+        }
+      } else if (!s.swap[k]) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           const int p = p0 + ty + NY * e, q = q0 + tx;
@@ -636,6 +687,7 @@ __global__ void __launch_bounds__(256) sum_swap_kernel(SumArgs s, typename cplx2
       const int p = p0 + ty + NY * e, q = q0 + tx;
       if (p < np && q < nq) out[base + (int64_t)p * nq + q] = C{re[e], im[e]};
     }
+    if (hv) __syncthreads();  // fac is rewritten for the next tile
   }
 }
 
@@ -645,19 +697,38 @@ void launch_sum_swap(const SumSources& s, void* out, bool acc, int64_t rows, int
   if (rows <= 0 || np <= 0 || nq <= 0) return;
   LRCC_REQUIRE(s.n >= 1 && s.n <= 4 && np < (int64_t(1) << 30) && nq < (int64_t(1) << 30), LRCC_E_INTERNAL,
                "summed permute: bad sources or sizes");
+  LRCC_REQUIRE(s.nouter >= 0 && s.nouter <= 2, LRCC_E_INTERNAL, "summed permute: bad outer products");
   SumArgs a{};
   a.n = s.n;
   for (int k = 0; k < s.n; ++k) {
     a.p[k] = s.p[k];
     a.swap[k] = s.swap[k];
+    a.virt[k] = s.virt[k];
     a.re[k] = s.re[k];
     a.im[k] = s.im[k];
+    LRCC_REQUIRE(!s.virt[k] || (s.nouter > 0 && np == nq && s.ni > 0 && s.nj > 0), LRCC_E_INTERNAL,
+                 "summed permute: a virtual source needs its outer products");
   }
+  a.nouter = s.nouter;
+  for (int c = 0; c < s.nouter; ++c) {
+    a.U[c] = s.U[c];
+    a.V[c] = s.V[c];
+    a.ustride[c] = s.ustride[c];
+    a.vstride[c] = s.vstride[c];
+    a.ore[c] = s.ore[c];
+    a.oim[c] = s.oim[c];
+  }
+  a.ni = s.ni;
+  a.nj = s.nj;
   const int64_t ntp = (np + UT - 1) / UT, ntq = (nq + UT - 1) / UT;
   const int64_t blocks = std::min<int64_t>(rows * ntp * ntq, int64_t(1) << 24);
   using C = typename cplx2<T>::type;
-  hipLaunchKernelGGL(sum_swap_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, a, (C*)out, acc ? 1 : 0, rows,
-                     (int)np, (int)nq, (int)ntp, (int)ntq);
+  if (rows * ntp * ntq < (int64_t(1) << 31) && s.ni < (int64_t(1) << 31) && s.nj < (int64_t(1) << 31))
+    hipLaunchKernelGGL((sum_swap_kernel<T, uint32_t>), dim3((unsigned)blocks), dim3(256), 0, st, a, (C*)out,
+                       acc ? 1 : 0, (uint32_t)rows, (int)np, (int)nq, (int)ntp, (int)ntq);
+  else
+    hipLaunchKernelGGL((sum_swap_kernel<T, int64_t>), dim3((unsigned)blocks), dim3(256), 0, st, a, (C*)out,
+                       acc ? 1 : 0, rows, (int)np, (int)nq, (int)ntp, (int)ntq);
   LAUNCH_CHECK();
 }
 

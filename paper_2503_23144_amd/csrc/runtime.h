@@ -173,8 +173,14 @@ class Executor {
 
   void contract(const Op& op, int nb);
   void add(const Op& op, int nb);
-  bool fuse_adds(const OpList& ops, const std::vector<size_t>& idx);
+  bool fuse_adds(const OpList& ops, const std::vector<size_t>& idx, bool launch = true);
+  std::vector<std::vector<size_t>> add_groups(const OpList& ops, size_t i, size_t w) const;
   size_t run_adds(const OpList& ops, size_t i, int nb);
+  bool outer_product(const Op& o, SumSources& s);
+  size_t run_dressed(const OpList& ops, size_t i, int nb);
+  int virt_id_ = -1;      // tensor evaluated in place by summed permutes (run_dressed)
+  SumSources virt_{};     // its outer products
+  std::vector<int> keep_;  // tensors the current run keeps
   void pack(const Op& op, int nb);
   void unpack(const Op& op, int nb);
   void permute_into(const void* src, int64_t src_cap, const std::string& sl, void* dst, int64_t dst_cap,

@@ -684,16 +684,17 @@ void Executor<T>::add(const Op& op, int nb) {
 // (t1 t1) with a <-> b, their adjoints, and the like) run as one summed
 // permute: every source is read once and the output written once, not once
 // per op.  ops[idx[0]] may be plain or accumulating, the rest must
-// accumulate.  Returns false, launching nothing, when the ops do not fit.
+// accumulate.  A source that is the tensor virt_id_ is evaluated in place
+// from its outer products.  Returns false, launching nothing, when the ops
+// do not fit; with launch false it only checks.
 template <typename T>
-bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx) {
+bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx, bool launch) {
   if (idx.size() < 2) return false;
   const Op& o0 = ops[idx[0]];
-  const int L = (int)letters(o0.out, o0.oi).size();
-  if (L < 2) return false;
-  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
   const std::string c0 = letters(o0.out, o0.oi);
-  if (c0[L - 1] == '#' || c0[L - 2] == '#') return false;
+  const int L = (int)c0.size();
+  if (L < 2 || c0[L - 1] == '#' || c0[L - 2] == '#') return false;
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
   const int64_t np = dimof(c0[L - 2]), nq = dimof(c0[L - 1]);
   int64_t total = 1;
   for (char l : c0) total *= dimof(l);
@@ -714,14 +715,22 @@ bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx) {
     }
     if (!ident && !swap) return false;
     sw[g] = ident ? 0 : 1;
-    if (total > capacity(o.a)) return false;
+    if (o.a == virt_id_) {
+      if (np != nq || total != (m_[o.a].batched ? g_nb : 1) * virt_.ni * virt_.nj * np * nq) return false;
+    } else if (total > capacity(o.a)) {
+      return false;
+    }
   }
+  if (!launch) return true;
   LRCC_REQUIRE(total <= capacity(o0.out), LRCC_E_INTERNAL, "summed permute exceeds its output buffer");
   for (size_t g0 = 0; g0 < idx.size(); g0 += 4) {  // at most four sources per launch
-    SumSources s{};
+    SumSources s = virt_;
+    s.n = 0;
     for (size_t g = g0; g < idx.size() && g < g0 + 4; ++g) {
       const Op& o = ops[idx[g]];
-      s.p[s.n] = ptr(o.a);
+      const bool v = o.a == virt_id_;
+      s.p[s.n] = v ? nullptr : ptr(o.a);
+      s.virt[s.n] = v ? 1 : 0;
       s.swap[s.n] = sw[g];
       s.re[s.n] = o.are;
       s.im[s.n] = o.aim;
@@ -732,17 +741,14 @@ bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx) {
   return true;
 }
 
-// Runs the Add ops from ops[i] to the next op of another kind; returns the
-// index after them.  When no op of the run reads a tensor that another op of
-// the run writes, and no tensor is first written after ops[i] within the run
-// (so no buffer of the liveness pool changes hands inside it), the ops are
-// regrouped by output tensor, each group keeping its order, and every group
-// that fits runs as one summed permute; otherwise consecutive ops into one
+// Groups of the Add ops ops[i..w) that run_adds executes together.  When no
+// op of the run reads a tensor that another op of the run writes, and no
+// tensor is first written after ops[i] within the run (so no buffer of the
+// liveness pool changes hands inside it), the ops are grouped by output
+// tensor, each group keeping its order; otherwise consecutive ops into one
 // tensor are grouped.
 template <typename T>
-size_t Executor<T>::run_adds(const OpList& ops, size_t i, int nb) {
-  size_t w = i;
-  while (w < ops.size() && ops[w].kind == OpKind::Add) ++w;
+std::vector<std::vector<size_t>> Executor<T>::add_groups(const OpList& ops, size_t i, size_t w) const {
   bool regroup = w - i >= 2;
   for (size_t k = i; k < w && regroup; ++k) {
     for (size_t q = i; q < w && regroup; ++q)
@@ -754,22 +760,115 @@ size_t Executor<T>::run_adds(const OpList& ops, size_t i, int nb) {
     }
   }
   std::vector<std::vector<size_t>> groups;
-  if (regroup) {
-    for (size_t k = i; k < w; ++k) {
+  for (size_t k = i; k < w; ++k) {
+    if (regroup) {
       size_t g = 0;
       while (g < groups.size() && ops[groups[g][0]].out != ops[k].out) ++g;
       if (g == groups.size()) groups.emplace_back();
       groups[g].push_back(k);
-    }
-  } else {
-    for (size_t k = i; k < w; ++k) {
+    } else {
       if (groups.empty() || ops[groups.back()[0]].out != ops[k].out) groups.emplace_back();
       groups.back().push_back(k);
     }
   }
-  for (const auto& g : groups)
-    if (!fuse_adds(ops, g))
-      for (size_t k : g) add(ops[k], nb);
+  return groups;
+}
+
+// Runs the Add ops from ops[i] to the next op of another kind, in the groups
+// of add_groups; every group that fits runs as one summed permute.  Returns
+// the index after the run.
+template <typename T>
+size_t Executor<T>::run_adds(const OpList& ops, size_t i, int nb) {
+  size_t w = i;
+  while (w < ops.size() && ops[w].kind == OpKind::Add) ++w;
+  for (const auto& g : add_groups(ops, i, w))
+    if (!fuse_adds(ops, g)) {
+      for (size_t k : g) {
+        LRCC_REQUIRE(ops[k].a != virt_id_, LRCC_E_INTERNAL, "in-place tensor read outside a summed permute");
+        add(ops[k], nb);
+      }
+    }
+  return w;
+}
+
+// An outer product into a 4-index tensor TT[(b)][i][j][p][q] = alpha
+// U[(b)][i][p] V[(b)][j][q] (no contracted index): appends it to s.
+template <typename T>
+bool Executor<T>::outer_product(const Op& o, SumSources& s) {
+  if (o.kind != OpKind::Contract || o.a < 0 || o.b < 0 || s.nouter >= 2) return false;
+  if (o.a == ladder_const || o.b == ladder_const) return false;
+  const std::string c = letters(o.out, o.oi);
+  const int L = (int)c.size();
+  if (!(L == 4 && !m_[o.out].batched) && !(L == 5 && m_[o.out].batched)) return false;
+  const std::string ia = {c[L - 4], c[L - 2]}, jb = {c[L - 3], c[L - 1]};
+  int U, V;
+  if (o.ai == ia && o.bi == jb) {
+    U = o.a, V = o.b;
+  } else if (o.bi == ia && o.ai == jb) {
+    U = o.b, V = o.a;
+  } else {
+    return false;
+  }
+  if (!m_[o.out].batched && (m_[U].batched || m_[V].batched)) return false;
+  if (m_[o.out].batched && !m_[U].batched && !m_[V].batched) return false;
+  const int64_t ni = dim(c[L - 4]), nj = dim(c[L - 3]), np = dim(c[L - 2]), nq = dim(c[L - 1]);
+  if (s.nouter > 0 && (s.ni != ni || s.nj != nj)) return false;
+  const int64_t nbU = m_[U].batched ? g_nb : 1, nbV = m_[V].batched ? g_nb : 1;
+  if (capacity(U) < nbU * ni * np || capacity(V) < nbV * nj * nq) return false;
+  const int c_ = s.nouter++;
+  s.U[c_] = ptr(U);
+  s.V[c_] = ptr(V);
+  s.ustride[c_] = m_[U].batched ? ni * np : 0;
+  s.vstride[c_] = m_[V].batched ? nj * nq : 0;
+  s.ore[c_] = o.are;
+  s.oim[c_] = o.aim;
+  s.ni = ni;
+  s.nj = nj;
+  return true;
+}
+
+// The dressed doubles: one or two outer products into a tensor TT (t1 X1
+// and X1 t1 in the tangents of the CC residual), read only by the
+// permute-accumulate run right after them.  When every group of that run
+// that reads TT fits a summed permute, TT is never stored: those groups
+// evaluate it in place from the (small) outer-product factors.  Returns the
+// index after the ops run, or i when the pattern does not apply.
+template <typename T>
+size_t Executor<T>::run_dressed(const OpList& ops, size_t i, int nb) {
+  const int tt = ops[i].out;
+  if (ops[i].kind != OpKind::Contract || ops[i].acc || bound_[tt]) return i;
+  for (int k : keep_)
+    if (k == tt) return i;
+  SumSources outer{};
+  size_t j = i;
+  while (j < ops.size() && j < i + 2 && ops[j].out == tt && (j == i) != ops[j].acc && outer_product(ops[j], outer)) ++j;
+  if (j == i) return i;
+  size_t w = j;
+  while (w < ops.size() && ops[w].kind == OpKind::Add) ++w;
+  if (w == j) return i;
+  for (size_t k = j; k < ops.size(); ++k) {
+    if (ops[k].out == tt || ops[k].b == tt) return i;
+    if (k >= w && ops[k].a == tt) return i;
+  }
+  virt_id_ = tt;
+  virt_ = outer;
+  bool ok = true;
+  for (const auto& g : add_groups(ops, j, w)) {
+    bool reads = false;
+    for (size_t k : g) reads = reads || ops[k].a == tt;
+    if (reads && !fuse_adds(ops, g, false)) ok = false;
+  }
+  if (!ok) {
+    virt_id_ = -1;
+    return i;
+  }
+  try {
+    run_adds(ops, j, nb);
+  } catch (...) {
+    virt_id_ = -1;
+    throw;
+  }
+  virt_id_ = -1;
   return w;
 }
 
@@ -1003,7 +1102,14 @@ void Executor<T>::run_ops(const OpList& ops, int nb) {
   for (size_t i = 0; i < ops.size(); ++i) {
     const Op& op = ops[i];
     switch (op.kind) {
-      case OpKind::Contract: contract(op, nb); break;
+      case OpKind::Contract: {
+        const size_t j = run_dressed(ops, i, nb);
+        if (j > i)
+          i = j - 1;
+        else
+          contract(op, nb);
+        break;
+      }
       case OpKind::Add: i = run_adds(ops, i, nb) - 1; break;
       case OpKind::Pack: pack(op, nb); break;
       case OpKind::Unpack: unpack(op, nb); break;
@@ -1019,6 +1125,7 @@ template <typename T>
 void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
   LRCC_REQUIRE(nb >= 1 && nb <= max_nb_, LRCC_E_INTERNAL, "batch exceeds executor maximum");
   g_nb = nb;
+  keep_ = keep;
   prepare(ops, nb, keep);
   if (!graphs_on_) {
     run_ops(ops, nb);
