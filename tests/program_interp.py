@@ -126,6 +126,40 @@ class Interp:
         return env
 
 
+def executor_order(ops):
+    """The order in which the executor runs `ops`: within each run of ADD ops
+    it groups the ops by output tensor (each group keeping its order, groups
+    in the order of their first op) when no op of the run reads a tensor that
+    another op of the run writes and no tensor is first written after the
+    run's first op; otherwise it keeps the list order.  Mirrors the grouping
+    rule of the executor's summed permutes."""
+    out, i = [], 0
+    while i < len(ops):
+        if ops[i]["kind"] != ADD:
+            out.append(ops[i])
+            i += 1
+            continue
+        w = i
+        while w < len(ops) and ops[w]["kind"] == ADD:
+            w += 1
+        regroup = w - i >= 2
+        for k in range(i, w):
+            if any(q != k and ops[k]["a"] == ops[q]["out"] for q in range(i, w)):
+                regroup = False
+            if k > i and not any(ops[q]["out"] == ops[k]["out"] for q in range(k)):
+                regroup = False
+        run = ops[i:w]
+        if regroup:
+            heads = []
+            for op in run:
+                if op["out"] not in heads:
+                    heads.append(op["out"])
+            run = [op for h in heads for op in run if op["out"] == h]
+        out.extend(run)
+        i = w
+    return out
+
+
 def _cls(ch):
     return "o" if "i" <= ch <= "n" else "v"
 

@@ -181,6 +181,64 @@ def test_derived_operation_lists_match_oracle(o, v, naux, seed):
         assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
 
 
+def test_executor_regrouping_leaves_every_program_unchanged():
+    """The executor may run a run of permute-accumulates grouped by output
+    tensor (its summed permutes); executed in that order with numpy, every
+    derived program writes exactly the same tensors as in list order, and the
+    regrouping does change the order of some program."""
+    import copy
+
+    from program_interp import executor_order
+    lrcc = _lrcc()
+    o, v, nb = 3, 5, 2
+    inp = make_inputs(o, v, 8, seed=4)
+    B = inp.B * 8
+    rng = np.random.default_rng(4)
+    P = Problem.from_arrays(B, inp.fock, inp.mu, o)
+    n = P.lay.n
+    tens, res_ops = parse(lrcc.program_text(lrcc.PROG_RESIDUAL))
+    I = Interp(tens, o, v, nb)
+    env = {}
+    for k, val in {**blocks_from_df(B, o), **fock_blocks(inp.fock, o)}.items():
+        env[I.id(k)] = val
+    t = torch.as_tensor(0.05 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))
+    t1, t2p = P.lay.split(t)
+    env[I.id("t1")], env[I.id("t2p")], env[I.id("one")] = t1.numpy(), t2p.numpy(), np.array(1.0 + 0j)
+    l1, l2 = P.lay.split(torch.as_tensor(0.02 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))))
+    env[I.id("lam1")], env[I.id("lam2p")] = l1.numpy(), l2.numpy()
+    X = [torch.as_tensor(rng.standard_normal(n) + 1j * rng.standard_normal(n)) for _ in range(nb)]
+    for pre in ("R", "L", "H", "F"):
+        x1, x2 = _batch(P.lay, X)
+        src = ("L(O1)", "L(O2p)") if pre == "L" else (f"{pre}(t1)", f"{pre}(t2p)")
+        env[I.id(src[0])], env[I.id(src[1])] = x1, x2
+    for nm in ("foo", "fov", "fvo", "fvv"):
+        blk = np.stack([fock_blocks(inp.mu[c], o)[nm] for c in (0, 2)])
+        env[I.id(f"X({nm})")] = blk
+        env[I.id(f"H({nm})")] = blk
+    changed = 0
+    for which in (lrcc.PROG_RESIDUAL, lrcc.PROG_RIGHT, lrcc.PROG_LEFT, lrcc.PROG_ETA0, lrcc.PROG_XI,
+                  lrcc.PROG_GRADL, lrcc.PROG_HVP, lrcc.PROG_FX):
+        _, ops = parse(lrcc.program_text(which))
+        order = executor_order(ops)
+        assert sorted(map(id, order)) == sorted(map(id, ops))
+        changed += order != ops
+        e1, e2 = I.run(ops, copy.deepcopy(env)), I.run(order, copy.deepcopy(env))
+        for k in {op["out"] for op in ops}:
+            assert np.array_equal(e1[k], e2[k]), (which, tens[k]["name"])
+        env = e1
+    assert changed >= 2
+    # synthetic runs where the conditions decide (ids: 10, 11, 12 written; 20, 21 read only)
+    add = lambda out, a, acc: dict(kind=0, acc=acc, alpha=1.0, out=out, oi="ab", a=a, ai="ab", b=-1, bi="", m=(0, 0))
+    zero = lambda out: dict(kind=4, acc=False, alpha=1.0, out=out, oi="ab", a=-1, ai="", b=-1, bi="", m=(0, 0))
+    pre = [zero(10), zero(11)]  # 10 and 11 written before the runs
+    free = pre + [add(10, 20, True), add(11, 21, True), add(10, 21, True)]
+    assert [op["out"] for op in executor_order(free)[2:]] == [10, 10, 11]  # regrouped by output
+    reads = pre + [add(10, 20, True), add(11, 10, True), add(10, 21, True)]  # 11 reads 10 mid-run
+    assert executor_order(reads) == reads
+    first = pre + [add(10, 20, True), add(12, 21, False), add(10, 21, True)]  # 12 first written mid-run
+    assert executor_order(first) == first
+
+
 def test_fnspp_projection_list_matches_oracle():
     """The FNS++ numerators (Eq. 48 and the singles projection), before the
     denominators of Eqs. 46-47 are applied."""
