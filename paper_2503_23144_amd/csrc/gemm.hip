@@ -91,6 +91,16 @@ constexpr int PADR = 16;
 constexpr int64_t GM = 8;
 // Products at most this wide (n) use the 128 x 32 tile.
 constexpr int64_t kNarrow = 32;
+
+// Split products run on the 128 x 32 tile when they are narrow or when its
+// grid pads the m x n output at least 10 % less than the 64 x 64 grid (n = 150:
+// 160 columns instead of 192).
+static bool split_narrow(int64_t m, int64_t n) {
+  if (n <= kNarrow) return true;
+  const double p64 = (double)((m + 63) / 64 * 64) * (double)((n + 63) / 64 * 64);
+  const double p32 = (double)((m + 127) / 128 * 128) * (double)((n + 31) / 32 * 32);
+  return p32 < 0.9 * p64;
+}
 __device__ inline void tile_of(int64_t bid, int64_t nbm, int64_t nbn, int64_t& tm, int64_t& tn) {
   const int64_t total = nbm * nbn;
   int64_t id = bid;
@@ -549,8 +559,8 @@ static int forced_tile() {
 
 void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 4 ? tile : -1); }
 
-// Split-K for deep products whose tile grid (64 x 64, or 128 x 32 for
-// narrow products) fills the chip poorly.  The chip holds `slots` resident
+// Split-K for deep products whose tile grid (64 x 64, or 128 x 32 where
+// split_narrow says so) fills the chip poorly.  The chip holds `slots` resident
 // workgroups (64 x 64: four per CU in FP32, two in FP64; 128 x 32: three in
 // FP32, two in FP64); a grid of w workgroups runs in ceil(w / slots) rounds,
 // so its efficiency is w / (rounds * slots).  The depth is split s ways (at
@@ -559,7 +569,7 @@ void set_gemm_tile(int tile) { g_forced_tile.store(tile >= 0 && tile <= 4 ? tile
 // gains at least 15 % over no split.
 int gemm_splits(int64_t m, int64_t n, int64_t k, bool fp64) {
   if (k < 2048) return 1;
-  const bool nar = n <= kNarrow;
+  const bool nar = split_narrow(m, n);
   const int64_t tiles = nar ? ((m + 127) / 128) * ((n + 31) / 32) : ((m + 63) / 64) * ((n + 63) / 64);
   const int64_t slots = nar ? (fp64 ? 512 : 768) : (fp64 ? 512 : 1024);
   const int64_t part = m * n * (fp64 ? 16 : 8);
@@ -597,8 +607,8 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
       if (trace_on())
         fprintf(stderr, "[lrcc gemm] %s ta=%d tb=%d kind=%d m=%lld n=%lld k=%lld tile=%d splits=%d\n",
                 sizeof(T) == 8 ? "c128" : "c64", (int)ta, (int)tb, kind, (long long)m, (long long)n, (long long)k,
-                n <= kNarrow ? 4 : 0, splits);
-      if (n <= kNarrow) {
+                split_narrow(m, n) ? 4 : 0, splits);
+      if (split_narrow(m, n)) {
         if (kind == 1)
           go<T, 1, 128, 32, 4>(ta, tb, m, n, k, are, aim, A, lda, B, ldb, bre, bim, C, om, st, splits, ws, conj_b);
         else

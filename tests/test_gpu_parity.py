@@ -55,7 +55,7 @@ def test_gemm_matches_host_matmul(dtype, ta, tb, m, n, k):
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
 @pytest.mark.parametrize("m,n,k", [(37, 53, 5000), (64, 64, 20011), (1, 7, 3000), (200, 10, 4100), (130, 3, 70000),
-                                   (300, 32, 9000), (1000, 1, 3000)])
+                                   (300, 32, 9000), (1000, 1, 3000), (960, 150, 9000)])
 def test_gemm_split_depth_matches_host_matmul(dtype, ta, tb, m, n, k):
     """Deep products with few output tiles run split over K (partial tiles
     reduced in a second kernel); alpha and beta apply after the reduction."""
