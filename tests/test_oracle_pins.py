@@ -392,3 +392,85 @@ def test_fns_no_truncation_is_exact_and_captured_norm():
     # and the truncated space keeps the largest occupations
     _, n4, _ = fns_transform(B, inp.fock, inp.mu, o, keep=4)
     assert np.allclose(np.sort(np.abs(n4))[::-1], np.abs(n4))
+
+
+# ---------------------------------------------------------------- Hbar diagonals (Eqs. 49-50)
+def _antisym_from_factors(B, p_sl, q_sl, r_sl, s_sl):
+    """<pq||rs> = (pr|qs) - (ps|qr) with (pr|qs) = sum_Q B^Q_pr B^Q_qs,
+    accumulated one auxiliary index at a time (no shared helper)."""
+    B = np.asarray(B)
+    out = 0.0
+    for Q in range(B.shape[0]):
+        pr, qs = B[Q][p_sl, r_sl], B[Q][q_sl, s_sl]
+        ps, qr = B[Q][p_sl, s_sl], B[Q][q_sl, r_sl]
+        out = out + pr[:, None, :, None] * qs[None, :, None, :] - ps[:, None, None, :] * qr[None, :, :, None]
+    return out
+
+
+def test_hbar_diagonals_are_closed_form_mp2_sums():
+    """With the MP2 doubles of Eq. 39, Eqs. 49-50 reduce per index to
+    Hbar_ii - F_ii =  sum_{n, e<f} |<in||ef>|^2 / (e_i + e_n - e_e - e_f) and
+    Hbar_aa - F_aa = -sum_{m<n, f} |<mn||fa>|^2 / (e_m + e_n - e_f - e_a),
+    and their traces are +2 E_MP2 and -2 E_MP2 (E_MP2 the closed form of
+    Eq. 39); the integrals are formed here directly from the factors."""
+    o, v = 3, 6
+    inp = make_inputs(o, v, 8, seed=12)
+    B = inp.B * 8.0
+    _, Hii, Haa = mp2_and_hbar(B, inp.fock, o)
+    Hii, Haa = Hii.numpy(), Haa.numpy()
+    e = np.real(np.diag(inp.fock))
+    so, sv = slice(0, o), slice(o, o + v)
+    g = _antisym_from_factors(B, so, so, sv, sv)           # <ij||ab>
+    ref_i = np.zeros(o)
+    for i in range(o):
+        for n in range(o):
+            for a in range(v):
+                for b in range(a + 1, v):
+                    ref_i[i] += abs(g[i, n, a, b]) ** 2 / (e[i] + e[n] - e[o + a] - e[o + b])
+    ref_a = np.zeros(v)
+    for a in range(v):
+        for m in range(o):
+            for n in range(m + 1, o):
+                for f in range(v):
+                    ref_a[a] -= abs(g[m, n, f, a]) ** 2 / (e[m] + e[n] - e[o + f] - e[o + a])
+    scale = np.abs(ref_i).max()
+    assert scale > 1e-6
+    assert np.abs((Hii - e[:o]) - ref_i).max() < 1e-13 * scale
+    assert np.abs((Haa - e[o:]) - ref_a).max() < 1e-13 * np.abs(ref_a).max()
+    emp2 = 0.0
+    for i in range(o):
+        for j in range(i + 1, o):
+            for a in range(v):
+                for b in range(a + 1, v):
+                    emp2 += abs(g[i, j, a, b]) ** 2 / (e[i] + e[j] - e[o + a] - e[o + b])
+    assert abs(np.sum(Hii - e[:o]) - 2 * emp2) < 1e-13 * abs(emp2)
+    assert abs(np.sum(Haa - e[o:]) + 2 * emp2) < 1e-13 * abs(emp2)
+
+
+def test_mp2_level_alpha_uses_f_as_symmetric_correctly():
+    """The MP2-level alpha applies F once per X^B(w) and uses its symmetry
+    for f_AB(-w); it must equal Eq. 36 evaluated with F X^A(-w) applied
+    explicitly, component by component, in a case where alpha is far from
+    symmetric in (A, B) and the F term is large."""
+    from oracle.mp2 import first_order, hbar_denominators, mp2_level
+    from oracle.response import alpha_eq36_from
+    o, v = 3, 5
+    inp = make_inputs(o, v, 8, seed=5)
+    B = inp.B * 8.0
+    w = 0.13
+    _, al = mp2_level(B, inp.fock, inp.mu, o, [w])
+    t1, l1, P = first_order(B, inp.fock, inp.mu, o)
+    Dbar = hbar_denominators(P, B, inp.fock)
+    comps = (0, 1, 2)
+    xis = [xi(P, t1, c) for c in comps]
+    etas = [eta(P, t1, l1, c) for c in comps]
+    Xp = [-x / (Dbar - w) for x in xis]
+    Xm = [-x / (Dbar + w) for x in xis]
+    FXp = [F_times(P, t1, l1, X) for X in Xp]
+    FXm = [F_times(P, t1, l1, X) for X in Xm]
+    ref = alpha_eq36_from(etas, Xp, Xm, FXp, FXm)
+    assert np.abs(al[0] - ref).max() < 1e-12 * np.abs(ref).max()
+    # the case is not symmetric in (A, B) and the F term matters at the tolerance
+    fterm = np.array([[complex(bdot(Xm[a], FXp[b])) for b in range(3)] for a in range(3)])
+    assert np.abs(fterm - fterm.T).max() > 1e-6 * np.abs(ref).max()
+    assert np.abs(fterm).max() > 1e-6 * np.abs(ref).max()
