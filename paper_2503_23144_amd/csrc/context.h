@@ -138,6 +138,16 @@ struct Context {
   int sigma_chunk(Side side, int nvec, int prec);  // right-hand sides per product that fit free memory
   int64_t sigma_count = 0;
   void sync() { HIP_CHECK(hipStreamSynchronize(st)); }
+  // Host <-> device copies ordered on the context's stream; they return once
+  // the copy is complete (the host buffer may be reused at once).
+  void h2d(void* dst, const void* src, size_t bytes) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    sync();
+  }
+  void d2h(void* dst, const void* src, size_t bytes) {
+    HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+    sync();
+  }
   void require_sizes() const;
   void upload_fock_blocks();
   void build_integrals();

@@ -159,7 +159,7 @@ static void* mp2_doubles(Context& c) {
   const size_t n2f = (size_t)c.o * c.o * c.v * c.v;
   DevBuf epsd;
   epsd.ensure(c.nmo * 8);
-  HIP_CHECK(hipMemcpy(epsd.p, c.eps.data(), c.nmo * 8, hipMemcpyHostToDevice));
+  c.h2d(epsd.p, c.eps.data(), c.nmo * 8);
   void* tm2 = c.x64->ptr(c.P.n_t2);
   hipLaunchKernelGGL(mp2_kernel, dim3(grid_of(n2f)), dim3(256), 0, c.st, c.o, c.v,
                      (const double2*)c.x64->ptr(c.P.m.find("gvvoo")), epsd.as<double>(), (double2*)tm2);
@@ -209,8 +209,8 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
   hbar_diagonals(Hii, Haa);
   DevBuf Hd;
   Hd.ensure((oo + vv) * 8);
-  HIP_CHECK(hipMemcpy(Hd.p, Hii.data(), oo * 8, hipMemcpyHostToDevice));
-  HIP_CHECK(hipMemcpy((char*)Hd.p + oo * 8, Haa.data(), vv * 8, hipMemcpyHostToDevice));
+  h2d(Hd.p, Hii.data(), oo * 8);
+  h2d((char*)Hd.p + oo * 8, Haa.data(), vv * 8);
   // 3-4. projections per direction, first-order amplitudes per frequency,
   // and the averaged Gram density
   DevBuf Dm, t1A, t2A, P2, P2c, P1, P1c;
@@ -298,7 +298,7 @@ void Context::truncate_by_density(const void* Dmp, double thresh, int keep, int*
   Ft.ensure((size_t)nk * nk * 16);
   Ud.ensure(vv * nk * 16);
   Zd.ensure((size_t)nk * nk * 16);
-  HIP_CHECK(hipMemcpy(Vd.p, Vt.data(), vv * nk * 16, hipMemcpyHostToDevice));
+  h2d(Vd.p, Vt.data(), vv * nk * 16);
   launch_gather_block(1, nmo, o, v, o, v, fock.p, Fv.p, st);
   launch_gemm<double>(false, false, vv, nk, vv, 1.0, 0.0, Fv.p, vv, Vd.p, nk, 0.0, 0.0, Y.p, nk, st);
   conj_copy(vv * nk, Vd.p, Vc.p, st);
@@ -306,18 +306,18 @@ void Context::truncate_by_density(const void* Dmp, double thresh, int keep, int*
   std::vector<double> et;
   std::vector<cplx> Z;
   sol.eigh(nk, Ft.p, et, Z, st);
-  HIP_CHECK(hipMemcpy(Zd.p, Z.data(), (size_t)nk * nk * 16, hipMemcpyHostToDevice));
+  h2d(Zd.p, Z.data(), (size_t)nk * nk * 16);
   launch_gemm<double>(false, false, vv, nk, nk, 1.0, 0.0, Vd.p, nk, Zd.p, nk, 0.0, 0.0, Ud.p, nk, st);
   // 7. C = diag(1_occ, U) and the rotated inputs
   const int64_t m = o + nk;
   std::vector<cplx> Uh((size_t)vv * nk), C((size_t)nmo * m, 0.0);
-  HIP_CHECK(hipMemcpy(Uh.data(), Ud.p, vv * nk * 16, hipMemcpyDeviceToHost));
+  d2h(Uh.data(), Ud.p, vv * nk * 16);
   for (int64_t i = 0; i < o; ++i) C[i * m + i] = 1.0;
   for (int64_t a = 0; a < vv; ++a)
     for (int k = 0; k < nk; ++k) C[(o + a) * m + o + k] = Uh[a * nk + k];
   DevBuf Cd, Bn, Fn, Mn;
   Cd.ensure((size_t)nmo * m * 16);
-  HIP_CHECK(hipMemcpy(Cd.p, C.data(), (size_t)nmo * m * 16, hipMemcpyHostToDevice));
+  h2d(Cd.p, C.data(), (size_t)nmo * m * 16);
   Bn.ensure((size_t)naux * m * m * 16);
   Fn.ensure((size_t)m * m * 16);
   Mn.ensure((size_t)ncomp * m * m * 16);
@@ -359,7 +359,7 @@ void Context::mp2_response(int nw, const double* om, cplx& emp2, std::vector<cpl
   DevBuf hbd, Dbar;
   hbd.ensure(nmo * 8);
   Dbar.ensure(n * 8);
-  HIP_CHECK(hipMemcpy(hbd.p, hb.data(), nmo * 8, hipMemcpyHostToDevice));
+  h2d(hbd.p, hb.data(), nmo * 8);
   launch_denominators(o, v, hbd.as<double>(), Dbar.as<double>(), st);
   {
     std::vector<double> hD(n);

@@ -200,7 +200,7 @@ void Context::load_fock(const void* F, int where) {
   fock.ensure(nmo * nmo * 16);
   copy_in(fock.p, F, nmo * nmo * 16, where, st);
   std::vector<cplx> h(nmo * nmo);
-  HIP_CHECK(hipMemcpy(h.data(), fock.p, nmo * nmo * 16, hipMemcpyDeviceToHost));
+  d2h(h.data(), fock.p, nmo * nmo * 16);
   double herm = 0, scale = 0;
   for (int64_t p = 0; p < nmo; ++p)
     for (int64_t q = 0; q < nmo; ++q) {
@@ -215,7 +215,7 @@ void Context::load_fock(const void* F, int where) {
   LRCC_REQUIRE(emin_v - emax_o > 1e-8, LRCC_E_SINGULAR, "no gap between occupied and virtual Fock diagonals");
   DevBuf e;
   e.ensure(nmo * 8);
-  HIP_CHECK(hipMemcpy(e.p, eps.data(), nmo * 8, hipMemcpyHostToDevice));
+  h2d(e.p, eps.data(), nmo * 8);
   D.ensure(n * 8);
   launch_denominators(o, v, e.as<double>(), D.as<double>(), st);
   upload_fock_blocks();
@@ -230,7 +230,7 @@ void Context::load_dipoles(int nc, const void* m, int where) {
   mu.ensure(nc * nmo * nmo * 16);
   copy_in(mu.p, m, nc * nmo * nmo * 16, where, st);
   std::vector<cplx> h(nc * nmo * nmo);
-  HIP_CHECK(hipMemcpy(h.data(), mu.p, h.size() * 16, hipMemcpyDeviceToHost));
+  d2h(h.data(), mu.p, h.size() * 16);
   for (int c = 0; c < nc; ++c)
     for (int64_t p = 0; p < nmo; ++p)
       for (int64_t q = 0; q <= p; ++q) {
@@ -895,7 +895,7 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
   // a frequency on a denominator makes (A -/+ w) singular in the Jacobi metric
   {
     std::vector<double> hD(n);
-    HIP_CHECK(hipMemcpy(hD.data(), D.p, n * 8, hipMemcpyDeviceToHost));
+    d2h(hD.data(), D.p, n * 8);
     for (int k = 0; k < nw; ++k)
       for (int64_t i = 0; i < n; ++i)
         LRCC_REQUIRE(std::abs(hD[i] - std::abs(om[k])) >= 1e-8, LRCC_E_SINGULAR,

@@ -406,6 +406,33 @@ def test_fns_truncation_matches_oracle():
     assert _relerr(c.alpha(1), ref.alpha) < 1e-8
 
 
+@pytest.mark.parametrize("scheme", ["fnspp", "fns"])
+def test_truncation_on_a_side_stream_matches_null_stream(scheme):
+    """Every host transfer of the truncation is ordered on the context's
+    stream: on a non-blocking torch stream the occupations, the kept count
+    and the alpha of the truncated space equal those of a null-stream run."""
+    o, v, keep = 3, 10, 6
+    inp = make_inputs(o, v, 12, seed=33)
+    inp.B = inp.B * 8.0
+    out = []
+    for side in (False, True):
+        st = torch.cuda.Stream() if side else None
+        kw = {"stream": st.cuda_stream} if side else {}
+        c = _ctx(inp, **kw)
+        if scheme == "fnspp":
+            nk, occ = c.fnspp_truncate([0.05, 0.1], keep=keep)
+        else:
+            nk, occ = c.fns_truncate(keep=keep)
+        c.solve_ground()
+        c.solve_lambda()
+        c.solve_response([0.1])
+        out.append((nk, np.asarray(occ), c.alpha(1)))
+        c.close()
+    assert out[0][0] == out[1][0] == keep
+    assert _relerr(out[1][1], out[0][1]) < 1e-12
+    assert _relerr(out[1][2], out[0][2]) < 1e-12
+
+
 def test_fnspp_without_truncation_keeps_alpha():
     inp = make_inputs(3, 8, 10, seed=32)
     inp.B = inp.B * 8.0
