@@ -224,6 +224,22 @@ int lrcc_gemm(int precision, int transa, int transb, int64_t m, int64_t n, int64
               const double alpha[2], const void *A, int64_t lda, const void *B, int64_t ldb,
               const double beta[2], void *C, int64_t ldc, void *stream);
 
+/* The product of lrcc_gemm, for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): it calls no hipMalloc, hipFree or other allocating routine.
+   Same arguments, layout and results as lrcc_gemm (the same split over K and
+   tile choice; a shape never seen before takes the size heuristic instead of
+   being timed).  The split-K partials of deep products live in a static
+   device array of 256 MiB per GPU, held from the first call on that GPU until
+   the process ends; a product whose partials would not fit returns
+   LRCC_E_INVALID (the library caps its splits at that size, so none does
+   today).  Fully asynchronous on `stream`.  Every call on one GPU uses the
+   same array: calls that overlap in time on one GPU (different streams)
+   race on it and must be ordered by the caller. */
+int lrcc_gemm_noalloc(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k,
+                      const double alpha[2], const void *A, int64_t lda, const void *B, int64_t ldb,
+                      const double beta[2], void *C, int64_t ldc, void *stream);
+
 /* Workgroup tile of every later unsplit GEMM launch, process-wide:
    -1 = automatic (the autotuner when a context enables it, else a size
    heuristic; products at most 32 wide take tile 4); 0 = 64 x 64, 1 = 128 x

@@ -19,7 +19,7 @@ OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrcc.so")
 
 SOURCES = ["program.cpp", "devmem.hip", "kernels.hip", "gemm.hip", "runtime.hip", "integrals.hip", "solver.hip", "fnspp.hip",
-           "abi.hip"]
+           "abi.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",

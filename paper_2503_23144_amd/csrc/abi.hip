@@ -22,6 +22,12 @@ struct lrcc_ctx {
 
 static thread_local std::string g_create_error;
 
+namespace lrcc {
+// Message of the last failing context-free call on this thread (read with
+// lrcc_last_error(NULL)).
+void set_call_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace lrcc
+
 template <typename F>
 static int guard(lrcc_ctx* ctx, F&& f) {
   if (!ctx || !ctx->impl) return LRCC_E_INVALID;

@@ -26,6 +26,9 @@ struct Error : std::runtime_error {
                           std::string(#expr) + ": " + hipGetErrorString(e_));             \
   } while (0)
 
+// Sets the message lrcc_last_error(NULL) returns on this thread.
+void set_call_error(const std::string& msg);
+
 enum class Prec { F64 = 0, F32 = 1 };
 
 inline size_t cbytes(Prec p) { return p == Prec::F64 ? 16 : 8; }

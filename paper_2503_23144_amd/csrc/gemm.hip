@@ -598,7 +598,8 @@ size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k) {
 template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
-                 hipStream_t st, int kind, void* ws, size_t ws_bytes, const OutMap* omap, bool conj_b) {
+                 hipStream_t st, int kind, void* ws, size_t ws_bytes, const OutMap* omap, bool conj_b,
+                 bool allow_tune) {
   if (m <= 0 || n <= 0) return;
   const OutMap om = omap ? *omap : OutMap::plain(ldc);
   {
@@ -649,7 +650,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
       if (it != g_tune.end())
         cfg = it->second;
       else
-        tune = !capturing && forced_tile() < 0;
+        tune = allow_tune && !capturing && forced_tile() < 0;
     }
   }
   const bool small = (double)m * n * k < 1e8;  // not worth timing
@@ -696,10 +697,10 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
 
 template void launch_gemm<double>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                   const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                  size_t, const OutMap*, bool);
+                                  size_t, const OutMap*, bool, bool);
 template void launch_gemm<float>(bool, bool, int64_t, int64_t, int64_t, double, double, const void*, int64_t,
                                  const void*, int64_t, double, double, void*, int64_t, hipStream_t, int, void*,
-                                 size_t, const OutMap*, bool);
+                                 size_t, const OutMap*, bool, bool);
 template size_t gemm_workspace_bytes<double>(int64_t, int64_t, int64_t);
 template size_t gemm_workspace_bytes<float>(int64_t, int64_t, int64_t);
 

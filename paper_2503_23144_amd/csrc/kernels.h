@@ -99,7 +99,8 @@ template <typename T>
 void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim, const void* A,
                  int64_t lda, const void* B, int64_t ldb, double bre, double bim, void* C, int64_t ldc,
                  hipStream_t st, int kind = 0, void* ws = nullptr, size_t ws_bytes = 0,
-                 const OutMap* om = nullptr, bool conj_b = false);  // conj_b: use conj(B)
+                 const OutMap* om = nullptr, bool conj_b = false,  // conj_b: use conj(B)
+                 bool allow_tune = true);  // false: never time candidate tiles (no device allocation)
 int gemm_splits(int64_t m, int64_t n, int64_t k, bool fp64);
 template <typename T>
 size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k);

@@ -76,6 +76,7 @@ _sig = {
     "lrcc_get_amplitudes": (_i, [_vp, _i, _i, _vp, _i]),
     "lrcc_set_amplitudes": (_i, [_vp, _i, _i, _vp, _i]),
     "lrcc_gemm": (_i, [_i, _i, _i, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp]),
+    "lrcc_gemm_noalloc": (_i, [_i, _i, _i, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp]),
     "lrcc_gemm_set_tile": (_i, [_i]),
     "lrcc_program_text": (_i64, [_i, ctypes.c_char_p, _i64]),
     "lrcc_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
@@ -148,9 +149,11 @@ def trim_memory():
         raise LrccError(rc, lib.lrcc_last_error(None).decode())
 
 
-def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
+def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None, noalloc=False):
     """C = alpha op(A) op(B) + beta C on contiguous 2-D device tensors
-    (complex128: FP64 path; complex64: FP32 3M path)."""
+    (complex128: FP64 path; complex64: FP32 3M path).  noalloc=True calls
+    lrcc_gemm_noalloc (no device allocation; split-K partials in the
+    library's static scratch)."""
     import torch
     prec = FP64 if A.dtype == torch.complex128 else MIXED
     m = A.shape[1] if transa else A.shape[0]
@@ -160,8 +163,9 @@ def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
     be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
-    rc = lib.lrcc_gemm(prec, int(transa), int(transb), m, n, k, al, A.data_ptr(), A.shape[1], B.data_ptr(),
-                       B.shape[1], be, C.data_ptr(), C.shape[1], stream)
+    fn = lib.lrcc_gemm_noalloc if noalloc else lib.lrcc_gemm
+    rc = fn(prec, int(transa), int(transb), m, n, k, al, A.data_ptr(), A.shape[1], B.data_ptr(),
+            B.shape[1], be, C.data_ptr(), C.shape[1], stream)
     if rc != OK:
         raise LrccError(rc, lib.lrcc_last_error(None).decode())
     return C
