@@ -93,11 +93,28 @@ typedef struct lrcc_config {
                             LRCC_LADDER_TRIANGLE the upper triangle in row blocks (about half);
                             the lower part is read as conj(W^T), W being Hermitian.
                             Results agree with the full W to rounding. */
+  int ladder_mode_fp64;  /* storage of W for the FP64 products of LRCC_MIXED (certification, xi, eta):
+                            -1 (default) the same as ladder_mode, else one of the LRCC_LADDER_*
+                            values; e.g. FULL FP32 W with a DIRECT FP64 ladder keeps one W in HBM.
+                            Ignored with LRCC_FP64 (ladder_mode applies). */
+  int memory_mode;       /* LRCC_MEMORY_AUTO (default): LEAN when the RESIDENT footprint of one
+                            right-hand side would exceed half the device memory;
+                            LRCC_MEMORY_RESIDENT: every integral block dense in HBM;
+                            LRCC_MEMORY_LEAN: <ov||vv> only packed over its last pair, and
+                            <vv||vo>, <vv||oo> not stored (they equal the conjugates of <ov||vv>
+                            and <oo||vv> up to an index order and sign, B being Hermitian); each
+                            contraction forms the dense block it reads in chunks of at most 1 GiB.
+                            Intermediates only one product reads are freed after it in every mode.
+                            Results agree between modes to rounding. */
 } lrcc_config;
 
 #define LRCC_LADDER_FULL 0
 #define LRCC_LADDER_DIRECT 1
 #define LRCC_LADDER_TRIANGLE 2
+
+#define LRCC_MEMORY_AUTO 0
+#define LRCC_MEMORY_RESIDENT 1
+#define LRCC_MEMORY_LEAN 2
 
 typedef struct lrcc_stats {
   int iterations;        /* iterations taken */

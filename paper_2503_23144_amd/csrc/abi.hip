@@ -81,6 +81,9 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->verbose = 0;
   const char* g = std::getenv("LRCC_GRAPHS");  // default override, e.g. for profiling launch by launch
   cfg->graphs = (g && g[0] == '0') ? 0 : 1;
+  cfg->ladder_mode = LRCC_LADDER_FULL;
+  cfg->ladder_mode_fp64 = -1;
+  cfg->memory_mode = LRCC_MEMORY_AUTO;
 }
 
 int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
@@ -93,6 +96,10 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
     LRCC_REQUIRE(c.precision == LRCC_FP64 || c.precision == LRCC_MIXED, LRCC_E_INVALID, "bad precision");
     LRCC_REQUIRE(c.ladder_mode >= LRCC_LADDER_FULL && c.ladder_mode <= LRCC_LADDER_TRIANGLE, LRCC_E_INVALID,
                  "bad ladder_mode");
+    LRCC_REQUIRE(c.ladder_mode_fp64 >= -1 && c.ladder_mode_fp64 <= LRCC_LADDER_TRIANGLE, LRCC_E_INVALID,
+                 "bad ladder_mode_fp64");
+    LRCC_REQUIRE(c.memory_mode >= LRCC_MEMORY_AUTO && c.memory_mode <= LRCC_MEMORY_LEAN, LRCC_E_INVALID,
+                 "bad memory_mode");
     LRCC_REQUIRE(c.tol_residual > 0 && c.maxit > 0 && c.diis_size >= 0 && c.diis_size <= 32 && c.rhs_chunk >= 0,
                  LRCC_E_INVALID, "bad tolerance, iteration limit, DIIS size or chunk");
     int ndev = 0;

@@ -71,6 +71,8 @@ struct Context {
   std::unique_ptr<Executor<double>> x64;
   std::unique_ptr<Executor<float>> x32;
 
+  bool lean = false;         // LRCC_MEMORY_LEAN in effect (decided by load_df)
+  int mode64 = 0, mode32 = 0;  // storage of W for the FP64 and the FP32 executor (LRCC_LADDER_*)
   DevBuf B, fock, mu, D;     // FP64 inputs; D = real denominators [n]
   DevBuf L64, L32;           // DF-direct ladder: virtual-virtual block of B [naux][v][v] per precision
   DevBuf Tri64, Tri32;       // Hermitian-triangle ladder: row blocks of W's upper triangle per precision

@@ -28,7 +28,8 @@ namespace lrcc {
 
 namespace {
 
-// t[i][j][a][b] = g[a][b][i][j] / (e_i + e_j - e_a - e_b)   (g = <ab||ij>)
+// t[i][j][a][b] = <ab||ij> / (e_i + e_j - e_a - e_b) = conj <ij||ab> / (...)
+// (g = <ij||ab>, [i][j][a][b]; the factors are Hermitian)
 __global__ void mp2_kernel(int64_t o, int64_t v, const double2* __restrict__ g, const double* __restrict__ eps,
                            double2* __restrict__ t) {
   int64_t n = o * o * v * v;
@@ -38,8 +39,8 @@ __global__ void mp2_kernel(int64_t o, int64_t v, const double2* __restrict__ g, 
     r /= v;
     int64_t j = r % o, i = r / o;
     double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
-    double2 x = g[((a * v + b) * o + i) * o + j];
-    t[k] = (i == j || a == b) ? double2{0.0, 0.0} : double2{x.x / d, x.y / d};
+    double2 x = g[k];
+    t[k] = (i == j || a == b) ? double2{0.0, 0.0} : double2{x.x / d, -x.y / d};
   }
 }
 
@@ -162,7 +163,7 @@ static void* mp2_doubles(Context& c) {
   c.h2d(epsd.p, c.eps.data(), c.nmo * 8);
   void* tm2 = c.x64->ptr(c.P.n_t2);
   hipLaunchKernelGGL(mp2_kernel, dim3(grid_of(n2f)), dim3(256), 0, c.st, c.o, c.v,
-                     (const double2*)c.x64->ptr(c.P.m.find("gvvoo")), epsd.as<double>(), (double2*)tm2);
+                     (const double2*)c.x64->ptr(c.P.m.find("goovv")), epsd.as<double>(), (double2*)tm2);
   HIP_CHECK(hipGetLastError());
   HIP_CHECK(hipStreamSynchronize(c.st));  // before epsd is released
   return tm2;

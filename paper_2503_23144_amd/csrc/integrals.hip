@@ -32,7 +32,7 @@ constexpr size_t kChunkBytes = size_t(1) << 30;
 }  // namespace
 
 void build_block(const void* Bdev, int64_t naux, int64_t o, int64_t v, const std::string& spec, void* dst,
-                 hipStream_t st) {
+                 hipStream_t st, bool pack_last) {
   const int64_t nmo = o + v;
   auto start = [&](char c) { return c == 'o' ? int64_t(0) : o; };
   auto len = [&](char c) { return c == 'o' ? o : v; };
@@ -47,9 +47,12 @@ void build_block(const void* Bdev, int64_t naux, int64_t o, int64_t v, const std
   const int64_t per_p = nq * nr * ns * 16;
   int64_t pc = std::max<int64_t>(1, std::min<int64_t>(np, (int64_t)kChunkBytes / per_p));
   DevTmp tmp(pc * per_p);
+  // with pack_last, each chunk is formed densely here and packed over (r < s)
+  LRCC_REQUIRE(!pack_last || R == S, LRCC_E_INTERNAL, "packed block needs equal last classes");
+  DevTmp dense(pack_last ? pc * per_p : 16);
   for (int64_t p0 = 0; p0 < np; p0 += pc) {
     int64_t pn = std::min(pc, np - p0);
-    char* out = (char*)dst + p0 * per_p;
+    char* out = pack_last ? (char*)dense.p : (char*)dst + p0 * per_p;
     // Coulomb (pr|qs): rows (p, r), columns (q, s)
     launch_gemm<double>(true, false, pn * nr, nq * ns, naux, 1.0, 0.0, (const char*)LPR.p + p0 * nr * 16, np * nr,
                         LQS.p, nq * ns, 0.0, 0.0, tmp.p, nq * ns, st);
@@ -63,6 +66,7 @@ void build_block(const void* Bdev, int64_t naux, int64_t o, int64_t v, const std
                         LQR.p, nq * nr, 0.0, 0.0, tmp.p, nq * nr, st);
     d.istride[0] = ns * nq * nr, d.istride[1] = nr, d.istride[2] = 1, d.istride[3] = nq * nr;
     launch_permute<double>(tmp.p, out, d, -1.0, 0.0, 1.0, 0.0, st);
+    if (pack_last) pack_last_pair(out, pn, nq, nr, (char*)dst + p0 * nq * (nr * (nr - 1) / 2) * 16, st);
   }
   HIP_CHECK(hipStreamSynchronize(st));
 }
@@ -88,6 +92,7 @@ void build_packed_vvvv(const void* Bdev, int64_t naux, int64_t o, int64_t v, voi
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
+template <typename TO>
 void build_vvvv_triangle(const void* Lvv, int64_t naux, int64_t v, const std::vector<int64_t>& bnd,
                          const std::vector<int64_t>& offs, void* dst, hipStream_t st) {
   const int64_t V = v * (v - 1) / 2;
@@ -108,13 +113,18 @@ void build_vvvv_triangle(const void* Lvv, int64_t naux, int64_t v, const std::ve
       launch_gemm<double>(true, false, (c1 - c0) * v, c1 * v, naux, 1.0, 0.0, (const char*)Lvv + c0 * v * 16, v * v,
                           Lvv, v * v, 0.0, 0.0, C.p, c1 * v, st);
       launch_pack_wrows<double>(v, c0, c1, C.p, Wc.p, st);
-      launch_copy_rows<double, double>(R(c1) - R(c0), ld, (const char*)Wc.p + r0 * 16, V,
-                                       (char*)dst + (offs[j] + (R(c0) - r0) * ld) * 16, ld, st);
+      launch_copy_rows<double, TO>(R(c1) - R(c0), ld, (const char*)Wc.p + r0 * 16, V,
+                                   (char*)dst + (offs[j] + (R(c0) - r0) * ld) * 2 * sizeof(TO), ld, st);
       c0 = c1;
     }
   }
   HIP_CHECK(hipStreamSynchronize(st));
 }
+
+template void build_vvvv_triangle<double>(const void*, int64_t, int64_t, const std::vector<int64_t>&,
+                                          const std::vector<int64_t>&, void*, hipStream_t);
+template void build_vvvv_triangle<float>(const void*, int64_t, int64_t, const std::vector<int64_t>&,
+                                         const std::vector<int64_t>&, void*, hipStream_t);
 
 void pack_last_pair(const void* full, int64_t n0, int64_t n1, int64_t n, void* packed, hipStream_t st) {
   // packed[x][y][P(e,f)] = full[x][y][e][f], e < f

@@ -52,6 +52,27 @@ template <typename T>
 void launch_unpack(const void* packed, void* full, const PackDesc& d, double are, double aim, bool acc,
                    hipStream_t st);
 
+// Dense tensor from a source that holds it up to a permutation, one
+// antisymmetric packed pair and a complex conjugation:
+//   out[t] (+)= (alpha * s) * X(src[off]),  X = conj if `conj` else identity,
+// for every target multi-index t (row-major over dims[0..rank)), where index
+// k of t (plus shift[k]) enters the source offset with stride str[k] (plain
+// index) or as member pairpos[k] = 0 / 1 of the source's packed pair
+// (offset P(p,q) * pstride with p < q, s = -1 when the members come as
+// (q, p), zero when they are equal; pairpos[k] = -1 for plain indices).
+struct MatDesc {
+  int rank;
+  int64_t dims[kMaxRank];
+  int64_t shift[kMaxRank];
+  int64_t str[kMaxRank];
+  int pairpos[kMaxRank];
+  int64_t pstride;
+  int conj;
+};
+template <typename T>
+void launch_materialize(const void* src, void* out, const MatDesc& d, double are, double aim, bool acc,
+                        hipStream_t st);
+
 template <typename T>
 void launch_fill_zero(void* p, int64_t n, hipStream_t st);
 

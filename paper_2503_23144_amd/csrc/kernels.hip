@@ -1122,6 +1122,70 @@ void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int6
   LAUNCH_CHECK();
 }
 
+// ---------------------------------------------------------------- materialize
+template <typename T, typename I>
+__global__ void __launch_bounds__(256) materialize_kernel(const typename cplx2<T>::type* __restrict__ src,
+                                                          typename cplx2<T>::type* __restrict__ out, MatDesc d,
+                                                          I total, T are, T aim, int acc) {
+  for (I lin = (I)blockIdx.x * blockDim.x + threadIdx.x; lin < total; lin += (I)gridDim.x * blockDim.x) {
+    I rem = lin;
+    int64_t off = 0, p = -1, q = -1;
+    for (int k = d.rank - 1; k >= 0; --k) {
+      const I dk = (I)d.dims[k];
+      const I qt = rem / dk;
+      const int64_t i = (int64_t)(rem - qt * dk) + d.shift[k];
+      rem = qt;
+      if (d.pairpos[k] < 0)
+        off += i * d.str[k];
+      else if (d.pairpos[k] == 0)
+        p = i;
+      else
+        q = i;
+    }
+    T s = 1;
+    bool zero = false;
+    if (p >= 0) {
+      if (p == q) {
+        zero = true;
+      } else if (p < q) {
+        off += (q * (q - 1) / 2 + p) * d.pstride;
+      } else {
+        off += (p * (p - 1) / 2 + q) * d.pstride;
+        s = -s;
+      }
+    }
+    T re = 0, im = 0;
+    if (!zero) {
+      const auto x = src[off];
+      const T xr = x.x, xi = d.conj ? -x.y : x.y;
+      re = s * (are * xr - aim * xi);
+      im = s * (are * xi + aim * xr);
+    }
+    if (acc) {
+      const auto y = out[lin];
+      re += y.x;
+      im += y.y;
+    }
+    out[lin] = {re, im};
+  }
+}
+
+template <typename T>
+void launch_materialize(const void* src, void* out, const MatDesc& d, double are, double aim, bool acc,
+                        hipStream_t st) {
+  int64_t total = 1;
+  for (int k = 0; k < d.rank; ++k) total *= d.dims[k];
+  if (total == 0) return;
+  using C = typename cplx2<T>::type;
+  if (total < (int64_t(1) << 31))
+    hipLaunchKernelGGL((materialize_kernel<T, uint32_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)src,
+                       (C*)out, d, (uint32_t)total, (T)are, (T)aim, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((materialize_kernel<T, int64_t>), dim3(nblocks(total)), dim3(256), 0, st, (const C*)src,
+                       (C*)out, d, total, (T)are, (T)aim, acc ? 1 : 0);
+  LAUNCH_CHECK();
+}
+
 // explicit instantiations
 #define INST(T)                                                                                               \
   template void launch_permute<T>(const void*, void*, const PermDesc&, double, double, double, double,       \
@@ -1136,7 +1200,8 @@ void launch_gather_block(int64_t naux, int64_t nmo, int64_t p0, int64_t np, int6
                                    int64_t, void*, hipStream_t, const double*);                              \
   template void launch_zero_diag<T>(void*, int64_t, hipStream_t);                                            \
   template void launch_pack_vvvv<T>(int64_t, int64_t, int64_t, int64_t, const void*, void*, hipStream_t);    \
-  template void launch_pack_wrows<T>(int64_t, int64_t, int64_t, const void*, void*, hipStream_t);
+  template void launch_pack_wrows<T>(int64_t, int64_t, int64_t, const void*, void*, hipStream_t);           \
+  template void launch_materialize<T>(const void*, void*, const MatDesc&, double, double, bool, hipStream_t);
 INST(double)
 INST(float)
 

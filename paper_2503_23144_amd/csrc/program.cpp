@@ -449,6 +449,22 @@ s2[ijac] += -1 * Tmi[ijac]
 s2[ijac] += Tmi[jiac]
 )";
 
+void mark_persistent(Module& m, const std::vector<const OpList*>& progs) {
+  m.persistent.assign(m.tensors.size(), 0);
+  for (const OpList* prog : progs) {
+    std::set<int> written;
+    for (const Op& op : *prog) {
+      for (int u : {op.a, op.b}) {
+        if (u < 0 || written.count(u)) continue;
+        const TensorDecl& t = m[u];
+        if (!t.batched && (t.role == Role::Temp || t.role == Role::Adjoint || t.role == Role::Tangent))
+          m.persistent[u] = 1;
+      }
+      written.insert(op.out);
+    }
+  }
+}
+
 void build_programs(CcPrograms& P) {
   Module& m = P.m;
   P.residual = parse_program(m, kCcsdProgram);
@@ -553,6 +569,7 @@ void build_programs(CcPrograms& P) {
     P.f_out2p = tt.at(P.g_gt2p);
     P.hvpt = prune(m, fops, {P.f_out1, P.f_out2p});
   }
+  mark_persistent(m, {&P.residual, &P.right, &P.left, &P.eta0, &P.xi, &P.gradL, &P.hvp, &P.hvpt, &P.fnspp});
 }
 
 }  // namespace lrcc

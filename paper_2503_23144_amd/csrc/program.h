@@ -56,6 +56,12 @@ using OpList = std::vector<Op>;
 struct Module {
   std::vector<TensorDecl> tensors;
   std::map<std::string, int> by_name;
+  // persistent[id] = 1: an unbatched temporary that some program reads
+  // before writing it (a primal intermediate or a gradient that another
+  // program consumes).  The executor keeps such tensors between runs; other
+  // unbatched temporaries that a program both writes and reads live only
+  // for that run.
+  std::vector<char> persistent;
   int add(const std::string& name, const std::string& cls, Role role, bool batched = false);
   int find(const std::string& name) const;  // -1 if absent
   const TensorDecl& operator[](int i) const { return tensors.at(i); }
@@ -125,5 +131,8 @@ struct CcPrograms {
   int n_t2, n_A[4], n_s1, n_s2;
 };
 void build_programs(CcPrograms& P);
+// Marks in m.persistent the unbatched temporaries read by some program of
+// `progs` before that program writes them.
+void mark_persistent(Module& m, const std::vector<const OpList*>& progs);
 
 }  // namespace lrcc

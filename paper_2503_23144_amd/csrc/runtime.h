@@ -74,6 +74,9 @@ class Executor {
   size_t batched_bytes() const;
   // Free all batch-dependent storage (it is re-allocated on the next run).
   void release_batched();
+  // Free the private storage of the unbatched tensors `ops` writes (its
+  // results; they are formed again by the next run of `ops`).
+  void release_results(const OpList& ops);
   size_t bytes_allocated() const;
 
   // optional per-launch timing (HIP events on the stream)
@@ -98,6 +101,29 @@ class Executor {
     const void* p;
   };
   void set_triangle_ladder(const std::vector<TriBlock>& blocks) { tri_ = blocks; }
+
+  // Constants held only through another tensor (no storage of their own).
+  // V[vl] = alpha_v * X(src[sl]): sl lists the source's indices in stored
+  // order, written with V's letters; the two letters at pair_at (if >= 0)
+  // are the source's packed antisymmetric pair P(p, q), p < q; X is complex
+  // conjugation when `conj`.  A contraction reading V materializes it into
+  // a scratch slot in the order the GEMM wants, in chunks over the index at
+  // position `chunk` of vl when that index is contracted or an output index
+  // (at most virtual_chunk_bytes per chunk); a permuted copy (Add) writes
+  // straight into its output.  Used for <ov||vv> and <vv||vo> (from the
+  // packed <ov||vv>) and <vv||oo> (from <oo||vv>), whose dense forms are the
+  // largest integral blocks after vvvv.
+  struct VirtualDef {
+    int src = -1;
+    std::string vl, sl;
+    int pair_at = -1;
+    double sre = 1.0, sim = 0.0;
+    bool conj = false;
+    int chunk = -1;
+  };
+  void set_virtual(int id, const VirtualDef& d);
+  bool is_virtual(int id) const { return id >= 0 && id < (int)vdef_.size() && vdef_[id].src >= 0; }
+  void set_virtual_chunk_bytes(size_t b) { vchunk_bytes_ = std::max<size_t>(b, 1); }
 
   // HIP graph replay.  With graphs on, a run whose program, batch and every
   // buffer address match an earlier (eager) run is captured into HIP graphs
@@ -172,6 +198,13 @@ class Executor {
   int64_t replays_ = 0, captures_ = 0;
 
   void contract(const Op& op, int nb);
+  void contract_virtual(const Op& op);
+  // Writes V (letters vlet, as in an op) into dst in the order of `tgt`,
+  // restricted to [g0, g0 + gl) along letter g (0: no restriction).
+  void materialize(int id, const std::string& vlet, const std::string& tgt, char g, int64_t g0, int64_t gl,
+                   void* dst, int64_t dst_cap, double are, double aim, bool acc);
+  std::vector<VirtualDef> vdef_;
+  size_t vchunk_bytes_ = size_t(1) << 30;
   void add(const Op& op, int nb);
   bool fuse_adds(const OpList& ops, const std::vector<size_t>& idx, bool launch = true);
   std::vector<std::vector<size_t>> add_groups(const OpList& ops, size_t i, size_t w) const;

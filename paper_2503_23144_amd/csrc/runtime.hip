@@ -39,7 +39,7 @@ Executor<T>::Executor(const Module& m, Dims d, hipStream_t st) : m_(m), d_(d), s
   cap_.assign(n, 0);
   bound_.assign(n, 0);
   pooled_.assign(n, 0);
-  // 0-2 permutations, 3 unused, 4 split-K partials, 5-6 cached permutations,
+  // 0-2 permutations, 3 virtual constants, 4 split-K partials, 5-6 cached permutations,
   // 7-8 DF-direct ladder: (ae|bf) block and rebuilt rows of W
   scr_.assign(9, nullptr);
   scr_cap_.assign(9, 0);
@@ -82,6 +82,7 @@ int64_t Executor<T>::elems(int id, int nb) const {
 template <typename T>
 void* Executor<T>::ptr(int id) {
   if (bound_[id] || pooled_[id]) return buf_[id];
+  LRCC_REQUIRE(!is_virtual(id), LRCC_E_INTERNAL, "constant " + m_[id].name + " has no storage of its own");
   int64_t need = elems(id, max_nb_);
   if (cap_[id] < need) {
     on_realloc();
@@ -153,6 +154,23 @@ void Executor<T>::release_batched() {
       scr_cap_[s] = 0;
     }
   plans_.clear();
+}
+
+template <typename T>
+void Executor<T>::release_results(const OpList& ops) {
+  bool any = false;
+  for (const Op& op : ops) {
+    const int t = op.out;
+    if (m_[t].batched || bound_[t] || pooled_[t] || !buf_[t]) continue;
+    if (!any) {
+      on_realloc();
+      HIP_CHECK(hipStreamSynchronize(st_));
+      any = true;
+    }
+    dev_free(buf_[t]);
+    buf_[t] = nullptr;
+    cap_[t] = 0;
+  }
 }
 
 template <typename T>
@@ -389,6 +407,7 @@ void Executor<T>::contract(const Op& op, int nb) {
   (void)nb;
   if (dl_L_ && (op.a == ladder_const || op.b == ladder_const)) return ladder_direct(op);
   if (!tri_.empty() && (op.a == ladder_const || op.b == ladder_const)) return ladder_triangle(op);
+  if (is_virtual(op.a) || is_virtual(op.b)) return contract_virtual(op);
   std::string a = letters(op.a, op.ai), b = letters(op.b, op.bi), c = letters(op.out, op.oi);
   const void* pa = ptr(op.a);
   const void* pb = ptr(op.b);
@@ -672,8 +691,227 @@ void Executor<T>::ladder_triangle(const Op& op) {
 }
 
 template <typename T>
+void Executor<T>::set_virtual(int id, const VirtualDef& d) {
+  if (vdef_.size() < buf_.size()) vdef_.resize(buf_.size());
+  LRCC_REQUIRE(id >= 0 && id < (int)buf_.size() && m_[id].role == Role::Const && !m_[id].batched, LRCC_E_INTERNAL,
+               "only unbatched constants can be virtual");
+  LRCC_REQUIRE(d.src >= 0 && d.src != id && !is_virtual(d.src) && d.vl.size() == m_[id].cls.size() &&
+                   d.sl.size() == d.vl.size() && (d.chunk < (int)d.vl.size()),
+               LRCC_E_INTERNAL, "bad virtual constant " + m_[id].name);
+  if (buf_[id] && !bound_[id]) {
+    on_realloc();
+    HIP_CHECK(hipStreamSynchronize(st_));
+    dev_free(buf_[id]);
+  }
+  buf_[id] = nullptr;
+  cap_[id] = 0;
+  bound_[id] = 0;
+  vdef_[id] = d;
+  on_realloc();
+}
+
+template <typename T>
+void Executor<T>::materialize(int id, const std::string& vlet, const std::string& tgt, char g, int64_t g0,
+                              int64_t gl, void* dst, int64_t dst_cap, double are, double aim, bool acc) {
+  const VirtualDef& vd = vdef_[id];
+  LRCC_REQUIRE(vlet.size() == vd.vl.size() && tgt.size() == vlet.size(), LRCC_E_INTERNAL, "materialize: letters");
+  std::string sl;  // the source's indices in op letters
+  for (char ch : vd.sl) {
+    const size_t p = vd.vl.find(ch);
+    LRCC_REQUIRE(p != std::string::npos, LRCC_E_INTERNAL, "materialize: source letter");
+    sl += vlet[p];
+  }
+  // stored dims of the source: one per plain index, one for the packed pair
+  const std::string& scls = m_[vd.src].cls;
+  const int ns = (int)scls.size();
+  std::vector<int64_t> sdim(ns), sstr(ns);
+  for (int k = 0; k < ns; ++k) sdim[k] = d_.of(scls[k]);
+  int64_t s = 1;
+  for (int k = ns - 1; k >= 0; --k) sstr[k] = s, s *= sdim[k];
+  std::vector<int> stored_of(sl.size(), -1);
+  int k = 0;
+  for (int j = 0; j < (int)sl.size(); ++k) {
+    LRCC_REQUIRE(k < ns, LRCC_E_INTERNAL, "materialize: source rank");
+    if (j == vd.pair_at) {
+      const int64_t n = dim(sl[j]);
+      LRCC_REQUIRE(j + 1 < (int)sl.size() && dim(sl[j + 1]) == n && sdim[k] == n * (n - 1) / 2, LRCC_E_INTERNAL,
+                   "materialize: packed pair");
+      stored_of[j] = stored_of[j + 1] = k;
+      j += 2;
+    } else {
+      LRCC_REQUIRE(sdim[k] == dim(sl[j]), LRCC_E_INTERNAL, "materialize: source dims");
+      stored_of[j] = k;
+      j += 1;
+    }
+  }
+  LRCC_REQUIRE(k == ns, LRCC_E_INTERNAL, "materialize: source rank");
+  MatDesc md{};
+  md.rank = (int)tgt.size();
+  LRCC_REQUIRE(md.rank <= kMaxRank, LRCC_E_INTERNAL, "materialize: rank");
+  int64_t total = 1;
+  for (int q = 0; q < md.rank; ++q) {
+    const char ch = tgt[q];
+    const size_t j = sl.find(ch);
+    LRCC_REQUIRE(j != std::string::npos, LRCC_E_INTERNAL, "materialize: target letter");
+    const bool restricted = g != 0 && ch == g;
+    LRCC_REQUIRE(!restricted || (g0 >= 0 && gl >= 1 && g0 + gl <= dim(ch)), LRCC_E_INTERNAL, "materialize: range");
+    md.dims[q] = restricted ? gl : dim(ch);
+    md.shift[q] = restricted ? g0 : 0;
+    md.pairpos[q] = (int)j == vd.pair_at ? 0 : ((int)j == vd.pair_at + 1 && vd.pair_at >= 0 ? 1 : -1);
+    md.str[q] = md.pairpos[q] < 0 ? sstr[stored_of[j]] : 0;
+    total *= md.dims[q];
+  }
+  md.pstride = vd.pair_at >= 0 ? sstr[stored_of[vd.pair_at]] : 0;
+  md.conj = vd.conj ? 1 : 0;
+  LRCC_REQUIRE(total <= dst_cap && s <= capacity(vd.src), LRCC_E_INTERNAL, "materialize exceeds its buffers");
+  const double re = are * vd.sre - aim * vd.sim, im = are * vd.sim + aim * vd.sre;
+  launch_materialize<T>(ptr(vd.src), dst, md, re, im, acc, st_);
+}
+
+// A contraction with a virtual constant G (made the B operand): G is
+// materialized in [N][K] order into scratch slot 3, in chunks over its
+// chunk index g when g is contracted (the chunks split K; the other
+// operand's K order puts g first, so each chunk is a contiguous range of
+// its columns, and the partial products accumulate) or an output index (the
+// chunks write disjoint parts of the output through a mapped epilogue).
+template <typename T>
+void Executor<T>::contract_virtual(const Op& op) {
+  LRCC_REQUIRE(!(is_virtual(op.a) && is_virtual(op.b)), LRCC_E_INTERNAL, "two virtual operands");
+  const bool va = is_virtual(op.a);
+  const int idg = va ? op.a : op.b, idx = va ? op.b : op.a;
+  const std::string b = letters(idg, va ? op.ai : op.bi), a = letters(idx, va ? op.bi : op.ai),
+                    c = letters(op.out, op.oi);
+  auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
+  auto size = [&](const std::string& x) {
+    int64_t p = 1;
+    for (char ch : x) p *= dimof(ch);
+    return p;
+  };
+  std::string K, Mc, Nc;
+  for (char ch : a)
+    if (b.find(ch) != std::string::npos) K += ch;
+  for (char ch : c) {
+    if (a.find(ch) != std::string::npos)
+      Mc += ch;
+    else if (b.find(ch) != std::string::npos)
+      Nc += ch;
+    else
+      throw Error(LRCC_E_INTERNAL, "output index not in operands");
+  }
+  LRCC_REQUIRE(Mc.size() + K.size() == a.size() && Nc.size() + K.size() == b.size() && !K.empty() &&
+                   !(Mc.empty() && Nc.empty()),
+               LRCC_E_INTERNAL, "virtual contraction: unsupported letters");
+  const VirtualDef& vd = vdef_[idg];
+  const char g = vd.chunk >= 0 ? b[vd.chunk] : 0;
+  const bool gK = g && K.find(g) != std::string::npos, gN = g && Nc.find(g) != std::string::npos;
+  std::string Kx = K;  // in a's order, g first when contracted
+  if (gK && Kx[0] != g) Kx = std::string(1, g) + Kx.erase(Kx.find(g), 1);
+  const int64_t Ms = size(Mc), Ns = size(Nc), Ks = size(Kx);
+  const size_t es = 2 * sizeof(T);
+  // the other operand as [M][K] or [K][M]
+  const void* A = ptr(idx);
+  int64_t capA = capacity(idx), lda;
+  bool ta;
+  if (a == Mc + Kx) {
+    ta = false;
+    lda = Ks;
+  } else if (a == Kx + Mc) {
+    ta = true;
+    lda = Ms;
+  } else {
+    if (m_[idx].batched) {
+      const int slot = cached_permute(idx, a, Mc + Kx, A, capA);
+      A = scr_[slot];
+      capA = scratch_elems(slot);
+    } else {
+      void* t = scratch(0, size(a) * es);
+      permute_into(A, capA, a, t, scratch_elems(0), Mc + Kx, 1, 0, 0, 0);
+      A = t;
+      capA = scratch_elems(0);
+    }
+    ta = false;
+    lda = Ks;
+  }
+  const bool chunked = gK || gN;
+  const int64_t gdim = chunked ? dimof(g) : 1;
+  int64_t gc = gdim;
+  if (chunked) {
+    const double per_g = (double)(size(b) / gdim) * (double)es;
+    gc = std::max<int64_t>(1, std::min<int64_t>(gdim, (int64_t)((double)vchunk_bytes_ / per_g)));
+  }
+  void* pc = ptr(op.out);
+  const int64_t cc = capacity(op.out);
+  OutMap om;
+  bool direct = false, mapped = false;
+  int64_t gstride = 0;  // stride of g in the output (gN)
+  if (gN) {
+    // the M digits as output_map merges them; one N digit per letter, g's restricted per chunk
+    LRCC_REQUIRE(output_map(Mc, Nc, c, om) && (int)Nc.size() <= kMapRank, LRCC_E_INTERNAL,
+                 "virtual contraction: output map");
+    std::vector<int64_t> str(c.size());
+    int64_t s = 1;
+    for (int k = (int)c.size() - 1; k >= 0; --k) str[k] = s, s *= dimof(c[k]);
+    om.nn = (int)Nc.size();
+    for (int k = 0; k < om.nn; ++k) {
+      om.ndim[k] = Nc[k] == g ? gc : dimof(Nc[k]);
+      om.nstr[k] = str[c.find(Nc[k])];
+    }
+    gstride = str[c.find(g)];
+    mapped = true;
+  } else if (c == Mc + Nc) {
+    direct = true;
+  } else {
+    mapped = output_map(Mc, Nc, c, om);
+  }
+  void* prod = nullptr;
+  int64_t prod_cap = 0;
+  if (!direct && !mapped) {
+    prod = scratch(2, (size_t)Ms * Ns * es);
+    prod_cap = scratch_elems(2);
+  }
+  const int64_t Krest = gK ? Ks / gdim : Ks, Nrest = gN ? Ns / gdim : Ns;
+  for (int64_t g0 = 0; g0 < gdim; g0 += gc) {
+    const int64_t gl = std::min(gc, gdim - g0);
+    const int64_t Kc = gK ? gl * Krest : Ks, Nch = gN ? gl * Nrest : Ns;
+    void* Bm = scratch(3, (size_t)Nch * Kc * es);
+    materialize(idg, va ? op.ai : op.bi, Nc + Kx, chunked ? g : 0, g0, chunked ? gl : 0, Bm, scratch_elems(3), 1.0, 0.0,
+                false);
+    const void* Ac = A;
+    int64_t capAc = capA;
+    if (gK) {
+      const int64_t off = ta ? g0 * Krest * lda : g0 * Krest;
+      Ac = (const char*)A + off * es;
+      capAc = capA - off;
+    }
+    const double beta = gK ? (g0 == 0 ? (op.acc ? 1.0 : 0.0) : 1.0) : (op.acc ? 1.0 : 0.0);
+    if (direct) {
+      gemm(ta, true, Ms, Ns, Kc, op.are, op.aim, Ac, lda, capAc, Bm, Kc, scratch_elems(3), beta, pc, Ns, cc, false);
+    } else if (mapped) {
+      OutMap oc = om;
+      int64_t off = 0;
+      if (gN) {
+        for (int k = 0; k < oc.nn; ++k)
+          if (Nc[k] == g) oc.ndim[k] = gl;
+        off = g0 * gstride;
+      }
+      gemm(ta, true, Ms, Nch, Kc, op.are, op.aim, Ac, lda, capAc, Bm, Kc, scratch_elems(3), beta, (char*)pc + off * es,
+           Nch, cc - off, false, &oc);
+    } else {
+      gemm(ta, true, Ms, Ns, Kc, op.are, op.aim, Ac, lda, capAc, Bm, Kc, scratch_elems(3), g0 == 0 ? 0.0 : 1.0, prod,
+           Ns, prod_cap, false);
+    }
+  }
+  if (prod) permute_into(prod, prod_cap, Mc + Nc, pc, cc, c, 1, 0, op.acc ? 1 : 0, 0);
+}
+
+template <typename T>
 void Executor<T>::add(const Op& op, int nb) {
   (void)nb;
+  if (is_virtual(op.a)) {  // a permuted copy of a virtual constant: written straight into the output
+    LRCC_REQUIRE(!m_[op.out].batched, LRCC_E_INTERNAL, "add: batch mismatch");
+    materialize(op.a, op.ai, op.oi, 0, 0, 0, ptr(op.out), capacity(op.out), op.are, op.aim, op.acc);
+    return;
+  }
   std::string a = letters(op.a, op.ai), c = letters(op.out, op.oi);
   LRCC_REQUIRE(m_[op.a].batched == m_[op.out].batched, LRCC_E_INTERNAL, "add: batch mismatch");
   permute_into(ptr(op.a), capacity(op.a), a, ptr(op.out), capacity(op.out), c, op.are, op.aim, op.acc ? 1 : 0, 0);
@@ -702,6 +940,7 @@ bool Executor<T>::fuse_adds(const OpList& ops, const std::vector<size_t>& idx, b
   for (size_t g = 0; g < idx.size(); ++g) {
     const Op& o = ops[idx[g]];
     if (o.kind != OpKind::Add || o.out != o0.out || o.a == o.out || (g > 0 && !o.acc)) return false;
+    if (is_virtual(o.a)) return false;
     if (m_[o.a].batched != m_[o.out].batched) return false;
     const std::string c = letters(o.out, o.oi), a = letters(o.a, o.ai);
     if ((int)c.size() != L || (int)a.size() != L) return false;
@@ -896,6 +1135,7 @@ static void align(const std::string& pk, const std::string& fl, std::vector<int>
 template <typename T>
 void Executor<T>::pack(const Op& op, int nb) {
   (void)nb;
+  LRCC_REQUIRE(!is_virtual(op.a), LRCC_E_INTERNAL, "pack of a virtual constant");
   std::string pk = letters(op.out, op.oi), fl = letters(op.a, op.ai);
   auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
   std::vector<int> fpos, isp;
@@ -941,6 +1181,7 @@ void Executor<T>::pack(const Op& op, int nb) {
 template <typename T>
 void Executor<T>::unpack(const Op& op, int nb) {
   (void)nb;
+  LRCC_REQUIRE(!is_virtual(op.a), LRCC_E_INTERNAL, "unpack of a virtual constant");
   std::string pk = letters(op.a, op.ai), fl = letters(op.out, op.oi);
   auto dimof = [&](char l) { return l == '#' ? g_nb : dim(l); };
   std::vector<int> fpos, isp;
@@ -990,25 +1231,37 @@ int64_t tensor_elems(const Module& m, const Dims& d, int id, int nb) {
   return n;
 }
 
+// Tensors a run pools: batched tensors it writes (except those kept or
+// bound), and unbatched temporaries it both writes and reads that no other
+// program reads (Module::persistent): intermediates of this run only.
+// Unbatched tensors a run writes but never reads are its results and stay.
+static bool poolable(const Module& m, int t, const std::vector<char>& read_here) {
+  const TensorDecl& d = m[t];
+  if (d.batched) return true;
+  if (!(d.role == Role::Temp || d.role == Role::Adjoint || d.role == Role::Tangent)) return false;
+  if (t < (int)m.persistent.size() && m.persistent[t]) return false;
+  return read_here[t] != 0;
+}
+
 PoolPlan plan_pool(const Module& m, const Dims& d, const OpList& ops, int nb, const std::vector<int>& keep,
                    const std::vector<char>* bound) {
   const int nt = (int)m.tensors.size();
   std::vector<int> first(nt, -1), last(nt, -1);
-  std::vector<char> is_keep(nt, 0);
+  std::vector<char> is_keep(nt, 0), read_here(nt, 0);
   for (int k : keep) is_keep[k] = 1;
   for (int k = 0; k < (int)ops.size(); ++k) {
     const Op& op = ops[k];
     if (first[op.out] < 0) first[op.out] = k;
     last[op.out] = std::max(last[op.out], k);
-    if (op.a >= 0) last[op.a] = std::max(last[op.a], k);
-    if (op.b >= 0) last[op.b] = std::max(last[op.b], k);
+    if (op.a >= 0) last[op.a] = std::max(last[op.a], k), read_here[op.a] = 1;
+    if (op.b >= 0) last[op.b] = std::max(last[op.b], k), read_here[op.b] = 1;
   }
   PoolPlan pl;
   std::vector<int> slot_of(nt, -1);
   std::vector<char> busy;
   for (int k = 0; k < (int)ops.size(); ++k) {
     int t = ops[k].out;
-    if (first[t] == k && m[t].batched && !is_keep[t] && !(bound && (*bound)[t])) {
+    if (first[t] == k && poolable(m, t, read_here) && !is_keep[t] && !(bound && (*bound)[t])) {
       int64_t need = tensor_elems(m, d, t, nb);
       int best = -1;
       for (int s = 0; s < (int)pl.slot_elems.size(); ++s)
@@ -1029,6 +1282,20 @@ PoolPlan plan_pool(const Module& m, const Dims& d, const OpList& ops, int nb, co
     for (int u : used)
       if (u >= 0 && slot_of[u] >= 0 && last[u] == k) busy[slot_of[u]] = 0;
   }
+  // number the slots largest first: the executor's pool holds, per slot
+  // number, the largest size any program needs there, so that programs
+  // whose plans are alike in size share it closely
+  std::vector<int> order(pl.slot_elems.size()), rank(pl.slot_elems.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return pl.slot_elems[x] > pl.slot_elems[y]; });
+  std::vector<int64_t> sizes(order.size());
+  for (size_t q = 0; q < order.size(); ++q) {
+    rank[order[q]] = (int)q;
+    sizes[q] = pl.slot_elems[order[q]];
+  }
+  pl.slot_elems = sizes;
+  for (auto& ts : pl.slot) ts.second = rank[ts.second];
   return pl;
 }
 

@@ -24,6 +24,55 @@ namespace lrcc {
 static const char* kBlocks[][2] = {{"goooo", "oooo"}, {"gooov", "ooov"}, {"goovv", "oovv"}, {"govvo", "ovvo"},
                                    {"govvv", "ovvv"}, {"gvvoo", "vvoo"}, {"gvvvo", "vvvo"}, {"govoo", "ovoo"}};
 
+// Integral blocks that LRCC_MEMORY_LEAN does not store: <ov||vv> is kept
+// only packed over its last pair (govvp), <vv||vo> = -conj <ov||vv> with
+// (a, b, c, i) -> (i, c, a, b), and <vv||oo> = conj <oo||vv> transposed
+// (<pq||rs> = conj <rs||pq> for Hermitian factors).
+static bool lean_block(const char* name) {
+  return !std::strcmp(name, "govvv") || !std::strcmp(name, "gvvvo") || !std::strcmp(name, "gvvoo");
+}
+
+template <typename T>
+static void set_virtuals(Executor<T>& x, const Module& m) {
+  typename Executor<T>::VirtualDef d;
+  d.src = m.find("govvp");
+  d.vl = "wxyz";
+  d.sl = "wxyz";  // govvv[w][x][y][z] = govvp[w][x][P(y, z)]
+  d.pair_at = 2;
+  d.chunk = 0;
+  x.set_virtual(m.find("govvv"), d);
+  d.sl = "zywx";  // gvvvo[w][x][y][z] = -conj govvp[z][y][P(w, x)]
+  d.sre = -1.0;
+  d.conj = true;
+  d.chunk = 3;
+  x.set_virtual(m.find("gvvvo"), d);
+  d.src = m.find("goovv");
+  d.sl = "yzwx";  // gvvoo[w][x][y][z] = conj goovv[y][z][w][x]
+  d.pair_at = -1;
+  d.sre = 1.0;
+  d.chunk = 2;
+  x.set_virtual(m.find("gvvoo"), d);
+  const char* e = std::getenv("LRCC_VIRTUAL_CHUNK_BYTES");  // smaller chunks, for tests of the chunked path
+  if (e && std::atoll(e) > 0) x.set_virtual_chunk_bytes((size_t)std::atoll(e));
+}
+
+static size_t device_total_bytes() {
+  size_t fr = 0, tot = 0;
+  int n = 0;
+  if (hipGetDeviceCount(&n) == hipSuccess && n > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0) return tot;
+  return size_t(288) * 1000 * 1000 * 1000;  // MI355X
+}
+
+// LRCC_MEMORY_AUTO takes the lean layout when the resident one would need
+// more than half the device for a single right-hand side.
+static bool lean_layout(const lrcc_config& cfg, int o, int v, int naux) {
+  if (cfg.memory_mode == LRCC_MEMORY_LEAN) return true;
+  if (cfg.memory_mode == LRCC_MEMORY_RESIDENT) return false;
+  lrcc_config r = cfg;
+  r.memory_mode = LRCC_MEMORY_RESIDENT;
+  return (double)workspace_estimate(r, o, v, naux, 1) > 0.5 * (double)device_total_bytes();
+}
+
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -86,6 +135,10 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
       throw Error(LRCC_E_INVALID, "density-fitting factors are not Hermitian (B[Q][p][r] != conj B[Q][r][p])");
     }
   }
+  const bool mixed = cfg.precision == LRCC_MIXED;
+  mode32 = cfg.ladder_mode;
+  mode64 = (mixed && cfg.ladder_mode_fp64 >= 0) ? cfg.ladder_mode_fp64 : cfg.ladder_mode;
+  lean = lean_layout(cfg, (int)o, (int)v, (int)naux);
   x64.reset(new Executor<double>(P.m, dims, st));
   x64->ladder_const = P.m.find("W");
   x64->set_timing(timing);
@@ -94,11 +147,12 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   L32.release();
   Tri64.release();
   Tri32.release();
-  if (cfg.ladder_mode != LRCC_LADDER_FULL) {  // the virtual-virtual block of B builds W's rows
+  if (mode64 != LRCC_LADDER_FULL || (mixed && mode32 != LRCC_LADDER_FULL)) {
+    // the virtual-virtual block of B builds W's rows
     L64.ensure((size_t)naux * v * v * 16);
     launch_gather_block(naux, nmo, o, v, o, v, B.p, L64.p, st);
   }
-  if (cfg.ladder_mode == LRCC_LADDER_DIRECT) x64->set_direct_ladder(L64.p, naux, v);
+  if (mode64 == LRCC_LADDER_DIRECT) x64->set_direct_ladder(L64.p, naux, v);
   build_integrals();
   have_fock = false;
   ncomp = 0;
@@ -106,9 +160,10 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
 }
 
 void Context::build_integrals() {
-  for (auto& b : kBlocks) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
-  if (cfg.ladder_mode == LRCC_LADDER_FULL) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
-  if (cfg.ladder_mode == LRCC_LADDER_TRIANGLE) {
+  for (auto& b : kBlocks)
+    if (!(lean && lean_block(b[0]))) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
+  if (mode64 == LRCC_LADDER_FULL) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
+  if (mode64 == LRCC_LADDER_TRIANGLE || (cfg.precision == LRCC_MIXED && mode32 == LRCC_LADDER_TRIANGLE)) {
     // row blocks of about equal size (rows grow as b^2): b_j = 1 + (v - 1) sqrt(j / nb)
     const int nb = (int)std::min<int64_t>(8, v - 1);
     tri_bnd.assign(1, 1);
@@ -123,11 +178,18 @@ void Context::build_integrals() {
       const int64_t r0 = tri_bnd[j] * (tri_bnd[j] - 1) / 2, r1 = tri_bnd[j + 1] * (tri_bnd[j + 1] - 1) / 2;
       tri_offs.push_back(tri_offs.back() + (r1 - r0) * (V - r0));
     }
+  }
+  if (mode64 == LRCC_LADDER_TRIANGLE) {
     Tri64.ensure((size_t)tri_offs.back() * 16);
-    build_vvvv_triangle(L64.p, naux, v, tri_bnd, tri_offs, Tri64.p, st);
+    build_vvvv_triangle<double>(L64.p, naux, v, tri_bnd, tri_offs, Tri64.p, st);
     x64->set_triangle_ladder(tri_blocks<double>(Tri64.p));
   }
-  pack_last_pair(x64->ptr(P.m.find("govvv")), o, v, v, x64->ptr(P.m.find("govvp")), st);
+  if (lean) {
+    build_block(B.p, naux, o, v, "ovvv", x64->ptr(P.m.find("govvp")), st, true);
+    set_virtuals(*x64, P.m);
+  } else {
+    pack_last_pair(x64->ptr(P.m.find("govvv")), o, v, v, x64->ptr(P.m.find("govvp")), st);
+  }
   const double one[2] = {1.0, 0.0};
   HIP_CHECK(hipMemcpyAsync(x64->ptr(P.one), one, 16, hipMemcpyHostToDevice, st));
   sync();
@@ -144,36 +206,47 @@ std::vector<typename Executor<T>::TriBlock> Context::tri_blocks(const void* base
 
 static void ensure_x32(Context& c) {
   if (c.x32) return;
+  const int W = c.P.m.find("W");
+  auto stored = [&](int id) {  // constants the FP32 executor holds a copy of (W apart)
+    const Role r = c.P.m[id].role;
+    if (id == W || (c.lean && lean_block(c.P.m[id].name.c_str()))) return false;
+    return r == Role::Const || r == Role::Scalar1 || r == Role::Fock;
+  };
   {  // the FP32 copies of the constants; make room from FP64 batch storage if needed
     int64_t need = 0;
-    const int W = c.P.m.find("W");
-    for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
-      Role r = c.P.m[(int)id].role;
-      if (c.cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == W) continue;
-      if (r == Role::Const || r == Role::Scalar1 || r == Role::Fock) need += c.x64->elems((int)id, 1) * 8;
-    }
+    for (size_t id = 0; id < c.P.m.tensors.size(); ++id)
+      if (stored((int)id)) need += c.x64->elems((int)id, 1) * 8;
+    if (c.mode32 == LRCC_LADDER_FULL) need += c.x64->elems(W, 1) * 8;
     if ((double)dev_available() < 1.1 * (double)need + (1 << 30)) c.x64->release_batched();
   }
   c.x32.reset(new Executor<float>(c.P.m, c.dims, c.st));
-  c.x32->ladder_const = c.P.m.find("W");
+  c.x32->ladder_const = W;
   c.x32->set_timing(c.timing);
   c.x32->set_graphs(c.cfg.graphs != 0);
   for (size_t id = 0; id < c.P.m.tensors.size(); ++id) {
-    Role r = c.P.m[(int)id].role;
-    if (c.cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == c.x32->ladder_const) continue;
-    if (r == Role::Const || r == Role::Scalar1 || (r == Role::Fock && c.have_fock))
-      launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
+    if (!stored((int)id) || (c.P.m[(int)id].role == Role::Fock && !c.have_fock)) continue;
+    launch_d2s(c.x64->elems((int)id, 1), c.x64->ptr((int)id), c.x32->ptr((int)id), c.st);
   }
-  if (c.cfg.ladder_mode == LRCC_LADDER_DIRECT) {
+  if (c.mode32 == LRCC_LADDER_FULL) {
+    if (c.mode64 == LRCC_LADDER_FULL)
+      launch_d2s(c.x64->elems(W, 1), c.x64->ptr(W), c.x32->ptr(W), c.st);
+    else  // rows of W formed in FP64 from the factors, rounded once
+      build_vvvv_triangle<float>(c.L64.p, c.naux, c.v, {1, c.v}, {0}, c.x32->ptr(W), c.st);
+  }
+  if (c.mode32 == LRCC_LADDER_DIRECT) {
     c.L32.ensure((size_t)c.naux * c.v * c.v * 8);
     launch_d2s(c.naux * c.v * c.v, c.L64.p, c.L32.p, c.st);
     c.x32->set_direct_ladder(c.L32.p, c.naux, c.v);
   }
-  if (c.cfg.ladder_mode == LRCC_LADDER_TRIANGLE) {
+  if (c.mode32 == LRCC_LADDER_TRIANGLE) {
     c.Tri32.ensure((size_t)c.tri_offs.back() * 8);
-    launch_d2s(c.tri_offs.back(), c.Tri64.p, c.Tri32.p, c.st);
+    if (c.mode64 == LRCC_LADDER_TRIANGLE)
+      launch_d2s(c.tri_offs.back(), c.Tri64.p, c.Tri32.p, c.st);
+    else
+      build_vvvv_triangle<float>(c.L64.p, c.naux, c.v, c.tri_bnd, c.tri_offs, c.Tri32.p, c.st);
     c.x32->set_triangle_ladder(c.tri_blocks<float>(c.Tri32.p));
   }
+  if (c.lean) set_virtuals(*c.x32, c.P.m);
   if (c.have_fock) {
     launch_zero_diag<float>(c.x32->ptr(c.P.foo), c.o, c.st);
     launch_zero_diag<float>(c.x32->ptr(c.P.fvv), c.v, c.st);
@@ -244,7 +317,20 @@ void Context::load_dipoles(int nc, const void* m, int where) {
 
 // ---------------------------------------------------------------- Jacobian products
 
+// Before a run of `ops` at batch nb on executor `run`: when the device has
+// less free memory than the run's transients still need, the other
+// executor's batch storage (its pool and scratch, formed again on its next
+// run) is released.  The FP32 and FP64 products of a mixed solve alternate,
+// so they need not hold their transients at the same time.
+template <typename A, typename B>
+static void make_room(A* run, const OpList& ops, int nb, const std::vector<int>& keep, B* other) {
+  if (!other || other->batched_bytes() == 0) return;
+  const double need = (double)run->transient_bytes(ops, nb, keep) - (double)run->batched_bytes();
+  if (need > 0.9 * (double)dev_available()) other->release_batched();
+}
+
 void Context::residual64(const void* tvec, void* R, cplx* E) {
+  make_room(x64.get(), P.residual, 1, {}, x32.get());
   x64->bind(P.t1, const_cast<void*>(tvec));
   x64->bind(P.t2p, (char*)const_cast<void*>(tvec) + n1 * 16);
   x64->bind(P.O1, R);
@@ -287,6 +373,8 @@ void Context::sigma64(Side side, int nb, const void* in, void* out) {
   ensure_primal(64);
   x64->set_max_batch(nb);
   const bool r = side == Side::Right;
+  make_room(x64.get(), r ? P.right : P.left, nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
+            std::vector<int>{P.l_gt1, P.l_gt2p}, x32.get());
   int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, double>(nb, n1, in, n, x64->ptr(a1), n1, st);
@@ -301,6 +389,8 @@ void Context::sigma32(Side side, int nb, const void* in64, void* out32) {
   ensure_primal(32);
   x32->set_max_batch(nb);
   const bool r = side == Side::Right;
+  make_room(x32.get(), r ? P.right : P.left, nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
+            std::vector<int>{P.l_gt1, P.l_gt2p}, x64.get());
   int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, float>(nb, n1, in64, n, x32->ptr(a1), n1, st);
@@ -322,15 +412,17 @@ static void gather_mu_blocks(Context& c, int nb, const int* comp, const int* dst
   }
 }
 
+// One component at a time: these run once per response solve, and a batch
+// of one keeps their transients at a single right-hand side's size.
 void Context::xi_vectors(void* out) {
   ensure_primal(64);
-  x64->set_max_batch(ncomp);
-  std::vector<int> comp(ncomp);
-  for (int c = 0; c < ncomp; ++c) comp[c] = c;
-  gather_mu_blocks(*this, ncomp, comp.data(), P.x_df);
-  x64->run(P.xi, ncomp, {P.x_dO1, P.x_dO2p});
-  launch_copy_rows<double, double>(ncomp, n1, x64->ptr(P.x_dO1), n1, out, n, st);
-  launch_copy_rows<double, double>(ncomp, n2, x64->ptr(P.x_dO2p), n2, (char*)out + n1 * 16, n, st);
+  for (int c = 0; c < ncomp; ++c) {
+    gather_mu_blocks(*this, 1, &c, P.x_df);
+    x64->run(P.xi, 1, {P.x_dO1, P.x_dO2p});
+    char* o = (char*)out + (size_t)c * n * 16;
+    launch_copy_rows<double, double>(1, n1, x64->ptr(P.x_dO1), n1, o, n, st);
+    launch_copy_rows<double, double>(1, n2, x64->ptr(P.x_dO2p), n2, o + n1 * 16, n, st);
+  }
 }
 
 void Context::hvp(int nb, const int* comp, const void* Xdt, void* out) {
@@ -343,6 +435,7 @@ void Context::hvp(int nb, const int* comp, const void* Xdt, void* out) {
     gradL_ready = 1;
   }
   x64->set_max_batch(nb);
+  make_room(x64.get(), P.hvp, nb, {P.h_out1, P.h_out2p}, x32.get());
   if (Xdt) {
     launch_copy_rows<double, double>(nb, n1, Xdt, n, x64->ptr(P.h_dt1), n1, st);
     launch_copy_rows<double, double>(nb, n2, (const char*)Xdt + n1 * 16, n, x64->ptr(P.h_dt2p), n2, st);
@@ -370,6 +463,7 @@ static void vec_norms(Context& c, int nb, const void* v, std::vector<double>& ou
 
 void Context::residual32(const void* tvec, void* R) {
   ensure_x32(*this);
+  make_room(x32.get(), P.residual, 1, {}, x64.get());
   t32.ensure(n * 8);
   work.ensure(n * 16);
   launch_d2s(n, tvec, t32.p, st);
@@ -397,6 +491,7 @@ void Context::fx32(int nb, const void* X64, void* out32) {
     gradL32_ready = 1;
   }
   x32->set_max_batch(nb);
+  make_room(x32.get(), P.hvpt, nb, {P.f_out1, P.f_out2p}, x64.get());
   launch_copy_rows<double, float>(nb, n1, X64, n, x32->ptr(P.f_dt1), n1, st);
   launch_copy_rows<double, float>(nb, n2, (const char*)X64 + n1 * 16, n, x32->ptr(P.f_dt2p), n2, st);
   x32->run(P.hvpt, nb, {P.f_out1, P.f_out2p});
@@ -808,23 +903,61 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
   const int64_t nmo = o + v, n = (int64_t)o * v + d.O * d.V;
   const bool mixed = cfg.precision == LRCC_MIXED;
   const int nb = nrhs;
+  const int mode32 = cfg.ladder_mode;
+  const int mode64 = (mixed && cfg.ladder_mode_fp64 >= 0) ? cfg.ladder_mode_fp64 : cfg.ladder_mode;
+  const bool lean = lean_layout(cfg, o, v, naux);
   // context buffers: B, F, mu, D, t, lambda, work, xi, eta, X, Y (+ FP32 copies)
   double bytes = 16.0 * ((double)naux * nmo * nmo + 4.0 * nmo * nmo) + 8.0 * n + 16.0 * n * (3 + 6) +
                  2 * 16.0 * (double)nrhs * n + (mixed ? 8.0 * n * (2 + nb) : 0.0);
+  if (mode64 != LRCC_LADDER_FULL || (mixed && mode32 != LRCC_LADDER_FULL))
+    bytes += 16.0 * naux * (double)v * v;  // the virtual-virtual block of B
   // one executor: its unbatched tensors (constants, Fock blocks, primal
   // intermediates), the pool, the batched tensors outside the pool, scratch
-  auto executor = [&](double elem, const std::vector<std::pair<const OpList*, int>>& runs) {
+  // returns the executor's fixed bytes; its batch storage goes to *batch
+  // unbatched tensors the FP64 gradient of L writes: in mixed precision they
+  // exist only while eta is formed (F X runs in FP32 afterwards)
+  std::vector<char> grad_result(m.tensors.size(), 0);
+  for (const Op& op : P.gradL) grad_result[op.out] = !m.tensors[op.out].batched;
+  double grad64 = 0;
+  auto executor = [&](double elem, int mode, const std::vector<std::pair<const OpList*, int>>& runs,
+                      double* batch) {
     double b = 0;
-    for (size_t id = 0; id < m.tensors.size(); ++id)
-      if (!m.tensors[id].batched && !(cfg.ladder_mode != LRCC_LADDER_FULL && (int)id == m.find("W")))
-        b += elem * (double)tensor_elems(m, d, (int)id, 1);
-    if (cfg.ladder_mode == LRCC_LADDER_TRIANGLE)  // row blocks of the upper triangle: about (V^2 + V^2 / nb) / 2
+    std::vector<char> in_pool(m.tensors.size(), 0), touched(m.tensors.size(), 0);
+    for (auto& r : runs) {  // unbatched intermediates of a single run live in the pool
+      for (auto& ts : plan_pool(m, d, *r.first, r.second, {}, nullptr).slot) in_pool[ts.first] = 1;
+      for (const Op& op : *r.first)
+        for (int u : {op.out, op.a, op.b})
+          if (u >= 0) touched[u] = 1;
+    }
+    static const bool trace = std::getenv("LRCC_TRACE_ESTIMATE") != nullptr;
+    for (size_t id = 0; id < m.tensors.size(); ++id) {
+      if (m.tensors[id].batched || in_pool[id] || !touched[id]) continue;
+      if ((int)id == m.find("W") && mode != LRCC_LADDER_FULL) continue;
+      if (lean && lean_block(m.tensors[id].name.c_str())) continue;
+      if (mixed && elem == 16.0 && grad_result[id]) {
+        grad64 += elem * (double)tensor_elems(m, d, (int)id, 1);
+        continue;
+      }
+      b += elem * (double)tensor_elems(m, d, (int)id, 1);
+      if (trace && elem * (double)tensor_elems(m, d, (int)id, 1) > 1e8)
+        fprintf(stderr, "[estimate] %s unbatched %s %.2f GB\n", elem == 16 ? "fp64" : "fp32",
+                m.tensors[id].name.c_str(), elem * (double)tensor_elems(m, d, (int)id, 1) / 1e9);
+    }
+    if (mode == LRCC_LADDER_TRIANGLE)  // row blocks of the upper triangle: about (V^2 + V^2 / nb) / 2
       b += elem * 0.5625 * (double)d.V * (double)d.V;
+    if (mode == LRCC_LADDER_DIRECT && elem == 8.0) b += 8.0 * naux * (double)v * v;  // its FP32 copy
+    if (lean) b += 1.25 * (double)(size_t(1) << 30);  // chunks of the blocks formed on use
     std::vector<int64_t> pool;
     std::vector<char> pooled(m.tensors.size(), 0), used(m.tensors.size(), 0);
     int64_t big = 0;
     for (auto& r : runs) {
       PoolPlan pl = plan_pool(m, d, *r.first, r.second, {}, nullptr);
+      if (trace) {
+        double tot = 0;
+        for (int64_t e : pl.slot_elems) tot += elem * (double)e;
+        fprintf(stderr, "[estimate] %s run of %zu ops at batch %d: pool %zu slots %.2f GB\n",
+                elem == 16 ? "fp64" : "fp32", r.first->size(), r.second, pl.slot_elems.size(), tot / 1e9);
+      }
       if (pool.size() < pl.slot_elems.size()) pool.resize(pl.slot_elems.size(), 0);
       for (size_t k = 0; k < pl.slot_elems.size(); ++k) pool[k] = std::max(pool[k], pl.slot_elems[k]);
       for (auto& ts : pl.slot) pooled[ts.first] = 1;
@@ -835,21 +968,43 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
             big = std::max(big, tensor_elems(m, d, u, r.second));
           }
     }
+    double fixed = b;
+    b = 0;
     for (int64_t e : pool) b += elem * (double)e;
+    if (trace) {
+      double pb = 0;
+      for (int64_t e : pool) pb += elem * (double)e;
+      fprintf(stderr, "[estimate] %s pool %zu slots %.2f GB, 4 x big %.2f GB\n", elem == 16 ? "fp64" : "fp32",
+              pool.size(), pb / 1e9, elem * 4.0 * (double)big / 1e9);
+    }
     for (size_t id = 0; id < m.tensors.size(); ++id)
-      if (used[id] && !pooled[id]) b += elem * (double)tensor_elems(m, d, (int)id, nb);
+      if (used[id] && !pooled[id]) {
+        b += elem * (double)tensor_elems(m, d, (int)id, nb);
+        if (trace)
+          fprintf(stderr, "[estimate] %s batched kept %s %.2f GB\n", elem == 16 ? "fp64" : "fp32",
+                  m.tensors[id].name.c_str(), elem * (double)tensor_elems(m, d, (int)id, nb) / 1e9);
+      }
     b += elem * 4.0 * (double)big;  // three permutation slots and one tile-timing output
-    if (cfg.ladder_mode == LRCC_LADDER_DIRECT) b += 2.0 * (double)Executor<double>::kDirectChunkBytes;
-    return b + 320.0 * (1 << 20);    // split-K partials (at most 256 MB) and small buffers
+    *batch = b;
+    if (mode == LRCC_LADDER_DIRECT) fixed += 2.0 * (double)Executor<double>::kDirectChunkBytes;
+    return fixed + 320.0 * (1 << 20);  // split-K partials (at most 256 MB) and small buffers
   };
-  bytes += executor(16.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 3}, {&P.eta0, 1},
-                           {&P.gradL, 1}, {&P.hvp, nb}});
-  if (mixed) bytes += executor(8.0, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.gradL, 1}, {&P.hvpt, nb}});
+  // the two executors' batch storage is not held at once when memory is
+  // short (the products alternate; see make_room)
+  double batch64 = 0, batch32 = 0;
+  bytes += executor(16.0, mode64, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 1}, {&P.eta0, 1},
+                                   {&P.gradL, 1}, {&P.hvp, nb}}, &batch64);
+  if (mixed)
+    bytes += executor(8.0, mode32, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.gradL, 1}, {&P.hvpt, nb}},
+                      &batch32);
   // solver buffers per right-hand side (iterates, residuals, driving terms,
   // DIIS history, products, certification)
-  bytes += (double)nb * (2.0 * std::max(cfg.diis_size, 0) + 12.0) * 16.0 * n;
-  // integral build temporaries (freed before the solves; counted on top)
-  bytes += 4.0 * 16.0 * naux * (double)v * v + (double)(size_t(1) << 30);
+  const double solver = (double)nb * (2.0 * std::max(cfg.diis_size, 0) + 12.0) * 16.0 * n;
+  // phases: eta (the FP64 Hessian products with the FP64 gradient of L), then
+  // the solves (the executors' transients alternate); the integral build
+  // temporaries are freed before either
+  const double build = 4.0 * 16.0 * naux * (double)v * v + (double)(size_t(1) << 30);
+  bytes += std::max({batch64 + grad64, std::max(batch64, batch32) + solver, build});
   return (size_t)(1.1 * bytes) + (size_t(64) << 20);
 }
 
@@ -908,9 +1063,13 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
   xi.ensure(ncomp * vb);
   eta.ensure(ncomp * vb);
   xi_vectors(xi.p);
-  std::vector<int> comps(ncomp);
-  for (int c = 0; c < ncomp; ++c) comps[c] = c;
-  hvp(ncomp, comps.data(), nullptr, eta.p);
+  for (int c = 0; c < ncomp; ++c) hvp(1, &c, nullptr, (char*)eta.p + (size_t)c * vb);
+  if (prec == 32) {
+    // F X runs with FP32 products from here on: the FP64 gradient of L that
+    // only the FP64 Hessian products read is dropped (rebuilt on demand)
+    x64->release_results(P.gradL);
+    gradL_ready = 0;
+  }
   X.ensure(nrhs * vb);
   Y.ensure(nrhs * vb);
   have_alpha = false;

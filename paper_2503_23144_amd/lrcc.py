@@ -43,7 +43,8 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("precision", ctypes.c_int),
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
-                ("graphs", ctypes.c_int), ("ladder_mode", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("ladder_mode", ctypes.c_int), ("ladder_mode_fp64", ctypes.c_int),
+                ("memory_mode", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -130,14 +131,17 @@ def build_info() -> str:
 LADDER_FULL, LADDER_DIRECT, LADDER_TRIANGLE = 0, 1, 2
 
 
-def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full"):
+def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", ladder_fp64=None, memory="auto"):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
     lib.lrcc_default_config(ctypes.byref(cfg))
     cfg.precision = {"fp64": FP64, "mixed": MIXED}[precision]
     cfg.diis_size = diis
-    cfg.ladder_mode = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}[ladder]
+    modes = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}
+    cfg.ladder_mode = modes[ladder]
+    cfg.ladder_mode_fp64 = -1 if ladder_fp64 is None else modes[ladder_fp64]
+    cfg.memory_mode = {"auto": 0, "resident": 1, "lean": 2}[memory]
     return int(lib.lrcc_workspace_bytes(ctypes.byref(cfg), o, v, naux, nrhs))
 
 
@@ -184,7 +188,7 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True, graphs=None, ladder="full"):
+                 verbose=0, autotune=True, graphs=None, ladder="full", ladder_fp64=None, memory="auto"):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -203,7 +207,12 @@ class Context:
             cfg.graphs = int(graphs)
         # storage of the vvvv matrix: "full", "direct" (rebuilt from the DF
         # factors in every ladder) or "triangle" (upper triangle only)
-        cfg.ladder_mode = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}[ladder]
+        modes = {"full": LADDER_FULL, "direct": LADDER_DIRECT, "triangle": LADDER_TRIANGLE}
+        cfg.ladder_mode = modes[ladder]
+        # W of the FP64 products in mixed precision (None: as `ladder`)
+        cfg.ladder_mode_fp64 = -1 if ladder_fp64 is None else modes[ladder_fp64]
+        # "auto", "resident" (dense integral blocks) or "lean" (packed / formed on use)
+        cfg.memory_mode = {"auto": 0, "resident": 1, "lean": 2}[memory]
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:

@@ -259,3 +259,17 @@ def test_fnspp_projection_list_matches_oracle():
     I.run(ops, env)
     assert np.abs(env[I.id("s1")] - 0.5 * tA1.numpy()).max() < 1e-14
     assert np.abs(env[I.id("s2")] - tA2.numpy()).max() < 1e-14
+
+
+def test_workspace_estimate_fits_largest_config_in_lean_layout():
+    """The footprint estimate of the o=40, v=400 mixed pipeline with one
+    right-hand side per batch in the lean layout (FP32 W as its triangle,
+    FP64 ladder rebuilt from the factors) fits one MI355X (288 GB); the
+    resident layout with both full W does not."""
+    from paper_2503_23144_amd import lrcc
+    lean = lrcc.workspace_bytes(40, 400, 800, 1, precision="mixed", ladder="triangle", ladder_fp64="direct",
+                                memory="lean")
+    resident = lrcc.workspace_bytes(40, 400, 800, 1, precision="mixed", memory="resident")
+    assert 0 < lean < 250e9 < 288e9 < resident
+    # the plain FP64 solver with the rebuilt ladder fits as well
+    assert lrcc.workspace_bytes(40, 400, 800, 1, precision="fp64", ladder="direct", memory="lean") < 250e9
