@@ -1,15 +1,25 @@
 """Benchmark: LR-CCSD Jacobian-product throughput on one MI355X.
 
-A step is one pass of the whole hot path over one synthetic system:
-integral blocks from density-fitting factors, ground-state T, Lambda, the
-batched X(w)/Y(w) solves for 3 dipole directions x n_w frequencies, and the
-polarizability tensor.  `value` is Jacobian-vector products (sigma
-evaluations, right or left, per right-hand side) completed per second over
-the timed steps, for the mixed-precision batched solver (FP32 3M products on
-MFMA, FP64 residuals/updates).  The same pass in plain FP64 is timed once
-beside it, and the alpha tensors of the two are compared.
+Headline (default, workload c5: o=40, v=400, naux=800, the largest
+configuration, about 30 % of the 1300-virtual spaces the paper truncates):
+a step is one batched right Jacobian product (sigma = A X, Eqs. 29-30) over a
+chunk of right-hand sides of the 3 dipole directions x 64 frequencies, in
+mixed precision (complex FP32 3M products on MFMA, the FP64 diagonal),
+inputs resident in HBM.  `value` is sigma evaluations (one per right-hand
+side) per second over the timed steps.  Beside it, in the same record:
+  * the plain FP64 solver's product (one right-hand side per product, FP64
+    4M on MFMA) at the same size, and the mixed / plain ratio;
+  * parity at full size: the mixed product against the FP64 one, and the
+    adjoint identity u.(A v) = (u A).v with FP64 products;
+  * the ladder kernel's roofline (HIP-event time of its launches);
+  * a full T -> Lambda -> X, Y -> alpha solve at o=40, v=400 on a subset of
+    the frequencies (mixed precision), and alpha by both routes (Eq. 35 and
+    Eq. 36);
+  * the full pass at o=20, v=150 (integrals, T, Lambda, 48 X and 48 Y,
+    alpha) as a secondary figure;
+  * the FP64 oracle on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c3]
 """
 from __future__ import annotations
 
@@ -57,8 +67,9 @@ def measured_traffic(workload):
     has not changed since (else None)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "ladder_o20_v150_hbm_traffic.md")
-    if workload != "c3" or not os.path.exists(path):
+    name = {"c3": "ladder_o20_v150_hbm_traffic.md", "c5": "ladder_o40_v400_hbm_traffic.md"}.get(workload)
+    path = os.path.join(ROOT, "profiles", name or "-")
+    if name is None or not os.path.exists(path):
         return None
     m = re.search(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_src_sha256_16=([0-9a-f]{16})", open(path).read())
     if not m or gemm_source_hash() != m.group(3):
@@ -186,12 +197,20 @@ def _sampled_entries(A, W, C, dt, count=48):
     return {"entries": count, "max_err_over_eps_scale": ratio, "bound": bound, "ok": bool(ok)}
 
 
-def gemm_probe(lrcc, o=20, v=150, nrhs=48, tile=0):
-    """C = A W^T with the shape of the o=20, v=150 ladder at full batch
-    (M = nrhs * o(o-1)/2, N = K = v(v-1)/2, complex64), three launches with
-    one pinned workgroup tile; prints each launch time."""
+def gemm_probe(lrcc, o=20, v=150, nrhs=48, tile=0, calibrate=False):
+    """C = A W^T with the shape of a batched ladder (M = nrhs * o(o-1)/2,
+    N = K = v(v-1)/2, complex64), three launches with one pinned workgroup
+    tile; prints each launch time.  calibrate: first one plain 1 GiB device
+    copy, the reference for the HBM byte counters."""
     import torch
     dev = torch.device("cuda:0")
+    if calibrate:
+        src = torch.ones(2**27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1 GiB read, 1 GiB written", file=sys.stderr, flush=True)
+        del src, dst
     po, pv = o * (o - 1) // 2, v * (v - 1) // 2
     g = torch.Generator(device=dev)
     g.manual_seed(5)
@@ -372,15 +391,196 @@ def cpu_baseline(inp, budget_s=25.0):
                       f"integral build excluded ({dt:.1f} s)"}
 
 
+def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0):
+    c = lrcc.Context(precision=precision, tol=tol, ladder=ladder, ladder_fp64=ladder_fp64, memory="lean",
+                     rhs_chunk=chunk)
+    c.load_df(inp.o, inp.v, dev_in["B"])
+    c.load_fock(dev_in["fock"])
+    c.load_dipoles(dev_in["mu"])
+    return c
+
+
+def _probe_set(n, nb, seed=5):
+    """Seeded amplitudes T (0.01 N(0,1) complex) and nb right-hand sides X
+    (N(0,1) complex) for the product legs; the work of a Jacobian product
+    does not depend on the values."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = 0.01 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+    X = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    return t, X
+
+
+def sigma_leg(lrcc, inp, dev_in, nb, steps, warmup):
+    """The headline: batched mixed-precision right products at full size.
+    FP32 W resident (the ladder's operand), the FP64 ladder rebuilt from the
+    factors (it serves only FP64 products, none timed here)."""
+    import torch
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    c = _c5_context(lrcc, inp, dev_in, "mixed", "full", "direct")
+    t, Xh = _probe_set(c.n, nb)
+    c.set_amplitudes(lrcc.AMP_T, t)
+    X = torch.tensor(Xh, dtype=torch.complex128, device=dev)
+    out = torch.empty_like(X)
+    setup = time.perf_counter() - t0
+    print(f"[bench] c5 mixed context ready ({setup:.1f} s), n = {c.n}, batch {nb}", file=sys.stderr, flush=True)
+    for w in range(warmup):
+        tw = time.perf_counter()
+        c.sigma("right", X, precision="mixed", out=out)
+        torch.cuda.synchronize()
+        print(f"[bench] c5 warmup {w}: {time.perf_counter() - tw:.2f} s", file=sys.stderr, flush=True)
+    c.set_timing(True)  # HIP events around every GEMM launch, on the executor's stream
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ladder, allg = [0.0, 0, 0.0], [0.0, 0, 0.0]
+    for k in range(steps):
+        c.sigma("right", X, precision="mixed", out=out)
+        torch.cuda.synchronize()
+        for acc, cls in ((ladder, 0), (allg, 2)):  # each product reports its own launches
+            for q, x in enumerate(c.kernel_time(cls)):
+                acc[q] += x
+        print(f"[bench] c5 step {k}: {time.perf_counter() - ts:.2f} s", file=sys.stderr, flush=True)
+    dt = time.perf_counter() - ts
+    c.set_timing(False)
+    row0 = out[0].cpu().numpy()
+    c.close()
+    del X, out
+    lrcc.trim_memory()
+    torch.cuda.empty_cache()
+    return {"value": steps * nb / dt, "seconds": dt, "steps": steps, "batch": nb, "setup_s": setup,
+            "ladder": ladder, "gemm": allg, "row0_mixed": row0, "t": t, "X0": Xh[0], "n": len(t)}
+
+
+def fp64_plain_leg(lrcc, inp, dev_in, t, X0, reps=3):
+    """The plain FP64 solver's product at full size: one right-hand side per
+    product, FP64 W resident.  Also the parity checks at this size: the
+    adjoint identity u.(A v) = (u A).v and the FP64 product of the first
+    right-hand side for the mixed leg's comparison."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    c = _c5_context(lrcc, inp, dev_in, "fp64", "full")
+    c.set_amplitudes(lrcc.AMP_T, t)
+    X = torch.tensor(X0[None], dtype=torch.complex128, device=dev)
+    out = torch.empty_like(X)
+    setup = time.perf_counter() - t0
+    c.sigma("right", X, precision="fp64", out=out)  # warm-up: tiles of the FP64 shapes
+    torch.cuda.synchronize()
+    print(f"[bench] c5 fp64 context ready ({setup:.1f} s) and warm", file=sys.stderr, flush=True)
+    c.set_timing(True)
+    ts = time.perf_counter()
+    ladder = [0.0, 0, 0.0]
+    for k in range(reps):
+        c.sigma("right", X, precision="fp64", out=out)
+        torch.cuda.synchronize()
+        for q, x in enumerate(c.kernel_time(1)):
+            ladder[q] += x
+    dt = time.perf_counter() - ts
+    c.set_timing(False)
+    r64 = out[0].cpu().numpy()
+    rng = np.random.default_rng(23)
+    U = torch.tensor((rng.standard_normal(c.n) + 1j * rng.standard_normal(c.n))[None], dtype=torch.complex128,
+                     device=dev)
+    UA = torch.empty_like(U)
+    c.sigma("left", U, precision="fp64", out=UA)
+    torch.cuda.synchronize()
+    lhs = complex((U[0] * out[0]).sum())
+    rhs = complex((UA[0] * X[0]).sum())
+    c.close()
+    del X, out, U, UA
+    lrcc.trim_memory()
+    torch.cuda.empty_cache()
+    print(f"[bench] c5 fp64 plain: {reps / dt:.3f} products/s", file=sys.stderr, flush=True)
+    return {"sigma_evals_per_s": reps / dt, "seconds": dt, "products": reps, "setup_s": setup,
+            "ladder_tflops": ladder[2] / max(ladder[0] / 1e3, 1e-30) / 1e12, "ladder_ms_per_launch":
+            ladder[0] / max(ladder[1], 1), "adjoint_identity_rel": abs(lhs - rhs) / abs(lhs), "row0_fp64": r64}
+
+
+def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6):
+    """A full T -> Lambda -> X, Y -> alpha solve at full size in mixed
+    precision on a subset of the frequencies (one right-hand side per
+    product: the FP32 W as its Hermitian triangle, the FP64 ladder rebuilt,
+    so that the solver's buffers fit beside it), then alpha by Eq. 36."""
+    import numpy as np
+    import torch
+    out = {"omegas": list(omegas), "tol_residual": tol, "ladder": "FP32 triangle, FP64 rebuilt from the factors",
+           "rhs_per_product": 1}
+    t0 = time.perf_counter()
+    c = _c5_context(lrcc, inp, dev_in, "mixed", "triangle", "direct", tol=tol, chunk=1)
+    out["integrals_s"] = time.perf_counter() - t0
+    t = time.perf_counter()
+    e, st0 = c.solve_ground()
+    out["ground"] = {"seconds": time.perf_counter() - t, "ecorr": [e.real, e.imag], "iterations": st0["iterations"]}
+    print(f"[bench] c5 solve: ground {out['ground']}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    st1 = c.solve_lambda()
+    out["lambda"] = {"seconds": time.perf_counter() - t, "iterations": st1["iterations"]}
+    t = time.perf_counter()
+    per = c.solve_response(omegas)
+    out["response"] = {"seconds": time.perf_counter() - t, "iterations": [p["iterations"] for p in per],
+                       "sigma_evals": int(sum(p["sigma_evals"] for p in per)),
+                       "converged": bool(all(p["converged"] for p in per))}
+    a35 = c.alpha(len(omegas))
+    print(f"[bench] c5 solve: response {out['response']}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    per = c.solve_response(omegas, quadratic=True)
+    out["eq36"] = {"seconds": time.perf_counter() - t, "converged": bool(all(p["converged"] for p in per))}
+    a36 = c.alpha(len(omegas))
+    c.close()
+    lrcc.trim_memory()
+    torch.cuda.empty_cache()
+    out["alpha_iso"] = [float(x) for x in np.real(np.trace(a35, axis1=-2, axis2=-1)) / 3.0]
+    out["alpha"] = [[[complex(z).real, complex(z).imag] for z in row] for row in np.asarray(a35[0])]
+    out["alpha_rel_diff_eq36_vs_eq35"] = float(np.abs(a36 - a35).max() / np.abs(a35).max())
+    out["seconds"] = time.perf_counter() - t0
+    print(f"[bench] c5 solve: {out['seconds']:.1f} s, eq36 vs eq35 {out['alpha_rel_diff_eq36_vs_eq35']:.1e}",
+          file=sys.stderr, flush=True)
+    return out, a35
+
+
+def cpu_baseline_scaled(budget_s=25.0):
+    """The oracle, as it stands, on the host cores.  It holds dense vvvv
+    (410 GB at o=40, v=400), so it is timed at o=20, v=150 (one right-hand
+    side per product) and its rate scaled to o=40, v=400 by the ratio of the
+    estimated complex multiply-adds per product."""
+    from paper_2503_23144_amd.synth import config_inputs
+    inp = config_inputs("c3")
+    r = cpu_baseline(inp, budget_s=budget_s)
+    macs = lambda o, v: (o * (o - 1) / 2) * (v * (v - 1) / 2) ** 2 + (o * v) ** 3 \
+        + o * v * (o * (o - 1) / 2) * (v * (v - 1) / 2) + 2 * (o * (o - 1) / 2) ** 2 * (v * (v - 1) / 2) \
+        + 3 * (o ** 2 * v ** 3 + o ** 3 * v ** 2)
+    scale = macs(20, 150) / macs(40, 400)
+    r["measured_at_o20_v150"] = r["value"]
+    r["value"] = r["value"] * scale
+    r["sample"] = (r["sample"] + f"; scaled to o=40, v=400 by the estimated complex MACs per product "
+                   f"(x{scale:.3g}), i.e. extrapolated")
+    r["extrapolated"] = True
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3"])
+    ap.add_argument("--chunk", type=int, default=4, help="right-hand sides per batched product (c5)")
+    ap.add_argument("--solve-omega", type=float, default=0.25,
+                    help="frequency of the full o=40, v=400 solve (3 dipole directions)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 product leg (c5)")
+    ap.add_argument("--no-solve", action="store_true", help="skip the full o=40, v=400 solve (c5)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the o=20, v=150 full pass (c5)")
+    ap.add_argument("--solve-fp64", action="store_true",
+                    help="also the plain FP64 solve at o=40, v=400 on the same frequency, for the mixed-vs-FP64 "
+                         "alpha comparison (about 5 minutes)")
     ap.add_argument("--fp64", default="both", choices=["none", "plain", "batched", "both"],
-                    help="FP64 comparison passes: plain (one RHS per product) and/or batched")
+                    help="FP64 comparison passes of the c3 pass: plain (one RHS per product) and/or batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--extras", action="store_true",
+                    help="also the o=20, v=150 legs: Eq. 36 pass, ladder storage modes, truncation curve, "
+                         "per-size product rates, the o=40, v=400 ladder on random operands")
     ap.add_argument("--no-ladder-scale", action="store_true", help="skip the o=40, v=400 ladder measurement")
     ap.add_argument("--no-sigma-table", action="store_true", help="skip the per-workload product rates")
     ap.add_argument("--no-eq36", action="store_true", help="skip the Eq. 36 (X(w), X(-w)) pass")
@@ -388,8 +588,8 @@ def main():
     ap.add_argument("--no-ladder-modes", action="store_true",
                     help="skip the passes with the DF-direct and the triangle-stored ladder")
     ap.add_argument("--gemm-probe", action="store_true",
-                    help="only launch the o=20, v=150 ladder GEMM (48 right-hand sides, FP32 3M, 64 x 64 tile) "
-                         "three times, for hardware counter runs")
+                    help="only launch the ladder GEMM of the workload (c5: 4 x 780 rows of packed doubles "
+                         "against the 79800 x 79800 W, FP32 3M) three times, for hardware counter runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     # residual tolerances that meet each path's alpha target (mixed: 1e-6
@@ -401,7 +601,151 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if not args.extras:
+        args.no_eq36 = args.no_ladder_modes = args.no_truncation = args.no_sigma_table = True
+        args.no_ladder_scale = True
+    if args.workload == "c3":
+        return main_full_pass(args)
+    main_c5(args)
 
+
+def main_c5(args):
+    import numpy as np
+    import torch
+
+    from paper_2503_23144_amd import lrcc
+    from paper_2503_23144_amd.synth import CONFIGS, config_inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gemm_probe:
+        gemm_probe(lrcc, o=40, v=400, nrhs=args.chunk, tile=0, calibrate=args.calibrate_copy)
+        return
+    inp = config_inputs("c5")
+    cfg = CONFIGS["c5"]
+    print(f"[bench] workload c5: o={inp.o} v={inp.v} naux={inp.naux} nw={len(inp.omegas)} gap={inp.gap:.3f}",
+          file=sys.stderr, flush=True)
+    dev_in = resident(inp)
+    nb = args.chunk
+    sig = sigma_leg(lrcc, inp, dev_in, nb, args.steps, args.warmup)
+    value = sig["value"]
+    ladder_ms, ladder_n, ladder_fl = sig["ladder"]
+    gemm_ms, gemm_n, gemm_fl = sig["gemm"]
+    ladder_avg_s = ladder_ms / 1e3 / max(ladder_n, 1)
+    ladder_tf = ladder_fl / max(ladder_ms / 1e3, 1e-30) / 1e12
+    traffic = measured_traffic("c5")
+    po, pv = inp.o * (inp.o - 1) // 2, inp.v * (inp.v - 1) // 2
+    out = {
+        "metric": METRIC, "value": value, "unit": "sigma evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * sig["seconds"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 products (3M on FP32 MFMA) + c128 diagonal",
+        "data": "synthetic",
+        "config": {"workload": f"c5: o={cfg['o']} v={cfg['v']} naux={cfg['naux']} (O={po}, V={pv} packed pairs; "
+                               f"W {pv * pv * 8 / 1e9:.1f} GB FP32 in HBM), batched mixed-precision right Jacobian "
+                               f"products over chunks of {nb} of the 3 dipole directions x {len(cfg['omegas'])} omegas "
+                               f"in [0,{max(cfg['omegas']):.1f}] Ha",
+                   "precision": "mixed", "rhs_per_product": nb, "memory_layout": "lean",
+                   "amplitudes": "seeded random T (0.01 N(0,1)) and X (N(0,1)), complex"},
+        "ladder_tflops": ladder_tf,
+        "ladder_complex_equiv_tflops": ladder_tf * 8.0 / 6.0,
+        "gemm_all_tflops": gemm_fl / max(gemm_ms / 1e3, 1e-30) / 1e12, "gemm_all_ms_per_step": gemm_ms / args.steps,
+        "gemm_launches_per_step": gemm_n / args.steps,
+        "roofline": {"bound": "mfma", "achieved": ladder_tf, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                     "frac": ladder_tf / PEAK["fp32"],
+                     "traffic": (traffic or {}).get("bytes_per_launch"), "traffic_unit": "bytes per launch",
+                     "traffic_source": traffic,
+                     "algorithmic_flops_per_launch": 6.0 * nb * po * pv * pv,
+                     "kernel": "zgemm_kernel<float, false, true, 1, ...> (packed vvvv ladder, 3M)",
+                     "avg_launch_ms": 1e3 * ladder_avg_s, "launches": ladder_n},
+        "setup_s": sig["setup_s"],
+    }
+    if not args.no_fp64:
+        fp = fp64_plain_leg(lrcc, inp, dev_in, sig["t"], sig["X0"])
+        mvf = float(np.abs(sig["row0_mixed"] - fp["row0_fp64"]).max() / np.abs(fp["row0_fp64"]).max())
+        out["fp64_plain"] = {k: v for k, v in fp.items() if k != "row0_fp64"}
+        out["fp64_plain"]["sample"] = (f"{fp['products']} right products of one right-hand side each at o=40, v=400, "
+                                       "FP64 W (102 GB) resident")
+        out["mixed_over_fp64_plain_sigma_rate"] = value / fp["sigma_evals_per_s"]
+        out["check_mixed_vs_fp64_rel"] = mvf
+        out["check_adjoint_identity_rel"] = fp["adjoint_identity_rel"]
+        print(f"[bench] c5 checks: mixed vs FP64 {mvf:.2e}, adjoint identity {fp['adjoint_identity_rel']:.2e}",
+              file=sys.stderr, flush=True)
+        assert mvf < 2e-5 and fp["adjoint_identity_rel"] < 1e-10, "products at full size fail their checks"
+    if not args.no_solve:
+        out["c5_solve"], a35 = solve_leg(lrcc, inp, dev_in, [args.solve_omega], tol=args.tol)
+        sv = out["c5_solve"]
+        if args.solve_fp64:
+            t = time.perf_counter()
+            c = _c5_context(lrcc, inp, dev_in, "fp64", "full", tol=args.tol64, chunk=1)
+            c.solve_ground()
+            c.solve_lambda()
+            c.solve_response([args.solve_omega])
+            a64 = c.alpha(1)
+            c.close()
+            lrcc.trim_memory()
+            sv["fp64_solve_s"] = time.perf_counter() - t
+            sv["alpha_rel_diff_mixed_vs_fp64"] = float(np.abs(a35 - a64).max() / np.abs(a64).max())
+            print(f"[bench] c5 fp64 solve: {sv['fp64_solve_s']:.1f} s, mixed vs FP64 alpha "
+                  f"{sv['alpha_rel_diff_mixed_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+        out["c5_solve"]["subset"] = (f"3 dipole directions x 1 of the 64 frequencies (omega = {args.solve_omega} Ha); "
+                                     "T, Lambda, X, Y, alpha by Eq. 35, then X(w), X(-w) and alpha by Eq. 36")
+        out["c5_solve"]["response_sigma_evals_per_s"] = sv["response"]["sigma_evals"] / sv["response"]["seconds"]
+    del dev_in
+    lrcc.trim_memory()
+    torch.cuda.empty_cache()
+    if not args.no_c3:
+        out["c3_full_pass"] = c3_pass(lrcc, args)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_scaled()
+        out["cpu_baseline"]["host"] = host_info()
+    print(json.dumps(out))
+
+
+def c3_pass(lrcc, args):
+    """The full pass at o=20, v=150: integrals, T, Lambda, 48 X and 48 Y,
+    alpha, mixed precision, with the plain FP64 solver timed on two of the
+    16 frequencies beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2503_23144_amd.synth import config_inputs
+    inp = config_inputs("c3")
+    dev_in = resident(inp)
+    run_pass(lrcc, inp, "mixed", args.tol, dev_in=dev_in)  # warm-up (tiles of the new shapes)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = run_pass(lrcc, inp, "mixed", args.tol, timing=True, dev_in=dev_in)
+    torch.cuda.synchronize()
+    d = time.perf_counter() - t
+    lm, ln, lf = r["ladder"]
+    out = {"workload": "c3: o=20 v=150 naux=300, 3 dipole directions x 16 omegas in [0,0.3] Ha, full pass",
+           "sigma_evals_per_s": r["sigma_evals"] / d, "seconds": d, "phases_s": r["phases"],
+           "response_sigma_evals_per_s": r["resp_sigma_evals"] / r["phases"]["response"],
+           "ladder_tflops": lf / max(lm / 1e3, 1e-30) / 1e12, "ladder_avg_launch_ms": lm / max(ln, 1)}
+    if args.fp64 in ("both", "plain"):
+        sub = dataclasses.replace(inp, omegas=inp.omegas[:2])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r64 = run_pass(lrcc, sub, "fp64", args.tol64, chunk=1, dev_in=dev_in)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t
+        out["fp64_plain"] = {"sigma_evals_per_s": r64["sigma_evals"] / d64, "seconds": d64,
+                             "response_sigma_evals_per_s": r64["resp_sigma_evals"] / r64["phases"]["response"],
+                             "sample": "6 right-hand sides (2 of 16 frequencies), one per product",
+                             "alpha_rel_diff_mixed_vs_this": float(np.abs(r["alpha"][:2] - r64["alpha"]).max()
+                                                                   / np.abs(r64["alpha"]).max())}
+        out["mixed_over_fp64_plain_sigma_rate"] = out["sigma_evals_per_s"] / out["fp64_plain"]["sigma_evals_per_s"]
+        out["mixed_over_fp64_plain_response_rate"] = (out["response_sigma_evals_per_s"]
+                                                      / out["fp64_plain"]["response_sigma_evals_per_s"])
+    print(f"[bench] c3 full pass: {d:.1f} s, {out['sigma_evals_per_s']:.1f} sigma evals/s", file=sys.stderr,
+          flush=True)
+    del dev_in
+    lrcc.trim_memory()
+    torch.cuda.empty_cache()
+    return out
+
+
+def main_full_pass(args):
+    """The o=20, v=150 full pass as the headline (--workload c3)."""
     import numpy as np
     import torch
 

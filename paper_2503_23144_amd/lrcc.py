@@ -14,7 +14,9 @@ import re
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblrcc.so")
+# LRCC_LIBRARY names another build of the library (e.g. the host-sanitized
+# one that the host-side checks run against)
+LIB_PATH = os.environ.get("LRCC_LIBRARY") or os.path.join(HERE, "liblrcc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lrcc.h")
 
 OK, E_INVALID, E_STATE, E_NOMEM, E_HIP, E_NOCONV, E_SINGULAR, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7

@@ -259,6 +259,47 @@ def test_polarizability_mixed_precision_close_to_fp64():
     assert _relerr(res["mixed"], res["fp64"]) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_uneven_convergence_in_chunks_matches_single_solves(precision):
+    """One frequency just below the first excitation (slow convergence)
+    among easy ones, 9 right-hand sides solved in batches of 2 (slots
+    compacted as right-hand sides converge at different iterations): every
+    right-hand side's X, Y and iteration count equal those of its own
+    single-right-hand-side solve, and alpha matches the oracle."""
+    from oracle.response import lr_ccsd
+    o, v = 3, 12
+    inp = make_inputs(o, v, 12, seed=41)
+    inp.B = inp.B * 8.0
+    # 0.03 below the lowest eigenvalue of the Jacobian at this input (1.2852,
+    # from the oracle's dense Jacobian; the orbital gap is 1.1755)
+    w_near = 1.255
+    omegas = [0.0, w_near, 0.1]
+    tol = 1e-11 if precision == "fp64" else 1e-10
+    res = {}
+    for chunk in (2, 1):
+        c = _ctx(inp, precision=precision, tol=tol, rhs_chunk=chunk)
+        c.solve_ground()
+        c.solve_lambda()
+        per = c.solve_response(omegas)
+        assert all(s["converged"] for s in per)
+        X = [c.get_amplitudes(_lrcc().AMP_X, r) for r in range(9)]
+        Y = [c.get_amplitudes(_lrcc().AMP_Y, r) for r in range(9)]
+        res[chunk] = (per, X, Y, c.alpha(len(omegas)))
+        c.close()
+    per2, X2, Y2, a2 = res[2]
+    per1, X1, Y1, a1 = res[1]
+    it = [s["iterations"] for s in per2]
+    # the near-pole right-hand sides (k = 1) take clearly more iterations
+    assert min(it[3:6]) >= max(it[0:3]) + 3, it
+    for r in range(9):
+        assert _relerr(X2[r], X1[r]) < 1e-9 and _relerr(Y2[r], Y1[r]) < 1e-9, r
+        for side in (0, 9):
+            assert abs(per2[side + r]["iterations"] - per1[side + r]["iterations"]) <= 1, (r, side)
+    ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
+    assert _relerr(a2, ref.alpha) < (1e-8 if precision == "fp64" else 1e-6)
+    assert _relerr(a2, a1) < 1e-9
+
+
 # ------------------------------------------------------------------ Eq. 36 route
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
 def test_quadratic_route_matches_oracle_eq36(name, o, v, naux, scale, seed):
