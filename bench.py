@@ -211,6 +211,8 @@ def gemm_probe(lrcc, o=20, v=150, nrhs=48, tile=0, calibrate=False):
         torch.cuda.synchronize()
         print("[bench] calibration copy: 1 GiB read, 1 GiB written", file=sys.stderr, flush=True)
         del src, dst
+    if nrhs == 0:
+        return
     po, pv = o * (o - 1) // 2, v * (v - 1) // 2
     g = torch.Generator(device=dev)
     g.manual_seed(5)
@@ -617,8 +619,10 @@ def main_c5(args):
     from paper_2503_23144_amd.synth import CONFIGS, config_inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:  # reference for the HBM byte counters: 1 GiB read, 1 GiB written
+        gemm_probe(lrcc, calibrate=True, nrhs=0)
     if args.gemm_probe:
-        gemm_probe(lrcc, o=40, v=400, nrhs=args.chunk, tile=0, calibrate=args.calibrate_copy)
+        gemm_probe(lrcc, o=40, v=400, nrhs=args.chunk, tile=0)
         return
     inp = config_inputs("c5")
     cfg = CONFIGS["c5"]

@@ -549,6 +549,28 @@ def test_c3_matches_stored_oracle():
     assert abs(e - complex(ref["ecorr"])) < 1e-9 * abs(complex(ref["ecorr"]))
 
 
+def test_c3_static_alpha_matches_finite_field_oracle():
+    """o=20, v=150, the o=20, v=150 workload: the static alpha_zz of the FP64
+    GPU solver against minus the second derivative of the oracle's CCSD
+    energy in the field strength (f -> f + h mu_z, central differences at
+    h = 1e-3 and 5e-4 with one Richardson step; tests/golden/
+    make_finite_field_c3.py), whose own error is about 1e-9 relative."""
+    import os
+    from paper_2503_23144_amd.synth import config_inputs
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c3_ff.npz"))
+    inp = config_inputs("c3")
+    inp.mu = inp.mu[2:3]
+    c = _ctx(inp, tol=1e-11)
+    e, _ = c.solve_ground()
+    # the zero-field energy of the finite-field set
+    assert abs(e - complex(ref["energies"][2])) < 1e-9 * abs(e)
+    c.solve_lambda()
+    c.solve_response([0.0])
+    al = c.alpha(1)[0, 0, 0]
+    assert abs(al.imag) < 1e-12 * abs(al)
+    assert abs(al.real - float(ref["alpha_zz_static"])) < 1e-7 * abs(al)
+
+
 # ------------------------------------------------------------------ DF-direct ladder (no resident W)
 @pytest.mark.parametrize("mode", ["direct", "triangle"])
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
