@@ -51,6 +51,8 @@ OpList parse_program(Module& m, const std::string& text) {
   static const std::regex re_pack(R"(^(pack|unpack)\(\s*(\w+)\[(\w*)\]\s*,\s*([01])(?:\s*,\s*([01]))?\s*\)$)");
   static const std::regex re_prod(R"(^(\w+)\[(\w*)\]\s*\*\s*(\w+)\[(\w*)\]$)");
   static const std::regex re_one(R"(^(\w+)\[(\w*)\]$)");
+  static const std::regex re_nodiff(R"(^nodiff\(\s*(\w+)\[(\w*)\]\s*\)$)");
+  static const std::regex re_partner(R"(^(\w+)\[(\w*)\]\s*\*\s*(\w+)\[(\w*)\]\s*~\s*(\w+)\[(\w*)\]$)");
 
   OpList ops;
   std::set<int> read;      // tensors already read (no further writes allowed)
@@ -117,6 +119,25 @@ OpList parse_program(Module& m, const std::string& text) {
       op.ai = mx[2];
       op.b = use(mx[3], mx[4]);
       op.bi = mx[4];
+    } else if (std::regex_match(rhs, mx, re_partner)) {
+      op.kind = OpKind::Contract;
+      op.a = use(mx[1], mx[2]);
+      op.ai = mx[2];
+      op.b = use(mx[3], mx[4]);
+      op.bi = mx[4];
+      if (mx[6] != mx[4]) fail("the partner must carry the indices of the second operand");
+      op.partner = use(mx[5], mx[6]);
+      if (m[op.partner].cls != m[op.b].cls) fail("partner and second operand differ in class");
+    } else if (std::regex_match(rhs, mx, re_nodiff)) {
+      op.kind = OpKind::Add;
+      op.nodiff = true;
+      op.a = use(mx[1], mx[2]);
+      op.ai = mx[2];
+      if (!op.acc) fail("nodiff must accumulate into a tensor written before");
+      std::string x = op.ai, y = op.oi;
+      std::sort(x.begin(), x.end());
+      std::sort(y.begin(), y.end());
+      if (x != y) fail("copy must permute indices");
     } else if (std::regex_match(rhs, mx, re_one)) {
       op.kind = OpKind::Add;
       op.a = use(mx[1], mx[2]);
@@ -128,7 +149,7 @@ OpList parse_program(Module& m, const std::string& text) {
     } else {
       fail("bad right-hand side");
     }
-    if (op.a == op.out || op.b == op.out) fail("in-place update");
+    if (op.a == op.out || op.b == op.out || op.partner == op.out) fail("in-place update");
     ops.push_back(op);
   }
   return ops;
@@ -154,15 +175,19 @@ OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::ve
       live.erase(op.out);
       continue;
     }
+    if (op.nodiff) continue;  // left out of derivatives (an accumulation: liveness unchanged)
     if (op.kind == OpKind::Contract) {
       if (lv(op.a)) {
         Op c = op;
         c.a = tangent_of(m, tan, op.a, tag);
+        if (op.partner >= 0) c.b = op.partner;
+        c.partner = -1;
         contrib.push_back(c);
       }
       if (lv(op.b)) {
         Op c = op;
         c.b = tangent_of(m, tan, op.b, tag);
+        c.partner = -1;
         contrib.push_back(c);
       }
     } else if (lv(op.a)) {
@@ -195,7 +220,7 @@ OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::ve
            bool batched, const std::string& tag) {
   std::set<int> act(wrt.begin(), wrt.end());
   for (const Op& op : prog)
-    if (act.count(op.a) || (op.b >= 0 && act.count(op.b))) act.insert(op.out);
+    if (!op.nodiff && (act.count(op.a) || (op.b >= 0 && act.count(op.b)))) act.insert(op.out);
   std::set<int> live;
   for (auto& kv : adj) live.insert(kv.first);
   auto adjoint = [&](int t) {
@@ -214,7 +239,7 @@ OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::ve
   };
   for (auto it = prog.rbegin(); it != prog.rend(); ++it) {
     const Op& op = *it;
-    if (op.kind == OpKind::Zero || !live.count(op.out)) {
+    if (op.kind == OpKind::Zero || op.nodiff || !live.count(op.out)) {
       if (!op.acc) live.erase(op.out);
       continue;
     }
@@ -239,7 +264,7 @@ OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::ve
           d.oi = op.ai;
           d.a = g;
           d.ai = op.oi;
-          d.b = op.b;
+          d.b = op.partner >= 0 ? op.partner : op.b;
           d.bi = op.bi;
           emit(d, op.a);
         }
@@ -293,6 +318,7 @@ OpList prune(const Module& m, const OpList& prog, const std::vector<int>& keep) 
     use[k] = 1;
     if (op.a >= 0) need.insert(op.a);
     if (op.b >= 0) need.insert(op.b);
+    if (op.partner >= 0) need.insert(op.partner);
   }
   OpList out;
   for (size_t k = 0; k < prog.size(); ++k)
@@ -317,8 +343,11 @@ std::string dump(const Module& m, const OpList& prog) {
       return m[t].name + (m[t].batched ? "#" : "") + "[" + idx + "]";
     };
     switch (op.kind) {
-      case OpKind::Add: os << ref(op.a, op.ai); break;
-      case OpKind::Contract: os << ref(op.a, op.ai) << " * " << ref(op.b, op.bi); break;
+      case OpKind::Add: os << (op.nodiff ? "nodiff(" : "") << ref(op.a, op.ai) << (op.nodiff ? ")" : ""); break;
+      case OpKind::Contract:
+        os << ref(op.a, op.ai) << " * " << ref(op.b, op.bi);
+        if (op.partner >= 0) os << " ~ " << ref(op.partner, op.bi);
+        break;
       case OpKind::Pack:
       case OpKind::Unpack:
         os << (op.kind == OpKind::Pack ? "pack(" : "unpack(") << ref(op.a, op.ai) << ", " << op.mode[0]
@@ -343,7 +372,7 @@ std::string serialize(const Module& m, const OpList& prog) {
   for (const Op& op : prog)
     os << "O " << (int)op.kind << " " << (int)op.acc << " " << op.are << " " << op.aim << " " << op.out << " "
        << s(op.oi) << " " << op.a << " " << s(op.ai) << " " << op.b << " " << s(op.bi) << " " << op.mode[0] << " "
-       << op.mode[1] << "\n";
+       << op.mode[1] << " " << (int)op.nodiff << " " << op.partner << "\n";
   return os.str();
 }
 
@@ -355,7 +384,12 @@ std::string serialize(const Module& m, const OpList& prog) {
 // that belongs to W_abef is folded into W_mnij (coefficient 1/2).  W_mbej is
 // stored in ring order [j b m e] and its doubles term written with (e,f)
 // swapped in both factors, so both ring contractions of a Jacobian product
-// read the doubles in the same permuted order [i a m e].
+// read the doubles in the same permuted order [i a m e].  The part of
+// W_mbej quadratic in t2, Y = -1/2 t2 <mn||fe>, enters the ring term
+// t2 . (W1 + Y(t2)), which is read only through the antisymmetrizer of O2p;
+// there t2 . Y(c) = c . Y(t2) (swap (i,a) <-> (j,b), m <-> n, e <-> f), so
+// its derivative along dt is dt . (W1 + 2 Y) + t2 . dW1: the derivative
+// programs run one (ov)^3 ring contraction fewer (nodiff / partner below).
 const char* kCcsdProgram = R"(
 input  t1[ia] t2p[IA]
 fock   foo[ij] fov[ia] fvo[ai] fvv[ab]
@@ -389,11 +423,15 @@ Wmnij[mnij] += -1 * Xmnij[mnji]
 Wmnij[mnij] += 0.5 * tau[ijef] * goovv[mnef]
 
 Xmnej[mnej]  = t1[jf] * goovv[mnef]
-Wmbej[jbme]  = govvo[mbej]
-Wmbej[jbme] += t1[jf] * govvv[mbef]
-Wmbej[jbme] += t1[nb] * gooov[mnje]
-Wmbej[jbme] += -0.5 * t2[jnbf] * goovv[mnfe]
-Wmbej[jbme] += -1 * t1[nb] * Xmnej[mnej]
+W1[jbme]     = govvo[mbej]
+W1[jbme]    += t1[jf] * govvv[mbef]
+W1[jbme]    += t1[nb] * gooov[mnje]
+W1[jbme]    += -1 * t1[nb] * Xmnej[mnej]
+Yq[jbme]     = -0.5 * t2[jnbf] * goovv[mnfe]
+Wmbej[jbme]  = W1[jbme]
+Wmbej[jbme] += nodiff(Yq[jbme])
+W2[jbme]     = W1[jbme]
+W2[jbme]    += 2 * Yq[jbme]
 
 O1[ia]  = fvo[ai]
 O1[ia] += t1[ie] * Fae[ae]
@@ -413,7 +451,7 @@ Pab[ijab]    = t2[ijae] * Ft[be]
 Pab[ijab]   += -1 * t1[ma] * govoo[mbij]
 Pij[ijab]    = -1 * t2[imab] * Fmt[mj]
 Pij[ijab]   += t1[ie] * gvvvo[abej]
-Pijab[ijab]  = t2[imae] * Wmbej[jbme]
+Pijab[ijab]  = t2[imae] * Wmbej[jbme] ~ W2[jbme]
 Pijab[ijab] += -1 * t1[ma] * Xmbij[mbij]
 S0[ijab]     = gvvoo[abij]
 S0[ijab]    += 0.5 * tau[mnab] * Wmnij[mnij]

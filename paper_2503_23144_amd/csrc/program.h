@@ -49,6 +49,17 @@ struct Op {
   int b = -1;
   std::string bi;
   int mode[2] = {0, 0};
+  // Derivative annotations (the op itself runs as written):
+  //  nodiff    an Add whose contribution the derivative programs leave out;
+  //  partner   a Contract whose derivative with respect to its first
+  //            operand a takes the tensor `partner` (same indices as b) in
+  //            place of b.
+  // Together they express a term a . W(a) in which W = W1 + Y(a), with Y
+  // linear in a, and the output is read only through an antisymmetrizer
+  // under which a . Y(c) = c . Y(a): its derivative along da is then
+  // da . (W1 + 2 Y) + a . dW1, one contraction with da fewer.
+  bool nodiff = false;
+  int partner = -1;
 };
 
 using OpList = std::vector<Op>;
@@ -76,6 +87,8 @@ char letter_class(char c);
 //   X[idx]  = [c *] A[idx]                      Add (permuted copy)
 //   X[idx] += [c *] A[idx] * B[idx]             Contract
 //   X[idx] += [c *] pack(A[idx], m1[, m2])      Pack / unpack(...) Unpack
+//   X[idx] += nodiff(A[idx])                    Add left out of derivatives
+//   X[idx] = A[idx] * B[idx] ~ C[idx]           Contract; d/dA takes C for B
 OpList parse_program(Module& m, const std::string& text);
 
 // Forward-mode tangent program.  `tan` maps seed tensors to their (batched)
