@@ -284,8 +284,11 @@ int lrcc_kernel_time(lrcc_ctx *ctx, int cls, double *ms, int64_t *launches, doub
    timed; the ladder GEMMs are then launched between graph segments so that
    classes 0 and 1 stay complete. */
 int lrcc_set_timing(lrcc_ctx *ctx, int on);
-/* Program runs captured into HIP graphs and graph replays so far (FP64 and
-   FP32 executors together).  Either pointer may be NULL. */
+/* HIP graphs captured and replayed so far: program runs of the FP64 and
+   FP32 executors (lrcc_sigma and the like) and whole solver iterations
+   (product, residual, norms, convergence test, DIIS update; the solves run
+   each batch's iteration as one graph from its third occurrence).  Either
+   pointer may be NULL. */
 int lrcc_graph_stats(lrcc_ctx *ctx, int64_t *captures, int64_t *replays);
 
 /* Caller-owned device memory.  lrcc_workspace_bytes estimates (from sizes

@@ -449,6 +449,8 @@ int lrcc_graph_stats(lrcc_ctx* ctx, int64_t* captures, int64_t* replays) {
     int64_t cap = 0, rep = 0;
     if (c.x64) cap += c.x64->graph_captures(), rep += c.x64->graph_replays();
     if (c.x32) cap += c.x32->graph_captures(), rep += c.x32->graph_replays();
+    cap += c.iter_captures;
+    rep += c.iter_replays;
     if (captures) *captures = cap;
     if (replays) *replays = rep;
   });

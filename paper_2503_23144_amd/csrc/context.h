@@ -62,6 +62,8 @@ struct Context {
 
   lrcc_config cfg;
   hipStream_t st = nullptr;
+  hipStream_t cst = nullptr;  // private stream that whole solver iterations are captured on
+  int64_t iter_captures = 0, iter_replays = 0;  // whole-iteration graphs of the solvers
   std::string err;
 
   // sizes

@@ -142,12 +142,41 @@ void launch_zero_diag(void* p, int64_t n, hipStream_t st);
 // Xn = X - R / (D + s_r);  E = Xn - X  (either output may be null).  With
 // out_rows (device, nvec entries) row r of Xn and E is their row out_rows[r]
 // (e.g. a slot of a history ring); E2, when given, receives E at row r too.
+// With `active` (device, nvec flags) rows whose flag is 0 are left untouched.
 void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X,
                    const void* R, void* Xn, void* E, hipStream_t st, const int* out_rows = nullptr,
-                   void* E2 = nullptr);
-// X[r] = sum_k c[r*m + k] * H[(r*hs + k)*n + ...]
+                   void* E2 = nullptr, const int* active = nullptr);
+// X[r] = sum_k c[r*m + k] * H[(r*hs + k)*n + ...]  (rows with active[r] == 0 untouched)
 void launch_combine(int64_t nvec, int m, int64_t n, const void* c, const void* H, int64_t hs, void* X,
-                    hipStream_t st);
+                    hipStream_t st, const int* active = nullptr);
+
+// Per right-hand-side state of the device-resident DIIS iteration.
+struct DiisSlot {
+  double rn;     // last residual norm
+  double bnorm;  // reference norm (< 0: taken from the first residual)
+  double best;   // best residual norm by a factor 0.7 so far, and the evaluation it came at
+  int best_it;
+  int itc;       // residual evaluations so far
+  int iters;     // updates applied (evaluations that left the slot active)
+  int cnt;       // DIIS entries stored (<= m), ring position of the next one
+  int next;
+  int conv;      // 1: converged (residual <= tol * bnorm)
+  int bad;       // 1: residual not finite
+};
+// After the residual norms dots[r] = ||R_r||^2 of nvec active-or-not slots:
+// updates each active slot's state, deactivates it when converged or when
+// `stall` > 0 evaluations passed without a 0.7x improvement, and sets the
+// history row hrow[r] = r * m + next of the slots that stay active.
+void launch_diis_check(int64_t nvec, const void* dots, double tol, int stall, int m, DiisSlot* st_dev, int* active,
+                       int* hrow, hipStream_t st);
+// DIIS extrapolation coefficients of every active slot, on the device: the
+// new Gram row gram[r*m + k] = <e_k, e_new> enters the slot's Hermitian Gram
+// matrix G[r] (m x m) at the ring position, and [G 1; 1^T 0][c; l] = [0; 1]
+// over the stored entries is solved by Gaussian elimination with partial
+// pivoting on G / max|G_kk|; coef[r*m + k] = c_k (0 for empty positions).
+// A singular system restarts the slot's subspace from its newest entry.
+void launch_diis_coef(int64_t nvec, int m, const void* gram, DiisSlot* st_dev, const int* active, void* G,
+                      void* coef, hipStream_t st);
 // dst[r*dld + i] = (To) src[r*sld + i], i < w, r < rows (complex; strided row copy)
 template <typename Ti, typename To>
 void launch_copy_rows(int64_t rows, int64_t w, const void* src, int64_t sld, void* dst, int64_t dld,

@@ -892,8 +892,9 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int64_t n, const double* __
                                                      const double* __restrict__ shift, const double2* __restrict__ X,
                                                      const double2* __restrict__ R, double2* __restrict__ Xn,
                                                      double2* __restrict__ E, const int* __restrict__ out_rows,
-                                                     double2* __restrict__ E2) {
+                                                     double2* __restrict__ E2, const int* __restrict__ active) {
   const int64_t r = blockIdx.y;
+  if (active && !active[r]) return;
   const int64_t ro = out_rows ? (int64_t)out_rows[r] : r;
   double s = shift ? shift[r] : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -907,18 +908,19 @@ __global__ void __launch_bounds__(256) jacobi_kernel(int64_t n, const double* __
 }
 
 void launch_jacobi(int64_t nvec, int64_t n, const double* D, const double* shift_dev, const void* X, const void* R,
-                   void* Xn, void* E, hipStream_t st, const int* out_rows, void* E2) {
+                   void* Xn, void* E, hipStream_t st, const int* out_rows, void* E2, const int* active) {
   if (nvec <= 0) return;
   unsigned gx = nblocks(n, 256, 4096);
   hipLaunchKernelGGL(jacobi_kernel, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, D, shift_dev, (const double2*)X,
-                     (const double2*)R, (double2*)Xn, (double2*)E, out_rows, (double2*)E2);
+                     (const double2*)R, (double2*)Xn, (double2*)E, out_rows, (double2*)E2, active);
   LAUNCH_CHECK();
 }
 
 __global__ void __launch_bounds__(256) combine_kernel(int64_t n, int m, const double2* __restrict__ c,
                                                       const double2* __restrict__ H, int64_t hs,
-                                                      double2* __restrict__ X) {
+                                                      double2* __restrict__ X, const int* __restrict__ active) {
   int64_t r = blockIdx.y;
+  if (active && !active[r]) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double re = 0, im = 0;
     for (int k = 0; k < m; ++k) {
@@ -931,11 +933,153 @@ __global__ void __launch_bounds__(256) combine_kernel(int64_t n, int m, const do
 }
 
 void launch_combine(int64_t nvec, int m, int64_t n, const void* c, const void* H, int64_t hs, void* X,
-                    hipStream_t st) {
+                    hipStream_t st, const int* active) {
   if (nvec <= 0) return;
   unsigned gx = nblocks(n, 256, 4096);
   hipLaunchKernelGGL(combine_kernel, dim3(gx, (unsigned)nvec), dim3(256), 0, st, n, m, (const double2*)c,
-                     (const double2*)H, hs, (double2*)X);
+                     (const double2*)H, hs, (double2*)X, active);
+  LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- device-resident DIIS
+__global__ void diis_check_kernel(int64_t nvec, const double2* __restrict__ dots, double tol, int stall, int m,
+                                  DiisSlot* __restrict__ q, int* __restrict__ active, int* __restrict__ hrow) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nvec || !active[r]) return;
+  DiisSlot s = q[r];
+  const double rn = sqrt(fmax(0.0, dots[r].x));
+  s.rn = rn;
+  s.itc += 1;
+  if (!isfinite(rn)) {
+    s.bad = 1;
+    active[r] = 0;
+    q[r] = s;
+    return;
+  }
+  if (s.bnorm < 0) s.bnorm = rn > 0 ? rn : 1.0;
+  if (rn < 0.7 * s.best) {
+    s.best = rn;
+    s.best_it = s.itc - 1;
+  }
+  const bool conv = rn <= tol * s.bnorm;
+  const bool stalled = stall > 0 && (s.itc - 1) - s.best_it >= stall;
+  if (conv || stalled) {
+    s.conv = conv ? 1 : 0;
+    active[r] = 0;
+  } else {
+    s.iters += 1;
+    if (m > 0) hrow[r] = (int)r * m + s.next;
+  }
+  q[r] = s;
+}
+
+void launch_diis_check(int64_t nvec, const void* dots, double tol, int stall, int m, DiisSlot* st_dev, int* active,
+                       int* hrow, hipStream_t st) {
+  if (nvec <= 0) return;
+  hipLaunchKernelGGL(diis_check_kernel, dim3((unsigned)((nvec + 63) / 64)), dim3(64), 0, st, nvec,
+                     (const double2*)dots, tol, stall, m, st_dev, active, hrow);
+  LAUNCH_CHECK();
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d};
+}
+__device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
+
+constexpr int kDiisMax = 32;  // lrcc_config.diis_size is at most 32
+
+// One workgroup per slot; its first thread solves the small system in LDS.
+__global__ void diis_coef_kernel(int m, const double2* __restrict__ gram, DiisSlot* __restrict__ q,
+                                 const int* __restrict__ active, double2* __restrict__ Gall,
+                                 double2* __restrict__ coef) {
+  const int64_t r = blockIdx.x;
+  if (!active[r] || threadIdx.x != 0) return;
+  __shared__ double2 A[(kDiisMax + 1) * (kDiisMax + 1)];
+  __shared__ double2 bvec[kDiisMax + 1], xv[kDiisMax + 1];
+  __shared__ int idx[kDiisMax];
+  DiisSlot s = q[r];
+  double2* G = Gall + r * m * m;
+  double2* c = coef + r * m;
+  const int p = s.next;
+  s.cnt = min(s.cnt + 1, m);
+  s.next = (s.next + 1) % m;
+  for (int k = 0; k < m; ++k) {
+    const double2 g = gram[r * m + k];
+    G[k * m + p] = g;
+    G[p * m + k] = {g.x, -g.y};
+  }
+  const int cnt = s.cnt, N = cnt + 1;
+  for (int k = 0; k < cnt; ++k) idx[k] = ((s.next - cnt + k) % m + m) % m;
+  double sc = 0;
+  for (int i = 0; i < cnt; ++i) sc = fmax(sc, cabs2(G[idx[i] * m + idx[i]]));
+  bool ok = sc > 0;
+  if (ok) {
+    for (int i = 0; i < cnt; ++i) {
+      for (int j = 0; j < cnt; ++j) {
+        const double2 g = G[idx[i] * m + idx[j]];
+        A[i * N + j] = {g.x / sc, g.y / sc};
+      }
+      A[i * N + cnt] = {1.0, 0.0};
+      A[cnt * N + i] = {1.0, 0.0};
+      bvec[i] = {0.0, 0.0};
+    }
+    A[cnt * N + cnt] = {0.0, 0.0};
+    bvec[cnt] = {1.0, 0.0};
+    for (int k = 0; k < N && ok; ++k) {
+      int piv = k;
+      for (int i = k + 1; i < N; ++i)
+        if (cabs2(A[i * N + k]) > cabs2(A[piv * N + k])) piv = i;
+      if (cabs2(A[piv * N + k]) < 1e-14) {
+        ok = false;
+        break;
+      }
+      if (piv != k) {
+        for (int j = 0; j < N; ++j) {
+          const double2 t = A[k * N + j];
+          A[k * N + j] = A[piv * N + j];
+          A[piv * N + j] = t;
+        }
+        const double2 t = bvec[k];
+        bvec[k] = bvec[piv];
+        bvec[piv] = t;
+      }
+      for (int i = k + 1; i < N; ++i) {
+        const double2 f = cdiv(A[i * N + k], A[k * N + k]);
+        for (int j = k; j < N; ++j) {
+          const double2 t = cmul(f, A[k * N + j]);
+          A[i * N + j] = {A[i * N + j].x - t.x, A[i * N + j].y - t.y};
+        }
+        const double2 t = cmul(f, bvec[k]);
+        bvec[i] = {bvec[i].x - t.x, bvec[i].y - t.y};
+      }
+    }
+  }
+  for (int k = 0; k < m; ++k) c[k] = {0.0, 0.0};
+  if (ok) {
+    for (int i = N - 1; i >= 0; --i) {
+      double2 t = bvec[i];
+      for (int j = i + 1; j < N; ++j) {
+        const double2 u = cmul(A[i * N + j], xv[j]);
+        t = {t.x - u.x, t.y - u.y};
+      }
+      xv[i] = cdiv(t, A[i * N + i]);
+    }
+    for (int i = 0; i < cnt; ++i) c[idx[i]] = xv[i];
+  } else {  // restart the subspace from the newest entry
+    s.cnt = 1;
+    c[p] = {1.0, 0.0};
+  }
+  q[r] = s;
+}
+
+void launch_diis_coef(int64_t nvec, int m, const void* gram, DiisSlot* st_dev, const int* active, void* G,
+                      void* coef, hipStream_t st) {
+  if (nvec <= 0 || m <= 0) return;
+  LRCC_REQUIRE(m <= kDiisMax, LRCC_E_INVALID, "DIIS subspace larger than 32");
+  hipLaunchKernelGGL(diis_coef_kernel, dim3((unsigned)nvec), dim3(64), 0, st, m, (const double2*)gram, st_dev,
+                     active, (double2*)G, (double2*)coef);
   LAUNCH_CHECK();
 }
 

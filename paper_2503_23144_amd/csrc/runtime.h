@@ -135,6 +135,13 @@ class Executor {
   void set_graphs(bool on);
   int64_t graph_replays() const { return replays_; }
   int64_t graph_captures() const { return captures_; }
+  // Outer capture: launches go to stream cs (which the caller is capturing
+  // into a graph of its own) and run eagerly, this executor's own graphs
+  // suspended; any allocation change meanwhile throws (it would invalidate
+  // the caller's graph).  epoch() counts allocation changes.
+  void begin_outer(hipStream_t cs);
+  void end_outer();
+  int64_t epoch() const { return epoch_; }
 
  private:
   struct LadderOperands {  // X[M][V] (contracted index last), output C[M][V]
@@ -192,6 +199,9 @@ class Executor {
   std::map<RunKey, Recorded> graphs_;
   bool graphs_on_ = false;
   bool capturing_ = false;
+  bool outer_ = false;
+  hipStream_t saved_st_ = nullptr;
+  int64_t epoch_ = 0;
   Recorded* rec_ = nullptr;
   hipStream_t gst_ = nullptr;  // private stream of graph runs
   hipEvent_t fork_ = nullptr, join_ = nullptr;

@@ -1394,7 +1394,7 @@ void Executor<T>::run(const OpList& ops, int nb, const std::vector<int>& keep) {
   g_nb = nb;
   keep_ = keep;
   prepare(ops, nb, keep);
-  if (!graphs_on_) {
+  if (!graphs_on_ || outer_) {
     run_ops(ops, nb);
     return;
   }
@@ -1512,8 +1512,24 @@ void Executor<T>::clear_graphs() {
 
 template <typename T>
 void Executor<T>::on_realloc() {
-  LRCC_REQUIRE(!capturing_, LRCC_E_INTERNAL, "allocation while capturing a graph");
+  LRCC_REQUIRE(!capturing_ && !outer_, LRCC_E_INTERNAL, "allocation while capturing a graph");
+  ++epoch_;
   clear_graphs();
+}
+
+template <typename T>
+void Executor<T>::begin_outer(hipStream_t cs) {
+  LRCC_REQUIRE(!outer_ && !capturing_, LRCC_E_INTERNAL, "nested capture");
+  saved_st_ = st_;
+  st_ = cs;
+  outer_ = true;
+}
+
+template <typename T>
+void Executor<T>::end_outer() {
+  if (!outer_) return;
+  st_ = saved_st_;
+  outer_ = false;
 }
 
 template <typename T>

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 
 #include "context.h"
 #include "integrals.h"
@@ -87,6 +88,7 @@ Context::~Context() {
   if (st) (void)hipStreamSynchronize(st);
   x64.reset();
   x32.reset();
+  if (cst) (void)hipStreamDestroy(cst);
 }
 
 void Context::require_sizes() const { LRCC_REQUIRE(n > 0, LRCC_E_STATE, "lrcc_load_df has not been called"); }
@@ -501,67 +503,40 @@ void Context::fx32(int nb, const void* X64, void* out32) {
 
 // ---------------------------------------------------------------- DIIS
 
-// Solve the DIIS equations [G 1; 1^T 0][c; l] = [0; 1] (complex, small) by
-// Gaussian elimination with partial pivoting on the scale-normalized Gram
-// matrix.  Returns false if singular.
-static bool diis_coeffs(const std::vector<cplx>& G, int m, int cnt, const std::vector<int>& idx, std::vector<cplx>& c) {
-  int N = cnt + 1;
-  std::vector<cplx> A(N * N), b(N);
-  double sc = 0;
-  for (int i = 0; i < cnt; ++i) sc = std::max(sc, std::abs(G[idx[i] * m + idx[i]]));
-  if (sc == 0) return false;
-  for (int i = 0; i < cnt; ++i) {
-    for (int j = 0; j < cnt; ++j) A[i * N + j] = G[idx[i] * m + idx[j]] / sc;
-    A[i * N + cnt] = 1.0;
-    A[cnt * N + i] = 1.0;
-  }
-  A[cnt * N + cnt] = 0.0;
-  b[cnt] = 1.0;
-  for (int k = 0; k < N; ++k) {
-    int p = k;
-    for (int i = k + 1; i < N; ++i)
-      if (std::abs(A[i * N + k]) > std::abs(A[p * N + k])) p = i;
-    if (std::abs(A[p * N + k]) < 1e-14) return false;
-    if (p != k) {
-      for (int j = 0; j < N; ++j) std::swap(A[k * N + j], A[p * N + j]);
-      std::swap(b[k], b[p]);
-    }
-    for (int i = k + 1; i < N; ++i) {
-      cplx f = A[i * N + k] / A[k * N + k];
-      for (int j = k; j < N; ++j) A[i * N + j] -= f * A[k * N + j];
-      b[i] -= f * b[k];
-    }
-  }
-  std::vector<cplx> x(N);
-  for (int i = N - 1; i >= 0; --i) {
-    cplx s = b[i];
-    for (int j = i + 1; j < N; ++j) s -= A[i * N + j] * x[j];
-    x[i] = s / A[i * N + i];
-  }
-  c.assign(m, 0.0);
-  for (int i = 0; i < cnt; ++i) c[idx[i]] = x[i];
-  return true;
-}
+// Batched DIIS-accelerated Jacobi solver over `nb` slots, resident on the
+// device.  One iteration is: the residual resid(na, shift, X, B, R) of the
+// active slots (a Jacobian product and the residual kernel), the residual
+// norms, the convergence test (launch_diis_check), the Jacobi step written
+// into each slot's history ring, the new Gram row, the DIIS coefficients
+// (launch_diis_coef: the small linear solve per slot) and the extrapolation
+// -- every step a kernel on the context's stream.  The host reads the slots'
+// state back once per iteration (one synchronization) to retire converged
+// slots: a retired slot's iterate is copied out and the last active slot
+// moves into its place, so uneven convergence costs no wasted products.
+// With graphs on (and no kernel timing), the whole iteration at a given
+// batch is captured into one HIP graph on its second occurrence and
+// replayed from the third.  b (slot order, may be null) sets the reference
+// norms; without it the first residual norm is the reference (or `ref`).
+using ResidFn = std::function<void(int, const double*, const void*, const void*, void*)>;
 
-struct SlotMeta {
-  int rhs = -1;
-  int best_it = 0;
-  double best = 1e300;
-  int cnt = 0;    // entries stored
-  int next = 0;   // ring position of the next entry
-  int iters = 0;
-  int64_t sig = 0;
-  double bnorm = 0, rn = 0;
-  std::vector<cplx> G;  // m x m Gram matrix of stored errors
+namespace {
+
+// Whole-iteration graphs of one diis_solve call, keyed by the batch.
+struct IterGraphs {
+  struct Entry {
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+    int64_t e64 = -1, e32 = -1;
+  };
+  std::map<int, Entry> by_na;
+  bool broken = false;  // a capture failed: eager from here on
+  ~IterGraphs() {
+    for (auto& kv : by_na)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  }
 };
 
-// Batched DIIS-accelerated Jacobi solver over `nb` slots.  Slots hold the
-// right-hand sides still iterating, compacted to [0, na): a converged slot
-// is replaced by the last active one.  resid(na, shift, X, B, R) writes the
-// residual of the first na slots (B: the slot-ordered driving terms, or null).
-// b (rhs order, may be null) also sets the reference norms; without it the
-// first residual norm is the reference.  Results go to x in rhs order.
-using ResidFn = std::function<void(int, const double*, const void*, const void*, void*)>;
+}  // namespace
 
 static void diis_solve(Context& c, int nb, const double* shifts_host, const void* b, void* x, double tol, int maxit,
                        const ResidFn& resid, std::vector<SolveStats>& stats, int sig_per_eval,
@@ -570,11 +545,10 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
   const int m = std::max(0, c.cfg.diis_size);
   const size_t vb = n * 16;
   double t0 = now_s();
-  DevBuf Xw, Bw, Rw, Xn, En, Hx, He, shift, hrows, coef, gram, dots, work;
+  DevBuf Xw, Bw, Rw, En, Hx, He, shift, coef, gram, dots, work, G, state, flags;
   Xw.ensure(nb * vb);
   Rw.ensure(nb * vb);
-  if (m == 0) Xn.ensure(nb * vb);  // with a history, the update goes straight into it
-  En.ensure(nb * vb);
+  if (m > 0) En.ensure(nb * vb);
   if (b) {
     Bw.ensure(nb * vb);
     HIP_CHECK(hipMemcpyAsync(Bw.p, b, nb * vb, hipMemcpyDeviceToDevice, c.st));
@@ -586,126 +560,183 @@ static void diis_solve(Context& c, int nb, const double* shifts_host, const void
     launch_fill_zero<double>(Hx.p, (int64_t)nb * m * n, c.st);
     coef.ensure(nb * m * 16);
     gram.ensure(nb * m * 16);
-    hrows.ensure(nb * sizeof(int));
+    G.ensure((size_t)nb * m * m * 16);
+    launch_fill_zero<double>(G.p, (int64_t)nb * m * m, c.st);
   }
   shift.ensure(nb * 8);
   dots.ensure(nb * 16);
   work.ensure((size_t)nb * std::max(m, 1) * 1024 * 16);
+  state.ensure(nb * sizeof(DiisSlot));
+  flags.ensure(2 * nb * sizeof(int));  // active[nb], hrow[nb]
+  int* active = flags.as<int>();
+  int* hrow = active + nb;
   HIP_CHECK(hipMemcpyAsync(Xw.p, x, nb * vb, hipMemcpyDeviceToDevice, c.st));
   std::vector<double> sh(nb, 0.0);
   if (shifts_host) sh.assign(shifts_host, shifts_host + nb);
-  std::vector<SlotMeta> meta(nb);
-  std::vector<cplx> hd(nb), hg((size_t)nb * std::max(m, 1)), hc((size_t)nb * std::max(m, 1));
-  std::vector<int> hr(nb);
-  if (b) {
-    launch_batched_dot<double>(nb, n, Bw.p, n, Bw.p, n, true, dots.p, work.p, c.st);
-    HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, nb * 16, hipMemcpyDeviceToHost, c.st));
-    c.sync();
-  }
-  for (int s = 0; s < nb; ++s) {
-    meta[s].rhs = s;
-    meta[s].bnorm = b ? std::sqrt(std::max(0.0, hd[s].real())) : ref;
-    if (b && meta[s].bnorm == 0) meta[s].bnorm = 1e-300;
-    meta[s].G.assign(std::max(m, 1) * std::max(m, 1), 0.0);
+  std::vector<DiisSlot> q(nb);
+  std::vector<int> rhs(nb), act(2 * nb, 1);
+  {
+    std::vector<cplx> hd(nb);
+    if (b) {
+      launch_batched_dot<double>(nb, n, Bw.p, n, Bw.p, n, true, dots.p, work.p, c.st);
+      c.d2h(hd.data(), dots.p, nb * 16);
+    }
+    for (int s = 0; s < nb; ++s) {
+      rhs[s] = s;
+      q[s] = DiisSlot{0.0, b ? std::sqrt(std::max(0.0, hd[s].real())) : ref, 1e300, 0, 0, 0, 0, 0, 0, 0};
+      if (b && q[s].bnorm == 0) q[s].bnorm = 1e-300;
+      act[nb + s] = s * std::max(m, 1);
+    }
   }
   stats.assign(nb, SolveStats());
   auto slot_ptr = [&](DevBuf& buf, int s) { return (char*)buf.p + (size_t)s * vb; };
   auto hist_ptr = [&](DevBuf& buf, int s, int k) { return (char*)buf.p + ((size_t)s * m + k) * vb; };
-  auto finalize = [&](int s, bool conv) {
-    SlotMeta& mt = meta[s];
-    HIP_CHECK(hipMemcpyAsync((char*)x + (size_t)mt.rhs * vb, slot_ptr(Xw, s), vb, hipMemcpyDeviceToDevice, c.st));
-    SolveStats& so = stats[mt.rhs];
-    so.iterations = mt.iters;
-    so.converged = conv ? 1 : 0;
-    so.residual = mt.bnorm > 0 ? mt.rn / mt.bnorm : mt.rn;
-    so.sigma_evals = mt.sig;
+  auto finalize = [&](int s, bool at_limit) {
+    const DiisSlot& t = q[s];
+    HIP_CHECK(hipMemcpyAsync((char*)x + (size_t)rhs[s] * vb, slot_ptr(Xw, s), vb, hipMemcpyDeviceToDevice, c.st));
+    SolveStats& so = stats[rhs[s]];
+    so.iterations = t.iters - (at_limit ? 1 : 0);  // at the limit the last test was not followed by an update
+    so.converged = at_limit ? 0 : t.conv;
+    so.residual = t.bnorm > 0 ? t.rn / t.bnorm : t.rn;
+    so.sigma_evals = (int64_t)t.itc * sig_per_eval;
     so.seconds = now_s() - t0;
   };
   auto move_slot = [&](int from, int to) {
     if (from == to) return;
     HIP_CHECK(hipMemcpyAsync(slot_ptr(Xw, to), slot_ptr(Xw, from), vb, hipMemcpyDeviceToDevice, c.st));
-    HIP_CHECK(hipMemcpyAsync(slot_ptr(Rw, to), slot_ptr(Rw, from), vb, hipMemcpyDeviceToDevice, c.st));
     if (b) HIP_CHECK(hipMemcpyAsync(slot_ptr(Bw, to), slot_ptr(Bw, from), vb, hipMemcpyDeviceToDevice, c.st));
     if (m > 0) {
       HIP_CHECK(hipMemcpyAsync(hist_ptr(Hx, to, 0), hist_ptr(Hx, from, 0), m * vb, hipMemcpyDeviceToDevice, c.st));
       HIP_CHECK(hipMemcpyAsync(hist_ptr(He, to, 0), hist_ptr(He, from, 0), m * vb, hipMemcpyDeviceToDevice, c.st));
+      HIP_CHECK(hipMemcpyAsync((char*)G.p + (size_t)to * m * m * 16, (char*)G.p + (size_t)from * m * m * 16,
+                               (size_t)m * m * 16, hipMemcpyDeviceToDevice, c.st));
     }
-    meta[to] = meta[from];
+    q[to] = q[from];
+    rhs[to] = rhs[from];
     sh[to] = sh[from];
   };
-  int na = nb;
-  for (int it = 0; it <= maxit && na > 0; ++it) {
+  auto upload = [&](int na) {  // slot state, flags and shifts of the active slots
+    for (int s = 0; s < na; ++s) {
+      act[s] = 1;
+      act[nb + s] = s * std::max(m, 1) + (m > 0 ? q[s].next : 0);
+    }
+    HIP_CHECK(hipMemcpyAsync(state.p, q.data(), na * sizeof(DiisSlot), hipMemcpyHostToDevice, c.st));
+    HIP_CHECK(hipMemcpyAsync(active, act.data(), na * sizeof(int), hipMemcpyHostToDevice, c.st));
+    HIP_CHECK(hipMemcpyAsync(hrow, act.data() + nb, na * sizeof(int), hipMemcpyHostToDevice, c.st));
     HIP_CHECK(hipMemcpyAsync(shift.p, sh.data(), na * 8, hipMemcpyHostToDevice, c.st));
+  };
+  // one iteration on the device; `update` false: residual and test only
+  auto body = [&](int na, bool update) {
     resid(na, shift.as<double>(), Xw.p, b ? Bw.p : nullptr, Rw.p);
     launch_batched_dot<double>(na, n, Rw.p, n, Rw.p, n, true, dots.p, work.p, c.st);
-    HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, na * 16, hipMemcpyDeviceToHost, c.st));
-    c.sync();
-    for (int s = 0; s < na; ++s) {
-      meta[s].rn = std::sqrt(std::max(0.0, hd[s].real()));
-      meta[s].sig += sig_per_eval;
-      if (meta[s].bnorm < 0) meta[s].bnorm = meta[s].rn > 0 ? meta[s].rn : 1.0;
-      LRCC_REQUIRE(std::isfinite(meta[s].rn), LRCC_E_NOCONV, "residual is not finite");
+    launch_diis_check(na, dots.p, tol, stall, m, (DiisSlot*)state.p, active, hrow, c.st);
+    if (!update) return;
+    if (m == 0) {  // plain Jacobi, in place
+      launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Xw.p, nullptr, c.st, nullptr, nullptr,
+                    active);
+      return;
     }
+    launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Hx.p, He.p, c.st, hrow, En.p, active);
+    launch_gram(na, m, n, He.p, m, En.p, gram.p, work.p, c.st);
+    launch_diis_coef(na, m, gram.p, (DiisSlot*)state.p, active, G.p, coef.p, c.st);
+    launch_combine(na, m, n, coef.p, Hx.p, m, Xw.p, c.st, active);
+  };
+  IterGraphs graphs;
+  const bool use_graphs = c.cfg.graphs != 0 && !c.timing;
+  auto epoch = [&](bool is64) -> int64_t {
+    if (is64) return c.x64 ? c.x64->epoch() : -1;
+    return c.x32 ? c.x32->epoch() : -1;
+  };
+  // one iteration through a whole-iteration graph: eager the first time at
+  // this batch, captured the second time, replayed afterwards
+  auto run_iteration = [&](int na) {
+    if (!use_graphs || graphs.broken) return body(na, true);
+    IterGraphs::Entry& e = graphs.by_na[na];
+    if (e.exec && (e.e64 != epoch(true) || e.e32 != epoch(false))) {  // buffers moved: capture again
+      (void)hipGraphExecDestroy(e.exec);
+      e.exec = nullptr;
+      e.seen = 1;
+    }
+    if (e.exec) {
+      HIP_CHECK(hipGraphLaunch(e.exec, c.st));
+      ++c.iter_replays;
+      return;
+    }
+    if (e.seen++ == 0) return body(na, true);
+    if (!c.cst) HIP_CHECK(hipStreamCreateWithFlags(&c.cst, hipStreamNonBlocking));
+    // the capture stream starts after everything queued on the context's stream
+    hipEvent_t ev;
+    HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_CHECK(hipEventRecord(ev, c.st));
+    HIP_CHECK(hipStreamWaitEvent(c.cst, ev, 0));
+    (void)hipEventDestroy(ev);
+    const hipStream_t home = c.st;
+    hipGraph_t g = nullptr;
+    bool ok = true;
+    HIP_CHECK(hipStreamBeginCapture(c.cst, hipStreamCaptureModeThreadLocal));
+    c.st = c.cst;
+    if (c.x64) c.x64->begin_outer(c.cst);
+    if (c.x32) c.x32->begin_outer(c.cst);
+    try {
+      body(na, true);
+    } catch (const Error&) {
+      ok = false;  // e.g. an allocation the capture cannot hold: this solve stays eager
+    }
+    if (c.x64) c.x64->end_outer();
+    if (c.x32) c.x32->end_outer();
+    c.st = home;
+    const hipError_t ec = hipStreamEndCapture(c.cst, &g);
+    hipGraphExec_t ex = nullptr;
+    if (ok && ec == hipSuccess && g) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+    else ok = false;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+      if (ex) (void)hipGraphExecDestroy(ex);
+      (void)hipGetLastError();
+      graphs.broken = true;
+      return body(na, true);
+    }
+    e.exec = ex;
+    e.e64 = epoch(true);
+    e.e32 = epoch(false);
+    ++c.iter_captures;
+    HIP_CHECK(hipGraphLaunch(ex, c.st));
+  };
+  int na = nb;
+  upload(na);
+  for (int it = 0;; ++it) {
+    const bool last = it == maxit;
+    if (last)
+      body(na, false);
+    else
+      run_iteration(na);
+    c.d2h(q.data(), state.p, na * sizeof(DiisSlot));
+    c.d2h(act.data(), active, na * sizeof(int));
+    for (int s = 0; s < na; ++s)
+      LRCC_REQUIRE(!q[s].bad, LRCC_E_NOCONV, "residual is not finite");
     if (c.cfg.verbose >= 2) {
       fprintf(stderr, "[lrcc] it %d active %d", it, na);
-      for (int s = 0; s < std::min(na, 4); ++s) fprintf(stderr, " %.3e", meta[s].rn / meta[s].bnorm);
+      for (int s = 0; s < std::min(na, 4); ++s) fprintf(stderr, " %.3e", q[s].rn / q[s].bnorm);
       fprintf(stderr, "\n");
     }
-    for (int s = 0; s < na; ++s)
-      if (meta[s].rn < 0.7 * meta[s].best) {
-        meta[s].best = meta[s].rn;
-        meta[s].best_it = it;
-      }
+    const int na0 = na;
     for (int s = 0; s < na;) {
-      bool conv = meta[s].rn <= tol * meta[s].bnorm;
-      bool stalled = stall > 0 && it - meta[s].best_it >= stall;
-      if (conv || stalled) {
-        finalize(s, conv);
+      if (!act[s]) {
+        finalize(s, false);
         move_slot(na - 1, s);
+        act[s] = act[na - 1];
         --na;
       } else {
         ++s;
       }
     }
-    if (na == 0 || it == maxit) break;
-    HIP_CHECK(hipMemcpyAsync(shift.p, sh.data(), na * 8, hipMemcpyHostToDevice, c.st));
-    for (int s = 0; s < na; ++s) meta[s].iters += 1;
-    if (m == 0) {
-      launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Xn.p, En.p, c.st);
-      HIP_CHECK(hipMemcpyAsync(Xw.p, Xn.p, na * vb, hipMemcpyDeviceToDevice, c.st));
-      continue;
+    if (na == 0) break;
+    if (last) {
+      for (int s = 0; s < na; ++s) finalize(s, true);
+      break;
     }
-    // the update and its step go straight into each slot's next history
-    // row (hist_ptr(Hx/He, s, next)); the step also into En for the Gram rows
-    for (int s = 0; s < na; ++s) hr[s] = s * m + meta[s].next;
-    HIP_CHECK(hipMemcpyAsync(hrows.p, hr.data(), na * sizeof(int), hipMemcpyHostToDevice, c.st));
-    launch_jacobi(na, n, c.D.as<double>(), shift.as<double>(), Xw.p, Rw.p, Hx.p, He.p, c.st, hrows.as<int>(), En.p);
-    launch_gram(na, m, n, He.p, m, En.p, gram.p, work.p, c.st);
-    HIP_CHECK(hipMemcpyAsync(hg.data(), gram.p, (size_t)na * m * 16, hipMemcpyDeviceToHost, c.st));
-    c.sync();
-    for (int s = 0; s < na; ++s) {
-      SlotMeta& mt = meta[s];
-      int p = mt.next;
-      mt.cnt = std::min(mt.cnt + 1, m);
-      mt.next = (mt.next + 1) % m;
-      for (int k = 0; k < m; ++k) {
-        mt.G[k * m + p] = hg[(size_t)s * m + k];
-        mt.G[p * m + k] = std::conj(hg[(size_t)s * m + k]);
-      }
-      std::vector<int> idx;
-      for (int k = 0; k < mt.cnt; ++k) idx.push_back(((mt.next - mt.cnt + k) % m + m) % m);
-      std::vector<cplx> cf;
-      if (!diis_coeffs(mt.G, m, mt.cnt, idx, cf)) {
-        mt.cnt = 1;  // restart the subspace from the newest vector
-        cf.assign(m, 0.0);
-        cf[p] = 1.0;
-      }
-      for (int k = 0; k < m; ++k) hc[(size_t)s * m + k] = cf[k];
-    }
-    HIP_CHECK(hipMemcpyAsync(coef.p, hc.data(), (size_t)na * m * 16, hipMemcpyHostToDevice, c.st));
-    launch_combine(na, m, n, coef.p, Hx.p, m, Xw.p, c.st);
+    if (na != na0) upload(na);
   }
-  for (int s = 0; s < na; ++s) finalize(s, false);
   c.sync();
 }
 
@@ -1103,6 +1134,12 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
       const Side sd = (side == 0 || quadratic) ? Side::Right : Side::Left;
       solve_linear(sd, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
       for (int q = 0; q < nc; ++q) per[side * nrhs + c0 + q] = ss[q];
+      if (cfg.verbose >= 1) {
+        int itmax = 0;
+        for (auto& t : ss) itmax = std::max(itmax, t.iterations);
+        fprintf(stderr, "[lrcc] %s right-hand sides %d..%d of %d: up to %d iterations\n", side == 0 ? "X" : "Y", c0,
+                c0 + nc - 1, nrhs, itmax);
+      }
     }
   }
   // alpha_AB(w) = -1/2 [f_AB + conj f_BA],  f_AB = Y^B . xi^A + eta^A . X^B
