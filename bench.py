@@ -574,6 +574,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 product leg (c5)")
     ap.add_argument("--no-solve", action="store_true", help="skip the full o=40, v=400 solve (c5)")
     ap.add_argument("--no-c3", action="store_true", help="skip the o=20, v=150 full pass (c5)")
+    ap.add_argument("--c4-check", action="store_true",
+                    help="only the o=30, v=300 check: mixed solves of all 3 x 32 right-hand sides by Eq. 35 and "
+                         "Eq. 36, and plain FP64 solves on 4 of the 32 frequencies for comparison")
     ap.add_argument("--solve-fp64", action="store_true",
                     help="also the plain FP64 solve at o=40, v=400 on the same frequency, for the mixed-vs-FP64 "
                          "alpha comparison (about 5 minutes)")
@@ -606,9 +609,76 @@ def main():
     if not args.extras:
         args.no_eq36 = args.no_ladder_modes = args.no_truncation = args.no_sigma_table = True
         args.no_ladder_scale = True
+    if args.c4_check:
+        return c4_check(args)
     if args.workload == "c3":
         return main_full_pass(args)
     main_c5(args)
+
+
+def c4_check(args):
+    """o=30, v=300, naux=600, 3 directions x 32 frequencies in [0, 0.4] Ha:
+    the batched mixed solver on every right-hand side (uneven convergence:
+    the frequencies approach the first excitation), alpha by Eq. 35 and by
+    Eq. 36, and the plain FP64 solver on four of the frequencies."""
+    import numpy as np
+    import torch
+
+    from paper_2503_23144_amd import lrcc
+    from paper_2503_23144_amd.synth import config_inputs
+    inp = config_inputs("c4")
+    dev_in = resident(inp)
+    om = [float(w) for w in inp.omegas]
+    out = {"workload": "c4: o=30 v=300 naux=600, 3 dipole directions x 32 omegas in [0,0.4] Ha",
+           "gap": inp.gap}
+
+    def ctx(prec, tol):
+        c = lrcc.Context(precision=prec, tol=tol, verbose=1)
+        c.load_df(inp.o, inp.v, dev_in["B"])
+        c.load_fock(dev_in["fock"])
+        c.load_dipoles(dev_in["mu"])
+        return c
+
+    t0 = time.perf_counter()
+    c = ctx("mixed", args.tol)
+    c.solve_ground()
+    c.solve_lambda()
+    out["mixed_ground_lambda_s"] = time.perf_counter() - t0
+    t = time.perf_counter()
+    per = c.solve_response(om)
+    out["mixed_eq35_s"] = time.perf_counter() - t
+    a35 = c.alpha(len(om))
+    its = [p["iterations"] for p in per]
+    out["iterations_x"] = its[:96]
+    out["iterations_y"] = its[96:]
+    out["sigma_evals_eq35"] = int(sum(p["sigma_evals"] for p in per))
+    captures, replays = c.graph_stats()
+    out["graph_captures"], out["graph_replays"] = captures, replays
+    print(f"[bench] c4 mixed eq35: {out['mixed_eq35_s']:.1f} s, X iterations {min(its[:96])}..{max(its[:96])}",
+          file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    c.solve_response(om, quadratic=True)
+    out["mixed_eq36_s"] = time.perf_counter() - t
+    a36 = c.alpha(len(om))
+    out["alpha_rel_diff_eq36_vs_eq35"] = float(np.abs(a36 - a35).max() / np.abs(a35).max())
+    c.close()
+    lrcc.trim_memory()
+    sub = [0, 10, 21, 31]
+    t = time.perf_counter()
+    c = ctx("fp64", args.tol64)
+    c.solve_ground()
+    c.solve_lambda()
+    c.solve_response([om[k] for k in sub])
+    a64 = c.alpha(len(sub))
+    c.close()
+    lrcc.trim_memory()
+    out["fp64_subset_omegas"] = [om[k] for k in sub]
+    out["fp64_s"] = time.perf_counter() - t
+    out["alpha_rel_diff_mixed_vs_fp64"] = float(np.abs(a35[sub] - a64).max() / np.abs(a64).max())
+    out["alpha_iso"] = [float(x) for x in np.real(np.trace(a35, axis1=-2, axis2=-1)) / 3.0]
+    print(f"[bench] c4 check: eq36 vs eq35 {out['alpha_rel_diff_eq36_vs_eq35']:.2e}, mixed vs FP64 "
+          f"{out['alpha_rel_diff_mixed_vs_fp64']:.2e}", file=sys.stderr, flush=True)
+    print(json.dumps(out))
 
 
 def main_c5(args):

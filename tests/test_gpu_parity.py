@@ -426,6 +426,32 @@ def test_fnspp_truncation_matches_oracle():
     assert _relerr(c.alpha(1), ref.alpha) < 1e-8
 
 
+def test_fnspp_truncation_at_larger_space_matches_oracle():
+    """FNS++ from 48 virtuals to 20 at o=6 (a 48 x 48 density from 15 x 48^2
+    perturbed doubles per direction and frequency, three directions, two
+    frequencies): all 48 occupations against the oracle, and E_corr and alpha
+    in the truncated space against the oracle's solve in its own truncated
+    space (alpha and E do not depend on the phases or the order the two
+    eigensolvers give the kept spinors)."""
+    from oracle.fnspp import fnspp_transform
+    from oracle.response import lr_ccsd
+    o, v, keep = 6, 48, 20
+    inp = make_inputs(o, v, 24, seed=37)
+    inp.B = inp.B * 4.0
+    omegas = [0.02, 0.15]
+    U, n_ref, (Bn, fn, mun) = fnspp_transform(inp.B, inp.fock, inp.mu, o, omegas, keep=keep)
+    c = _ctx(inp)
+    nk, occ = c.fnspp_truncate(omegas, keep=keep)
+    assert nk == keep
+    assert _relerr(occ, n_ref) < 1e-10
+    ref = lr_ccsd(Bn, fn, mun, o, [0.1], tol=1e-12)
+    e, _ = c.solve_ground()
+    assert abs(e - ref.ecorr) < 1e-10 * abs(ref.ecorr)
+    c.solve_lambda()
+    c.solve_response([0.1])
+    assert _relerr(c.alpha(1), ref.alpha) < 1e-8
+
+
 def test_fns_truncation_matches_oracle():
     """Ground-state natural spinors (Eq. 40): occupations, the truncated
     space and alpha in it against the oracle."""
