@@ -577,6 +577,8 @@ def main():
     ap.add_argument("--c4-check", action="store_true",
                     help="only the o=30, v=300 check: mixed solves of all 3 x 32 right-hand sides by Eq. 35 and "
                          "Eq. 36, and plain FP64 solves on 4 of the 32 frequencies for comparison")
+    ap.add_argument("--fnspp-scale", action="store_true",
+                    help="FNS++ from 1300 virtuals to 400 at o=40, then the static solve in the kept space")
     ap.add_argument("--solve-fp64", action="store_true",
                     help="also the plain FP64 solve at o=40, v=400 on the same frequency, for the mixed-vs-FP64 "
                          "alpha comparison (about 5 minutes)")
@@ -611,9 +613,78 @@ def main():
         args.no_ladder_scale = True
     if args.c4_check:
         return c4_check(args)
+    if args.fnspp_scale:
+        return fnspp_scale(args)
     if args.workload == "c3":
         return main_full_pass(args)
     main_c5(args)
+
+
+def fnspp_scale(args):
+    """FNS++ at the spectrum scale: o=40 with 1300 virtual spinors generated
+    (naux=800, the full space the o=40, v=400 workload stands for), the
+    static FNS++ density (Eqs. 45-50; three directions, omega = 0), its
+    1300 x 1300 eigensolve, and the 400 natural spinors of largest |n| kept
+    (random factors have no physical occupation decay, so a keep-count
+    replaces the 1e-5 threshold); then T, Lambda, X and Y (omega = 0, three
+    directions) and alpha in the truncated space, mixed precision.  Checks
+    that hold at any size: the kept count, the occupations ordered by |n|,
+    converged solves, and alpha(0) symmetric."""
+    import numpy as np
+    import torch
+
+    from paper_2503_23144_amd import lrcc
+    from paper_2503_23144_amd.synth import make_inputs_on_device
+    o, v, naux, keep = 40, 1300, 800, 400
+    out = {"workload": f"fnspp at scale: o={o}, {v} virtuals generated, naux={naux}, keep {keep}; omega = 0",
+           "inputs": "B drawn on the device (torch Philox, seed 0); eps, F, mu numpy PCG64 (seed 0)"}
+    t0 = time.perf_counter()
+    inp = make_inputs_on_device(o, v, naux, seed=0)
+    dev_in = {"B": inp.B, "fock": torch.as_tensor(inp.fock).cuda(), "mu": torch.as_tensor(inp.mu).cuda()}
+    torch.cuda.synchronize()
+    out["inputs_s"] = time.perf_counter() - t0
+    print(f"[bench] fnspp scale: inputs drawn ({out['inputs_s']:.1f} s)", file=sys.stderr, flush=True)
+    c = lrcc.Context(precision="mixed", tol=args.tol, ladder="triangle", ladder_fp64="direct", memory="lean",
+                     rhs_chunk=1)
+    c.load_df(o, v, dev_in["B"])
+    c.load_fock(dev_in["fock"])
+    c.load_dipoles(dev_in["mu"])
+    del dev_in, inp
+    torch.cuda.empty_cache()
+    t = time.perf_counter()
+    nk, occ = c.fnspp_truncate([0.0], keep=keep)
+    out["truncate_s"] = time.perf_counter() - t
+    a = np.abs(occ)
+    out["kept"] = int(nk)
+    out["occupations"] = {"n_1": float(occ[0]), "n_keep": float(occ[keep - 1]), "n_keep+1": float(occ[keep]),
+                          "n_last": float(occ[-1]), "captured_abs_fraction": float(a[:keep].sum() / a.sum()),
+                          "negative": int((occ < 0).sum())}
+    out["ordered_by_abs"] = bool(np.all(a[:-1] >= a[1:]))
+    print(f"[bench] fnspp scale: truncate {out['truncate_s']:.1f} s, kept {nk}, {out['occupations']}",
+          file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    e, st0 = c.solve_ground()
+    out["ground"] = {"seconds": time.perf_counter() - t, "ecorr": [e.real, e.imag], "iterations": st0["iterations"],
+                     "converged": bool(st0["converged"])}
+    print(f"[bench] fnspp scale: ground {out['ground']}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    st1 = c.solve_lambda()
+    out["lambda"] = {"seconds": time.perf_counter() - t, "iterations": st1["iterations"],
+                     "converged": bool(st1["converged"])}
+    print(f"[bench] fnspp scale: lambda {out['lambda']}", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    per = c.solve_response([0.0])
+    out["response"] = {"seconds": time.perf_counter() - t, "iterations": [p["iterations"] for p in per],
+                       "converged": bool(all(p["converged"] for p in per))}
+    al = np.asarray(c.alpha(1))[0]
+    c.close()
+    lrcc.trim_memory()
+    out["alpha"] = [[[complex(z).real, complex(z).imag] for z in row] for row in al]
+    out["alpha_asymmetry"] = float(np.abs(al - al.T).max() / np.abs(al).max())
+    out["seconds"] = time.perf_counter() - t0
+    print(f"[bench] fnspp scale: {out['seconds']:.1f} s, alpha asymmetry {out['alpha_asymmetry']:.1e}",
+          file=sys.stderr, flush=True)
+    print(json.dumps(out))
 
 
 def c4_check(args):

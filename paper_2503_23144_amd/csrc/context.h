@@ -155,6 +155,10 @@ struct Context {
   void require_sizes() const;
   void upload_fock_blocks();
   void build_integrals();
+  void ensure_integrals();  // every block (on first need)
+  void ensure_goovv();      // <oo||vv> alone (what truncation needs)
+  void release_goovv_if_alone();
+  bool ints_built = false, goovv_built = false;
   void reset_solutions();
   void collect_times();
 };

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 
 #include "context.h"
@@ -44,28 +45,66 @@ __global__ void mp2_kernel(int64_t o, int64_t v, const double2* __restrict__ g, 
   }
 }
 
-// tA1 = s1 / (Haa[a] - Hii[i] + w), tA2 = s2 / (Haa[a] + Haa[c] - Hii[i] - Hii[j] + w)
-__global__ void fnspp_divide_kernel(int64_t o, int64_t v, const double* __restrict__ Hii,
-                                    const double* __restrict__ Haa, double w, const double2* __restrict__ s1,
-                                    const double2* __restrict__ s2, double2* __restrict__ t1,
-                                    double2* __restrict__ t2) {
-  int64_t n1 = o * v, n2 = o * o * v * v;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n1 + n2;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    if (k < n1) {
-      int64_t i = k / v, a = k % v;
-      double d = Haa[a] - Hii[i] + w;
-      t1[k] = {s1[k].x / d, s1[k].y / d};
-    } else {
-      int64_t q = k - n1;
-      int64_t c = q % v, r = q / v;
-      int64_t a = r % v;
-      r /= v;
-      int64_t j = r % o, i = r / o;
-      double d = Haa[a] + Haa[c] - Hii[i] - Hii[j] + w;
-      t2[q] = (i == j || a == c) ? double2{0.0, 0.0} : double2{s2[q].x / d, s2[q].y / d};
-    }
+// tA1[i][a] = s1[i][a] / (Haa[a] - Hii[i] + w)
+__global__ void fnspp_singles_kernel(int64_t o, int64_t v, const double* __restrict__ Hii,
+                                     const double* __restrict__ Haa, double w, const double2* __restrict__ s1,
+                                     double2* __restrict__ t1) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < o * v; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / v, a = k % v;
+    const double d = Haa[a] - Hii[i] + w;
+    t1[k] = {s1[k].x / d, s1[k].y / d};
   }
+}
+
+// One chunk of pairs p = i*o + j in [p0, p0 + np) of a doubles tensor
+// s[p][a][c], written as X[a][p - p0][c] and Xc = conj X: the row layout in
+// which D[a][b] += sum_(p,c) X[a][(p,c)] Xc[b][(p,c)] is one GEMM.  With
+// Hii set, the values are first divided by Haa[a] + Haa[c] - Hii[i] - Hii[j] + w
+// (tA2, zero where i = j or a = c).
+__global__ void pair_chunk_kernel(int64_t o, int64_t v, int64_t p0, int64_t np, const double2* __restrict__ s,
+                                  const double* __restrict__ Hii, const double* __restrict__ Haa, double w,
+                                  double2* __restrict__ X, double2* __restrict__ Xc) {
+  const int64_t n = np * v * v;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = k % v, r = k / v;
+    const int64_t pp = r % np, a = r / np;
+    const int64_t p = p0 + pp;
+    double2 x = s[(p * v + a) * v + c];
+    if (Hii) {
+      const int64_t i = p / o, j = p % o;
+      if (i == j || a == c) {
+        x = {0.0, 0.0};
+      } else {
+        const double d = Haa[a] + Haa[c] - Hii[i] - Hii[j] + w;
+        x = {x.x / d, x.y / d};
+      }
+    }
+    X[k] = x;
+    Xc[k] = {x.x, -x.y};
+  }
+}
+
+// part[y][a] = Re sum_{r = y, y + gridDim.y, ...} x[r][a] y[r][a] (rows x cols)
+__global__ void col_dot_kernel(int64_t rows, int64_t cols, const double2* __restrict__ x,
+                               const double2* __restrict__ y, double* __restrict__ part) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= cols) return;
+  double acc = 0.0;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    const double2 p = x[r * cols + a], q = y[r * cols + a];
+    acc += p.x * q.x - p.y * q.y;
+  }
+  part[(int64_t)blockIdx.y * cols + a] = acc;
+}
+
+// out[a] = base[a] + scale * sum_y part[y][a]
+__global__ void col_sum_kernel(int64_t nparts, int64_t cols, const double* __restrict__ part,
+                               const double* __restrict__ base, double scale, double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= cols) return;
+  double acc = 0.0;
+  for (int64_t y = 0; y < nparts; ++y) acc += part[y * cols + a];
+  out[a] = base[a] + scale * acc;
 }
 
 __global__ void conj_kernel(int64_t n, const double2* __restrict__ x, double2* __restrict__ y) {
@@ -152,11 +191,43 @@ void rotate(int64_t nq, int64_t nmo, int64_t m, const void* X, const void* C, vo
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
+// Pair densities are formed in chunks of (i, j) pairs of at most this many
+// bytes per buffer (LRCC_DENSITY_CHUNK_BYTES overrides it), so that no
+// permuted copy of a whole o^2 v^2 tensor is needed.
+size_t density_chunk_bytes() {
+  static const size_t fixed = size_t(2) << 30;
+  const char* e = std::getenv("LRCC_DENSITY_CHUNK_BYTES");
+  if (e && *e) {
+    const long long b = std::atoll(e);
+    if (b > 0) return (size_t)b;
+  }
+  return fixed;
+}
+
+// D[a][b] += alpha sum_{ijc} x_ij^ac conj x_ij^bc for the doubles tensor s
+// [i][j][a][c] (x = s, or with Hii/Haa set the first-order amplitudes
+// s / (Haa[a] + Haa[c] - Hii[i] - Hii[j] + w)); D row-major v x v.
+void pair_density(int64_t o, int64_t v, const void* s, const double* Hii, const double* Haa, double w, double alpha,
+                  void* D, DevBuf& X, DevBuf& Xc, hipStream_t st) {
+  const int64_t npairs = o * o, per = v * v * 16;
+  const int64_t np = std::max<int64_t>(1, std::min<int64_t>(npairs, (int64_t)(density_chunk_bytes() / per)));
+  X.ensure(np * per);
+  Xc.ensure(np * per);
+  for (int64_t p0 = 0; p0 < npairs; p0 += np) {
+    const int64_t nc = std::min(np, npairs - p0);
+    hipLaunchKernelGGL(pair_chunk_kernel, dim3(grid_of(nc * v * v)), dim3(256), 0, st, o, v, p0, nc,
+                       (const double2*)s, Hii, Haa, w, (double2*)X.p, (double2*)Xc.p);
+    HIP_CHECK(hipGetLastError());
+    launch_gemm<double>(false, true, v, v, nc * v, alpha, 0.0, X.p, nc * v, Xc.p, nc * v, 1.0, 0.0, D, v, st);
+  }
+}
+
 }  // namespace
 
 // Step 1: MP2 doubles t[i][j][a][b] (Eq. 39) as a full tensor, written into
 // the input of the projection program (which reads it in step 3).
 static void* mp2_doubles(Context& c) {
+  c.ensure_goovv();
   const size_t n2f = (size_t)c.o * c.o * c.v * c.v;
   DevBuf epsd;
   epsd.ensure(c.nmo * 8);
@@ -173,29 +244,32 @@ static void* mp2_doubles(Context& c) {
 // program's input) and the Hbar diagonals.
 void Context::hbar_diagonals(std::vector<double>& Hii, std::vector<double>& Haa) {
   const int64_t vv = v, oo = o;
-  const size_t n2f = (size_t)oo * oo * vv * vv;
   void* tm2 = mp2_doubles(*this);
   // 2. Hbar diagonals: per-i and per-a bilinear sums of t2 with <ij||ab>
   const void* goovv = x64->ptr(P.m.find("goovv"));
-  DevBuf dots, wk, tA, gA;
-  dots.ensure(std::max(oo, vv) * 16);
-  wk.ensure((size_t)std::max(oo, vv) * 1024 * 16);
-  std::vector<cplx> hd(std::max(oo, vv));
+  DevBuf dots, wk, part, ev, hd;
+  dots.ensure(oo * 16);
+  wk.ensure((size_t)oo * 1024 * 16);
+  std::vector<cplx> hi(oo);
+  // Hii: sum over the row block i of [i][n][e][f]
   launch_batched_dot<double>(oo, oo * vv * vv, tm2, oo * vv * vv, goovv, oo * vv * vv, false, dots.p, wk.p, st);
-  HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, oo * 16, hipMemcpyDeviceToHost, st));
-  sync();
-  Hii.assign(oo, 0.0);
+  HIP_CHECK(hipMemcpyAsync(hi.data(), dots.p, oo * 16, hipMemcpyDeviceToHost, st));
+  // Haa: sum over the rows (m, n, f) of column a of [m][n][f][a]
+  const int64_t rows = oo * oo * vv, nparts = std::min<int64_t>(rows, 512);
+  part.ensure((size_t)nparts * vv * 8);
+  ev.ensure(vv * 8);
+  hd.ensure(vv * 8);
+  h2d(ev.p, eps.data() + o, vv * 8);
+  hipLaunchKernelGGL(col_dot_kernel, dim3((unsigned)((vv + 255) / 256), (unsigned)nparts), dim3(256), 0, st, rows, vv,
+                     (const double2*)tm2, (const double2*)goovv, part.as<double>());
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(col_sum_kernel, dim3((unsigned)((vv + 255) / 256)), dim3(256), 0, st, nparts, vv,
+                     part.as<double>(), ev.as<double>(), -0.5, hd.as<double>());
+  HIP_CHECK(hipGetLastError());
   Haa.assign(vv, 0.0);
-  for (int64_t i = 0; i < oo; ++i) Hii[i] = eps[i] + 0.5 * hd[i].real();
-  tA.ensure(n2f * 16);
-  gA.ensure(n2f * 16);
-  // [m][n][f][a] -> [a][m][n][f]
-  permute(tm2, tA.p, {vv, oo, oo, vv}, {1, oo * vv * vv, vv * vv, vv}, st);
-  permute(goovv, gA.p, {vv, oo, oo, vv}, {1, oo * vv * vv, vv * vv, vv}, st);
-  launch_batched_dot<double>(vv, oo * oo * vv, tA.p, oo * oo * vv, gA.p, oo * oo * vv, false, dots.p, wk.p, st);
-  HIP_CHECK(hipMemcpyAsync(hd.data(), dots.p, vv * 16, hipMemcpyDeviceToHost, st));
-  sync();
-  for (int64_t a = 0; a < vv; ++a) Haa[a] = eps[o + a] - 0.5 * hd[a].real();
+  d2h(Haa.data(), hd.p, vv * 8);
+  Hii.assign(oo, 0.0);
+  for (int64_t i = 0; i < oo; ++i) Hii[i] = eps[i] + 0.5 * hi[i].real();
 }
 
 void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, int* nvir_out, double* occ_out) {
@@ -205,22 +279,19 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
   LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");
   LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
   const int64_t vv = v, oo = o;
-  const size_t n2f = (size_t)oo * oo * vv * vv;
   std::vector<double> Hii, Haa;
   hbar_diagonals(Hii, Haa);
+  release_goovv_if_alone();  // the projections read the MP2 doubles and A only
   DevBuf Hd;
   Hd.ensure((oo + vv) * 8);
   h2d(Hd.p, Hii.data(), oo * 8);
   h2d((char*)Hd.p + oo * 8, Haa.data(), vv * 8);
   // 3-4. projections per direction, first-order amplitudes per frequency,
   // and the averaged Gram density
-  DevBuf Dm, t1A, t2A, P2, P2c, P1, P1c;
+  DevBuf Dm, t1A, P1, P1c, X, Xc;
   Dm.ensure(vv * vv * 16);
   launch_fill_zero<double>(Dm.p, vv * vv, st);
   t1A.ensure(oo * vv * 16);
-  t2A.ensure(n2f * 16);
-  P2.ensure(n2f * 16);
-  P2c.ensure(n2f * 16);
   P1.ensure(oo * vv * 16);
   P1c.ensure(oo * vv * 16);
   const int64_t p0[4] = {0, 0, o, o}, np[4] = {o, o, v, v}, r0[4] = {0, o, 0, o}, nr[4] = {o, v, o, v};
@@ -231,16 +302,13 @@ void Context::fnspp_truncate(const double* om, int nw, double thresh, int keep, 
                           x64->ptr(P.n_A[k]), st);
     x64->run(P.fnspp, 1);
     for (int k = 0; k < nw; ++k) {
-      hipLaunchKernelGGL(fnspp_divide_kernel, dim3(grid_of(oo * vv + n2f)), dim3(256), 0, st, oo, vv,
-                         Hd.as<double>(), Hd.as<double>() + oo, om[k], (const double2*)x64->ptr(P.n_s1),
-                         (const double2*)x64->ptr(P.n_s2), (double2*)t1A.p, (double2*)t2A.p);
-      HIP_CHECK(hipGetLastError());
-      // D[a][b] += s/2 sum_{ijc} t2A[ijac] conj t2A[ijbc]
-      permute(t2A.p, P2.p, {vv, oo, oo, vv}, {vv, oo * vv * vv, vv * vv, 1}, st);  // [a][i][j][c]
-      conj_copy(n2f, P2.p, P2c.p, st);
-      launch_gemm<double>(false, true, vv, vv, oo * oo * vv, 0.5 * scale, 0.0, P2.p, oo * oo * vv, P2c.p,
-                          oo * oo * vv, 1.0, 0.0, Dm.p, vv, st);
+      // D[a][b] += s/2 sum_{ijc} t2A[ijac] conj t2A[ijbc], t2A formed chunk by chunk
+      pair_density(oo, vv, x64->ptr(P.n_s2), Hd.as<double>(), Hd.as<double>() + oo, om[k], 0.5 * scale, Dm.p, X,
+                   Xc, st);
       // D[a][b] += s sum_i t1A[ia] conj t1A[ib]
+      hipLaunchKernelGGL(fnspp_singles_kernel, dim3(grid_of(oo * vv)), dim3(256), 0, st, oo, vv, Hd.as<double>(),
+                         Hd.as<double>() + oo, om[k], (const double2*)x64->ptr(P.n_s1), (double2*)t1A.p);
+      HIP_CHECK(hipGetLastError());
       permute(t1A.p, P1.p, {vv, oo}, {1, vv}, st);  // [a][i]
       conj_copy(oo * vv, P1.p, P1c.p, st);
       launch_gemm<double>(false, true, vv, vv, oo, scale, 0.0, P1.p, oo, P1c.p, oo, 1.0, 0.0, Dm.p, vv, st);
@@ -256,16 +324,12 @@ void Context::fns_truncate(double thresh, int keep, int* nvir_out, double* occ_o
   LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
   LRCC_REQUIRE(keep >= 0 && keep <= v && (keep > 0 || thresh > 0), LRCC_E_INVALID, "bad keep / thresh");
   const int64_t vv = v, oo = o;
-  const size_t n2f = (size_t)oo * oo * vv * vv;
-  DevBuf P2, P2c, Dm;
+  DevBuf X, Xc, Dm;
   void* tm2 = mp2_doubles(*this);
-  P2.ensure(n2f * 16);
-  P2c.ensure(n2f * 16);
+  release_goovv_if_alone();
   Dm.ensure(vv * vv * 16);
-  permute(tm2, P2.p, {vv, oo, oo, vv}, {vv, oo * vv * vv, vv * vv, 1}, st);  // [a][i][j][c]
-  conj_copy(n2f, P2.p, P2c.p, st);
-  launch_gemm<double>(false, true, vv, vv, oo * oo * vv, 0.5, 0.0, P2.p, oo * oo * vv, P2c.p, oo * oo * vv, 0.0, 0.0,
-                      Dm.p, vv, st);
+  launch_fill_zero<double>(Dm.p, vv * vv, st);
+  pair_density(oo, vv, tm2, nullptr, nullptr, 0.0, 0.5, Dm.p, X, Xc, st);
   truncate_by_density(Dm.p, thresh, keep, nvir_out, occ_out);
 }
 
@@ -347,6 +411,7 @@ void Context::truncate_by_density(const void* Dmp, double thresh, int keep, int*
 // the last alpha are not touched.
 void Context::mp2_response(int nw, const double* om, cplx& emp2, std::vector<cplx>& al) {
   require_sizes();
+  ensure_integrals();
   LRCC_REQUIRE(have_fock, LRCC_E_STATE, "lrcc_load_fock has not been called");
   LRCC_REQUIRE(ncomp > 0, LRCC_E_STATE, "lrcc_load_dipoles has not been called");
   LRCC_REQUIRE(nw >= 1 && om != nullptr, LRCC_E_INVALID, "need at least one frequency");

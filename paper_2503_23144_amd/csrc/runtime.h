@@ -77,6 +77,9 @@ class Executor {
   // Free the private storage of the unbatched tensors `ops` writes (its
   // results; they are formed again by the next run of `ops`).
   void release_results(const OpList& ops);
+  // Free the private storage of one unbatched tensor (allocated again on
+  // its next use).
+  void release(int id);
   size_t bytes_allocated() const;
 
   // optional per-launch timing (HIP events on the stream)

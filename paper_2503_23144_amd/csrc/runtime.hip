@@ -174,6 +174,16 @@ void Executor<T>::release_results(const OpList& ops) {
 }
 
 template <typename T>
+void Executor<T>::release(int id) {
+  if (id < 0 || m_[id].batched || bound_[id] || pooled_[id] || !buf_[id]) return;
+  on_realloc();
+  HIP_CHECK(hipStreamSynchronize(st_));
+  dev_free(buf_[id]);
+  buf_[id] = nullptr;
+  cap_[id] = 0;
+}
+
+template <typename T>
 size_t Executor<T>::bytes_allocated() const {
   size_t s = 0;
   for (size_t k = 0; k < buf_.size(); ++k)

@@ -117,6 +117,7 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   dims = Dims{o, v, o * (o - 1) / 2, v * (v - 1) / 2};
   n2 = dims.O * dims.V;
   n = n1 + n2;
+  if (B.bytes > 2 * (size_t)(naux * nmo * nmo * 16)) B.release();  // e.g. after a truncation
   B.ensure(naux * nmo * nmo * 16);
   copy_in(B.p, Bp, naux * nmo * nmo * 16, where, st);
   {  // the method (and the ladder's use of W = W^H) needs B^Q Hermitian for every Q
@@ -149,21 +150,47 @@ void Context::load_df(int nocc, int nvir, int na, const void* Bp, int where) {
   L32.release();
   Tri64.release();
   Tri32.release();
-  if (mode64 != LRCC_LADDER_FULL || (mixed && mode32 != LRCC_LADDER_FULL)) {
+  ints_built = goovv_built = false;  // the blocks are formed on first need (ensure_integrals)
+  have_fock = false;
+  ncomp = 0;
+  reset_solutions();
+}
+
+// The integral blocks are formed when something first needs them, not by
+// load_df: a system loaded only to be truncated (FNS / FNS++) needs <oo||vv>
+// alone, while all blocks of its full virtual space may not fit the device.
+void Context::ensure_integrals() {
+  if (ints_built) return;
+  require_sizes();
+  if (mode64 != LRCC_LADDER_FULL || (cfg.precision == LRCC_MIXED && mode32 != LRCC_LADDER_FULL)) {
     // the virtual-virtual block of B builds W's rows
     L64.ensure((size_t)naux * v * v * 16);
     launch_gather_block(naux, nmo, o, v, o, v, B.p, L64.p, st);
   }
   if (mode64 == LRCC_LADDER_DIRECT) x64->set_direct_ladder(L64.p, naux, v);
   build_integrals();
-  have_fock = false;
-  ncomp = 0;
-  reset_solutions();
+  ints_built = true;
+}
+
+void Context::ensure_goovv() {
+  if (ints_built || goovv_built) return;
+  require_sizes();
+  build_block(B.p, naux, o, v, "oovv", x64->ptr(P.m.find("goovv")), st);
+  goovv_built = true;
+}
+
+// <oo||vv> built alone for a truncation is freed once the MP2 doubles and
+// Hbar diagonals are formed (the full set is built again on first need).
+void Context::release_goovv_if_alone() {
+  if (ints_built || !goovv_built) return;
+  x64->release(P.m.find("goovv"));
+  goovv_built = false;
 }
 
 void Context::build_integrals() {
   for (auto& b : kBlocks)
-    if (!(lean && lean_block(b[0]))) build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
+    if (!(lean && lean_block(b[0])) && !(goovv_built && !std::strcmp(b[0], "goovv")))
+      build_block(B.p, naux, o, v, b[1], x64->ptr(P.m.find(b[0])), st);
   if (mode64 == LRCC_LADDER_FULL) build_packed_vvvv(B.p, naux, o, v, x64->ptr(P.m.find("W")), st);
   if (mode64 == LRCC_LADDER_TRIANGLE || (cfg.precision == LRCC_MIXED && mode32 == LRCC_LADDER_TRIANGLE)) {
     // row blocks of about equal size (rows grow as b^2): b_j = 1 + (v - 1) sqrt(j / nb)
@@ -208,6 +235,7 @@ std::vector<typename Executor<T>::TriBlock> Context::tri_blocks(const void* base
 
 static void ensure_x32(Context& c) {
   if (c.x32) return;
+  c.ensure_integrals();
   const int W = c.P.m.find("W");
   auto stored = [&](int id) {  // constants the FP32 executor holds a copy of (W apart)
     const Role r = c.P.m[id].role;
@@ -332,6 +360,7 @@ static void make_room(A* run, const OpList& ops, int nb, const std::vector<int>&
 }
 
 void Context::residual64(const void* tvec, void* R, cplx* E) {
+  ensure_integrals();
   make_room(x64.get(), P.residual, 1, {}, x32.get());
   x64->bind(P.t1, const_cast<void*>(tvec));
   x64->bind(P.t2p, (char*)const_cast<void*>(tvec) + n1 * 16);

@@ -426,16 +426,20 @@ def test_fnspp_truncation_matches_oracle():
     assert _relerr(c.alpha(1), ref.alpha) < 1e-8
 
 
-def test_fnspp_truncation_at_larger_space_matches_oracle():
-    """FNS++ from 48 virtuals to 20 at o=6 (a 48 x 48 density from 15 x 48^2
+@pytest.mark.parametrize("pairs_per_chunk", [None, 7])
+def test_fnspp_truncation_at_larger_space_matches_oracle(monkeypatch, pairs_per_chunk):
+    """FNS++ from 48 virtuals to 20 at o=6 (a 48 x 48 density from 36 x 48^2
     perturbed doubles per direction and frequency, three directions, two
     frequencies): all 48 occupations against the oracle, and E_corr and alpha
     in the truncated space against the oracle's solve in its own truncated
     space (alpha and E do not depend on the phases or the order the two
-    eigensolvers give the kept spinors)."""
+    eigensolvers give the kept spinors).  With 7 (i, j) pairs per chunk the
+    density accumulates over 6 chunks, the last holding one pair."""
     from oracle.fnspp import fnspp_transform
     from oracle.response import lr_ccsd
     o, v, keep = 6, 48, 20
+    if pairs_per_chunk:
+        monkeypatch.setenv("LRCC_DENSITY_CHUNK_BYTES", str(pairs_per_chunk * v * v * 16))
     inp = make_inputs(o, v, 24, seed=37)
     inp.B = inp.B * 4.0
     omegas = [0.02, 0.15]
@@ -452,12 +456,16 @@ def test_fnspp_truncation_at_larger_space_matches_oracle():
     assert _relerr(c.alpha(1), ref.alpha) < 1e-8
 
 
-def test_fns_truncation_matches_oracle():
+@pytest.mark.parametrize("pairs_per_chunk", [None, 2])
+def test_fns_truncation_matches_oracle(monkeypatch, pairs_per_chunk):
     """Ground-state natural spinors (Eq. 40): occupations, the truncated
-    space and alpha in it against the oracle."""
+    space and alpha in it against the oracle (with 2 (i, j) pairs per
+    density chunk: 5 chunks, the last holding one pair)."""
     from oracle.fnspp import fns_transform
     from oracle.response import lr_ccsd
     o, v, keep = 3, 10, 6
+    if pairs_per_chunk:
+        monkeypatch.setenv("LRCC_DENSITY_CHUNK_BYTES", str(pairs_per_chunk * v * v * 16))
     inp = make_inputs(o, v, 12, seed=31)
     inp.B = inp.B * 8.0
     U, n_ref, (Bn, fn, mun) = fns_transform(inp.B, inp.fock, inp.mu, o, keep=keep)
