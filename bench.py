@@ -393,9 +393,9 @@ def cpu_baseline(inp, budget_s=25.0):
                       f"integral build excluded ({dt:.1f} s)"}
 
 
-def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0):
+def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0, ring=None):
     c = lrcc.Context(precision=precision, tol=tol, ladder=ladder, ladder_fp64=ladder_fp64, memory="lean",
-                     rhs_chunk=chunk)
+                     rhs_chunk=chunk, ring_factored=ring)
     c.load_df(inp.o, inp.v, dev_in["B"])
     c.load_fock(dev_in["fock"])
     c.load_dipoles(dev_in["mu"])
@@ -456,14 +456,16 @@ def sigma_leg(lrcc, inp, dev_in, nb, steps, warmup):
 
 def fp64_plain_leg(lrcc, inp, dev_in, t, X0, reps=3):
     """The plain FP64 solver's product at full size: one right-hand side per
-    product, FP64 W resident.  Also the parity checks at this size: the
+    product, FP64 W resident, the ring's dt1 terms factored as in the mixed
+    leg (FP64 Z1, 41 GB; the solver's automatic choice at this size would
+    contract them directly).  Also the parity checks at this size: the
     adjoint identity u.(A v) = (u A).v and the FP64 product of the first
     right-hand side for the mixed leg's comparison."""
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    c = _c5_context(lrcc, inp, dev_in, "fp64", "full")
+    c = _c5_context(lrcc, inp, dev_in, "fp64", "full", ring=True)
     c.set_amplitudes(lrcc.AMP_T, t)
     X = torch.tensor(X0[None], dtype=torch.complex128, device=dev)
     out = torch.empty_like(X)
@@ -789,6 +791,7 @@ def main_c5(args):
                                f"products over chunks of {nb} of the 3 dipole directions x {len(cfg['omegas'])} omegas "
                                f"in [0,{max(cfg['omegas']):.1f}] Ha",
                    "precision": "mixed", "rhs_per_product": nb, "memory_layout": "lean",
+                   "ring_dt1_terms": "factored (Z1 = t2 . <ov||vv>, formed once per T)",
                    "amplitudes": "seeded random T (0.01 N(0,1)) and X (N(0,1)), complex"},
         "ladder_tflops": ladder_tf,
         "ladder_complex_equiv_tflops": ladder_tf * 8.0 / 6.0,
@@ -808,7 +811,7 @@ def main_c5(args):
         mvf = float(np.abs(sig["row0_mixed"] - fp["row0_fp64"]).max() / np.abs(fp["row0_fp64"]).max())
         out["fp64_plain"] = {k: v for k, v in fp.items() if k != "row0_fp64"}
         out["fp64_plain"]["sample"] = (f"{fp['products']} right products of one right-hand side each at o=40, v=400, "
-                                       "FP64 W (102 GB) resident")
+                                       "FP64 W (102 GB) resident, ring dt1 terms factored as in the mixed leg")
         out["mixed_over_fp64_plain_sigma_rate"] = value / fp["sigma_evals_per_s"]
         out["check_mixed_vs_fp64_rel"] = mvf
         out["check_adjoint_identity_rel"] = fp["adjoint_identity_rel"]

@@ -106,6 +106,13 @@ typedef struct lrcc_config {
                             contraction forms the dense block it reads in chunks of at most 1 GiB.
                             Intermediates only one product reads are freed after it in every mode.
                             Results agree between modes to rounding. */
+  int ring_factored;     /* the part of the ring term linear in dt1, t2 . dW(dt1), in the right and
+                            left Jacobian products: 1 as dt1 contracted with Z1 = t2 . <ov||vv>-like
+                            and Z2 (o v^3 and o^3 v complex elements, formed once per T at o^2 v^4
+                            cost), an o^2 v^3 contraction per right-hand side; 0 as the o^3 v^3
+                            contraction of t2 with dW per right-hand side; -1 (default) 1 for each
+                            executor whose Z1 takes at most 24 GiB at its precision, else 0.
+                            Results agree to rounding. */
 } lrcc_config;
 
 #define LRCC_LADDER_FULL 0
@@ -138,7 +145,11 @@ const char *lrcc_last_error(const lrcc_ctx *ctx);
 /* Density-fitting factors B[naux][nmo][nmo] (complex, B^Q Hermitian in pq for
    every Q).  Coulomb integrals (pr|qs) = sum_Q B^Q_pr B^Q_qs; the library
    builds the antisymmetrized blocks <pq||rs> = (pr|qs) - (ps|qr) it needs on
-   the device (Section II.B, Eq. 39 uses <ij||ab>).  Resets all solutions. */
+   the device (Section II.B, Eq. 39 uses <ij||ab>) when a later call first
+   needs them: here B is copied and checked only, so that a space loaded to
+   be truncated (lrcc_fnspp_truncate, lrcc_fns_truncate) forms <oo||vv>
+   alone.  An allocation failure of the blocks is reported by that later
+   call.  Resets all solutions. */
 int lrcc_load_df(lrcc_ctx *ctx, int nocc, int nvir, int naux, const void *B, int where);
 /* Fock matrix F[nmo][nmo], Hermitian; may be non-diagonal.  The diagonal
    gives the Jacobi preconditioner D_mu = e_a (+ e_b) - e_i (- e_j). */
@@ -270,7 +281,9 @@ int lrcc_gemm_set_tile(int tile);
 /* Text of the derived operation lists (host-only, no GPU needed):
    which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L
    along (X, mu), 5 dE/dt, 6 grad L, 7 F X (tangent of grad L along X),
-   8 FNS++ projections of the perturbation over the MP2 doubles.
+   8 FNS++ projections of the perturbation over the MP2 doubles, 9 the setup
+   of the factored ring terms (Z1, Z2 from t), 10 right and 11 left sigma
+   with the factored ring terms (they read Z1 and Z2).
    Writes at most `cap` bytes including the NUL; returns the full length. */
 int64_t lrcc_program_text(int which, char *buf, int64_t cap);
 

@@ -84,6 +84,7 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->ladder_mode = LRCC_LADDER_FULL;
   cfg->ladder_mode_fp64 = -1;
   cfg->memory_mode = LRCC_MEMORY_AUTO;
+  cfg->ring_factored = -1;
 }
 
 int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
@@ -100,6 +101,7 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
                  "bad ladder_mode_fp64");
     LRCC_REQUIRE(c.memory_mode >= LRCC_MEMORY_AUTO && c.memory_mode <= LRCC_MEMORY_LEAN, LRCC_E_INVALID,
                  "bad memory_mode");
+    LRCC_REQUIRE(c.ring_factored >= -1 && c.ring_factored <= 1, LRCC_E_INVALID, "bad ring_factored");
     LRCC_REQUIRE(c.tol_residual > 0 && c.maxit > 0 && c.diis_size >= 0 && c.diis_size <= 32 && c.rhs_chunk >= 0,
                  LRCC_E_INVALID, "bad tolerance, iteration limit, DIIS size or chunk");
     int ndev = 0;
@@ -352,6 +354,7 @@ int lrcc_set_amplitudes(lrcc_ctx* ctx, int which, int idx, const void* in, int w
       c.have_t = true;
       c.have_lam = c.have_alpha = false;
       c.primal64 = c.primal32 = c.gradL_ready = 0;
+      c.ring64 = c.ring32 = 0;
     } else if (which == LRCC_AMP_LAMBDA) {
       LRCC_REQUIRE(c.have_t, LRCC_E_STATE, "set T before Lambda");
       c.lam.ensure(vb);
@@ -412,9 +415,9 @@ int64_t lrcc_program_text(int which, char* buf, int64_t cap) {
       lrcc::build_programs(p);
       return p;
     }();
-    const lrcc::OpList* lists[] = {&P.residual, &P.right, &P.left, &P.xi, &P.hvp,
-                                   &P.eta0,     &P.gradL, &P.hvpt, &P.fnspp};
-    if (which < 0 || which > 8) return -1;
+    const lrcc::OpList* lists[] = {&P.residual, &P.right, &P.left,       &P.xi,      &P.hvp,   &P.eta0,
+                                   &P.gradL,    &P.hvpt, &P.fnspp, &P.ring_setup, &P.right_f, &P.left_f};
+    if (which < 0 || which > 11) return -1;
     std::string s = lrcc::serialize(P.m, *lists[which]);
     if (buf && cap > 0) {
       int64_t k = std::min<int64_t>(cap - 1, (int64_t)s.size());

@@ -55,6 +55,9 @@ enum class Side { Right, Left };
 
 // Device bytes the pipeline needs with batches of up to nrhs right-hand sides.
 size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nrhs);
+// Whether an executor of precision prec (64 or 32) takes the factored ring
+// terms (lrcc_config.ring_factored; automatic by the size of Z1).
+bool ring_factored_for(const lrcc_config& cfg, int o, int v, int prec);
 
 struct Context {
   explicit Context(const lrcc_config& cfg);
@@ -87,6 +90,12 @@ struct Context {
   DevBuf t, t32, lam, lam32;
   bool have_t = false, have_lam = false;
   int primal64 = 0, primal32 = 0;  // 1 if primal intermediates are at the current t
+  int ring64 = 0, ring32 = 0;      // 1 if Z1, Z2 of the factored ring terms are at the current t
+  // The factored ring terms in the FP64 (prec 64) or FP32 executor's right
+  // and left products (lrcc_config.ring_factored), and the programs to run.
+  bool factored(int prec) const;
+  const OpList& right_prog(int prec) const { return factored(prec) ? P.right_f : P.right; }
+  const OpList& left_prog(int prec) const { return factored(prec) ? P.left_f : P.left; }
   int gradL_ready = 0;
   cplx ecorr = 0;
 

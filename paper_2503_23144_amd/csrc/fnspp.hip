@@ -443,6 +443,7 @@ void Context::mp2_response(int nw, const double* om, cplx& emp2, std::vector<cpl
   if (had_lam) HIP_CHECK(hipMemcpyAsync(ls.ensure(vb), lam.p, vb, hipMemcpyDeviceToDevice, st));
   auto invalidate = [&]() {
     primal64 = primal32 = 0;
+    ring64 = ring32 = 0;
     gradL_ready = gradL32_ready = 0;
   };
   struct Restore {
@@ -457,6 +458,7 @@ void Context::mp2_response(int nw, const double* om, cplx& emp2, std::vector<cpl
       c.have_t = ht;
       c.have_lam = hl;
       c.primal64 = c.primal32 = 0;
+      c.ring64 = c.ring32 = 0;
       c.gradL_ready = c.gradL32_ready = 0;
     }
   } restore{*this, ts, ls, had_t, had_lam, vb};

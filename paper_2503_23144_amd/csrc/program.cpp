@@ -53,6 +53,7 @@ OpList parse_program(Module& m, const std::string& text) {
   static const std::regex re_one(R"(^(\w+)\[(\w*)\]$)");
   static const std::regex re_nodiff(R"(^nodiff\(\s*(\w+)\[(\w*)\]\s*\)$)");
   static const std::regex re_partner(R"(^(\w+)\[(\w*)\]\s*\*\s*(\w+)\[(\w*)\]\s*~\s*(\w+)\[(\w*)\]$)");
+  static const std::regex re_viaterm(R"(^(\w+)\[(\w*)\]\s*\*\s*(\w+)\[(\w*)\]$)");
 
   OpList ops;
   std::set<int> read;      // tensors already read (no further writes allowed)
@@ -95,12 +96,20 @@ OpList parse_program(Module& m, const std::string& text) {
     } else {
       if (m[out].role != Role::Temp) fail("cannot write " + oname);
       if (read.count(out)) fail(oname + " written after being read");
-      if (!op.acc) fail(oname + " overwritten");
+      if (!op.acc && !m.forward.count(out)) fail(oname + " overwritten");
+      if (op.acc && m.forward.count(out)) fail("first write of " + oname + " must be '='");
       if (m[out].cls != classes_of(oidx)) fail("index classes of " + oname);
+      m.forward.erase(out);
     }
     written.insert(out);
     op.out = out;
     op.oi = oidx;
+    std::string via_text;
+    const size_t bar = rhs.find('|');
+    if (bar != std::string::npos) {
+      via_text = trim(rhs.substr(bar + 1));
+      rhs = trim(rhs.substr(0, bar));
+    }
     std::smatch mc;
     if (std::regex_match(rhs, mc, re_coef)) {
       op.are = std::stod(mc[1]);
@@ -149,22 +158,58 @@ OpList parse_program(Module& m, const std::string& text) {
     } else {
       fail("bad right-hand side");
     }
+    if (!via_text.empty()) {
+      if (op.kind != OpKind::Contract) fail("via terms need a contraction");
+      std::istringstream terms(via_text);
+      std::string term;
+      while (std::getline(terms, term, '+')) {
+        term = trim(term);
+        std::smatch mv;
+        if (!std::regex_match(term, mv, re_viaterm)) fail("bad via term '" + term + "'");
+        Op::Via vt;
+        vt.var = use(mv[1], mv[2]);
+        vt.vi = mv[2];
+        vt.z = m.find(mv[3]);
+        if (vt.z < 0) {  // formed later by a setup program
+          vt.z = m.add(mv[3], classes_of(mv[4]), Role::Temp);
+          m.forward.insert(vt.z);
+        }
+        vt.z = use(mv[3], mv[4]);
+        vt.zi = mv[4];
+        // the term must produce the op's output indices
+        std::string have = vt.vi + vt.zi, want = op.oi;
+        for (char c : want)
+          if (have.find(c) == std::string::npos) fail("via term does not carry index " + std::string(1, c));
+        op.via.push_back(vt);
+      }
+      if (op.via.empty()) fail("empty via list");
+    }
     if (op.a == op.out || op.b == op.out || op.partner == op.out) fail("in-place update");
     ops.push_back(op);
   }
   return ops;
 }
 
+// A derived tensor by name: a second derivation with the same tag (a variant
+// of a program) reuses the tensors of the first.
+static int derived_tensor(Module& m, const std::string& name, const std::string& cls, Role role, bool batched) {
+  const int id = m.find(name);
+  if (id < 0) return m.add(name, cls, role, batched);
+  if (m[id].cls != cls || m[id].role != role || m[id].batched != batched)
+    throw Error(LRCC_E_INTERNAL, "derived tensor " + name + " redeclared differently");
+  return id;
+}
+
 static int tangent_of(Module& m, std::map<int, int>& tan, int t, const std::string& tag) {
   auto it = tan.find(t);
   if (it != tan.end()) return it->second;
-  int id = m.add(tag + "(" + m[t].name + ")", m[t].cls, Role::Tangent, true);
+  const int id = derived_tensor(m, tag + "(" + m[t].name + ")", m[t].cls, Role::Tangent, true);
   tan[t] = id;
   return id;
 }
 
 OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::vector<int>& want,
-           const std::string& tag) {
+           const std::string& tag, bool use_via) {
   std::set<int> live;
   for (auto& kv : tan) live.insert(kv.first);
   OpList out;
@@ -182,12 +227,26 @@ OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::ve
         c.a = tangent_of(m, tan, op.a, tag);
         if (op.partner >= 0) c.b = op.partner;
         c.partner = -1;
+        c.via.clear();
         contrib.push_back(c);
       }
-      if (lv(op.b)) {
+      if (lv(op.b) && use_via && !op.via.empty()) {
+        for (const Op::Via& vt : op.via) {
+          if (!lv(vt.var)) continue;  // a variable with no tangent contributes nothing
+          Op c = op;
+          c.a = tangent_of(m, tan, vt.var, tag);
+          c.ai = vt.vi;
+          c.b = vt.z;
+          c.bi = vt.zi;
+          c.partner = -1;
+          c.via.clear();
+          contrib.push_back(c);
+        }
+      } else if (lv(op.b)) {
         Op c = op;
         c.b = tangent_of(m, tan, op.b, tag);
         c.partner = -1;
+        c.via.clear();
         contrib.push_back(c);
       }
     } else if (lv(op.a)) {
@@ -217,7 +276,7 @@ OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::ve
 }
 
 OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::vector<int>& wrt,
-           bool batched, const std::string& tag) {
+           bool batched, const std::string& tag, bool use_via) {
   std::set<int> act(wrt.begin(), wrt.end());
   for (const Op& op : prog)
     if (!op.nodiff && (act.count(op.a) || (op.b >= 0 && act.count(op.b)))) act.insert(op.out);
@@ -226,7 +285,7 @@ OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::ve
   auto adjoint = [&](int t) {
     auto it = adj.find(t);
     if (it != adj.end()) return it->second;
-    int id = m.add(tag + "(" + m[t].name + ")", m[t].cls, Role::Adjoint, batched);
+    const int id = derived_tensor(m, tag + "(" + m[t].name + ")", m[t].cls, Role::Adjoint, batched);
     adj[t] = id;
     return id;
   };
@@ -268,7 +327,19 @@ OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::ve
           d.bi = op.bi;
           emit(d, op.a);
         }
-        if (act.count(op.b)) {
+        if (act.count(op.b) && use_via && !op.via.empty()) {
+          for (const Op::Via& vt : op.via) {
+            if (!act.count(vt.var)) continue;
+            Op d = c;
+            d.kind = OpKind::Contract;
+            d.oi = vt.vi;
+            d.a = vt.z;
+            d.ai = vt.zi;
+            d.b = g;
+            d.bi = op.oi;
+            emit(d, vt.var);
+          }
+        } else if (act.count(op.b)) {
           Op d = c;
           d.kind = OpKind::Contract;
           d.oi = op.bi;
@@ -347,6 +418,8 @@ std::string dump(const Module& m, const OpList& prog) {
       case OpKind::Contract:
         os << ref(op.a, op.ai) << " * " << ref(op.b, op.bi);
         if (op.partner >= 0) os << " ~ " << ref(op.partner, op.bi);
+        for (size_t k = 0; k < op.via.size(); ++k)
+          os << (k ? " + " : " | ") << ref(op.via[k].var, op.via[k].vi) << " * " << ref(op.via[k].z, op.via[k].zi);
         break;
       case OpKind::Pack:
       case OpKind::Unpack:
@@ -390,6 +463,11 @@ std::string serialize(const Module& m, const OpList& prog) {
 // there t2 . Y(c) = c . Y(t2) (swap (i,a) <-> (j,b), m <-> n, e <-> f), so
 // its derivative along dt is dt . (W1 + 2 Y) + t2 . dW1: the derivative
 // programs run one (ov)^3 ring contraction fewer (nodiff / partner below).
+// The remaining t2 . dW1 is linear in dt1 alone (W1 depends on t1 and the
+// integrals only): t2[imae] dW1[jbme] = dt1[jf] Z1[iabf] + dt1[nb] Z2[ianj]
+// with Z1, Z2 formed once per t by kRingSetup, so first-derivative programs
+// built with via terms replace that o^3 v^3 contraction per right-hand side
+// by two of o^2 v^3 and o^3 v^2 (the via list below).
 const char* kCcsdProgram = R"(
 input  t1[ia] t2p[IA]
 fock   foo[ij] fov[ia] fvo[ai] fvv[ab]
@@ -451,7 +529,7 @@ Pab[ijab]    = t2[ijae] * Ft[be]
 Pab[ijab]   += -1 * t1[ma] * govoo[mbij]
 Pij[ijab]    = -1 * t2[imab] * Fmt[mj]
 Pij[ijab]   += t1[ie] * gvvvo[abej]
-Pijab[ijab]  = t2[imae] * Wmbej[jbme] ~ W2[jbme]
+Pijab[ijab]  = t2[imae] * Wmbej[jbme] ~ W2[jbme] | t1[jf] * Z1[iabf] + t1[nb] * Z2[ianj]
 Pijab[ijab] += -1 * t1[ma] * Xmbij[mbij]
 S0[ijab]     = gvvoo[abij]
 S0[ijab]    += 0.5 * tau[mnab] * Wmnij[mnij]
@@ -471,6 +549,21 @@ Xjb[jb] = goovv[ijab] * t1[ia]
 E[]  = fov[ia] * t1[ia]
 E[] += 0.25 * goovv[ijab] * t2[ijab]
 E[] += 0.5 * Xjb[jb] * t1[jb]
+)";
+
+// The tensors of the via terms of the ring contraction, from the primal
+// intermediates t2, t1 and X_mnej of kCcsdProgram:
+//   Z1[iabf] = sum_me t2[imae] (<mb||ef> - sum_n t1[nb] <mn||ef>)
+//   Z2[ianj] = sum_me t2[imae] (<mn||je> - X[mnej])
+// (the dt1 coefficients of dW1: <mb||ef>, the -t1 X(dt1) term through
+// X_mnej = t1 . <mn||ef>, and <mn||je> - X_mnej).  Forming Z1 costs o^2 v^4
+// once per t.
+const char* kRingSetup = R"(
+Zq[ianf]  = t2[imae] * goovv[mnef]
+Z1[iabf]  = t2[imae] * govvv[mbef]
+Z1[iabf] += -1 * t1[nb] * Zq[ianf]
+Z2[ianj]  = t2[imae] * gooov[mnje]
+Z2[ianj] += -1 * t2[imae] * Xmnej[mnej]
 )";
 
 // Abar_i^a = A_ai + sum_me A_me t_im^ae;
@@ -506,6 +599,8 @@ void mark_persistent(Module& m, const std::vector<const OpList*>& progs) {
 void build_programs(CcPrograms& P) {
   Module& m = P.m;
   P.residual = parse_program(m, kCcsdProgram);
+  P.ring_setup = parse_program(m, kRingSetup);
+  if (!m.forward.empty()) throw Error(LRCC_E_INTERNAL, "a via tensor is never formed");
   P.fnspp = parse_program(m, kFnsppProgram);
   P.n_t2 = m.find("tm2");
   P.n_A[0] = m.find("Aoo");
@@ -536,6 +631,11 @@ void build_programs(CcPrograms& P) {
     P.r_dO1 = tan.at(P.O1);
     P.r_dO2p = tan.at(P.O2p);
     P.right = prune(m, ops, {P.r_dO1, P.r_dO2p});
+    // the same tangent tensors, with the ring's via terms
+    std::map<int, int> tf{{P.t1, P.r_dt1}, {P.t2p, P.r_dt2p}};
+    OpList fops = jvp(m, P.residual, tf, {P.O1, P.O2p}, "R", true);
+    if (tf.at(P.O1) != P.r_dO1 || tf.at(P.O2p) != P.r_dO2p) throw Error(LRCC_E_INTERNAL, "right variant outputs");
+    P.right_f = prune(m, fops, {P.r_dO1, P.r_dO2p});
   }
   {  // left sigma: adjoint of Omega with batched cotangents
     std::map<int, int> adj;
@@ -547,6 +647,11 @@ void build_programs(CcPrograms& P) {
     P.l_gt1 = adj.at(P.t1);
     P.l_gt2p = adj.at(P.t2p);
     P.left = prune(m, ops, {P.l_gt1, P.l_gt2p});
+    // the same adjoint tensors, with the ring's via terms
+    std::map<int, int> af{{P.O1, P.l_gO1}, {P.O2p, P.l_gO2p}};
+    OpList fops = vjp(m, P.residual, af, {P.t1, P.t2p}, true, "L", true);
+    if (af.at(P.t1) != P.l_gt1 || af.at(P.t2p) != P.l_gt2p) throw Error(LRCC_E_INTERNAL, "left variant outputs");
+    P.left_f = prune(m, fops, {P.l_gt1, P.l_gt2p});
   }
   {  // eta0 = dE/dt
     std::map<int, int> adj;
@@ -607,7 +712,8 @@ void build_programs(CcPrograms& P) {
     P.f_out2p = tt.at(P.g_gt2p);
     P.hvpt = prune(m, fops, {P.f_out1, P.f_out2p});
   }
-  mark_persistent(m, {&P.residual, &P.right, &P.left, &P.eta0, &P.xi, &P.gradL, &P.hvp, &P.hvpt, &P.fnspp});
+  mark_persistent(m, {&P.residual, &P.ring_setup, &P.right, &P.right_f, &P.left, &P.left_f, &P.eta0, &P.xi, &P.gradL,
+                      &P.hvp, &P.hvpt, &P.fnspp});
 }
 
 }  // namespace lrcc

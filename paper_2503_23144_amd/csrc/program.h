@@ -60,6 +60,22 @@ struct Op {
   // da . (W1 + 2 Y) + a . dW1, one contraction with da fewer.
   bool nodiff = false;
   int partner = -1;
+  //  via       a Contract whose first-order derivative through its second
+  //            operand b is given directly as sum_k du_k[vi] * Z_k[zi], with u_k
+  //            the variables b depends on and Z_k primal tensors a setup
+  //            program forms (a re-association: the derivative programs
+  //            that use it contract the small tangent du_k with a
+  //            precomputed Z_k instead of forming db and contracting it with
+  //            the first operand).  Valid for first derivatives only: a
+  //            program differentiated again must not use it, since Z_k's own
+  //            dependence on the variables is not part of the program.
+  struct Via {
+    int var = -1;
+    std::string vi;
+    int z = -1;
+    std::string zi;
+  };
+  std::vector<Via> via;
 };
 
 using OpList = std::vector<Op>;
@@ -73,6 +89,9 @@ struct Module {
   // unbatched temporaries that a program both writes and reads live only
   // for that run.
   std::vector<char> persistent;
+  // Tensors named by a `via` hint before any program writes them; the
+  // program that forms them may then write them with '=' once.
+  std::set<int> forward;
   int add(const std::string& name, const std::string& cls, Role role, bool batched = false);
   int find(const std::string& name) const;  // -1 if absent
   const TensorDecl& operator[](int i) const { return tensors.at(i); }
@@ -89,20 +108,24 @@ char letter_class(char c);
 //   X[idx] += [c *] pack(A[idx], m1[, m2])      Pack / unpack(...) Unpack
 //   X[idx] += nodiff(A[idx])                    Add left out of derivatives
 //   X[idx] = A[idx] * B[idx] ~ C[idx]           Contract; d/dA takes C for B
+//   X[idx] = A[idx] * B[idx] ... | u[i1] * Z[i2] + v[i3] * Y[i4]
+//                                               the same, with `via` terms for d/dB
 OpList parse_program(Module& m, const std::string& text);
 
 // Forward-mode tangent program.  `tan` maps seed tensors to their (batched)
 // tangent tensors on entry and is extended with every tangent created.
 // `want` lists primal tensors whose tangents must be produced (zero-filled
 // if they receive no contribution).
+// With use_via, a Contract carrying `via` terms takes its derivative
+// through b from them.
 OpList jvp(Module& m, const OpList& prog, std::map<int, int>& tan, const std::vector<int>& want,
-           const std::string& tag = "d");
+           const std::string& tag = "d", bool use_via = false);
 
 // Reverse-mode adjoint program.  `adj` maps output tensors to their
 // cotangent tensors on entry; `wrt` lists inputs whose adjoints are wanted.
 // Adjoints are created batched if `batched`.
 OpList vjp(Module& m, const OpList& prog, std::map<int, int>& adj, const std::vector<int>& wrt,
-           bool batched, const std::string& tag = "g");
+           bool batched, const std::string& tag = "g", bool use_via = false);
 
 // Remove ops that do not contribute to `keep`.
 OpList prune(const Module& m, const OpList& prog, const std::vector<int>& keep);
@@ -120,6 +143,9 @@ extern const char* kCcsdProgram;
 // doubles (the numerators of the FNS++ first-order amplitudes).
 extern const char* kFnsppProgram;
 
+// Primal setup of the tensors the ring contraction's via terms read.
+extern const char* kRingSetup;
+
 // All programs the solvers run, derived from kCcsdProgram.
 struct CcPrograms {
   Module m;
@@ -131,6 +157,9 @@ struct CcPrograms {
   OpList gradL;     // d/dt (E + lambda.Omega)                   (adjoint, unbatched)
   OpList hvp;       // tangent of gradL along (dt, df)           (batched)
   OpList hvpt;      // tangent of gradL along dt only: F dt      (batched)
+  OpList ring_setup;  // Z1, Z2 of the ring's via terms            (primal, once per t)
+  OpList right_f;     // right with the ring's via terms (reads Z1, Z2; same tensors as right)
+  OpList left_f;      // left with the ring's via terms (same tensors as left)
   // tensor ids
   int t1, t2p, foo, fov, fvo, fvv, O1, O2p, E, one;
   int r_dt1, r_dt2p, r_dO1, r_dO2p;           // right

@@ -57,6 +57,7 @@ class Executor {
   Executor& operator=(const Executor&) = delete;
 
   int64_t elems(int id, int nb) const;  // complex elements of tensor id at batch nb
+  const Module& module() const { return m_; }
   // Storage: owned (allocated on first use for the current max batch) or bound.
   void* ptr(int id);
   void bind(int id, void* p);

@@ -91,11 +91,24 @@ Context::~Context() {
   if (cst) (void)hipStreamDestroy(cst);
 }
 
+// With lrcc_config.ring_factored = -1, an executor forms Z1 of the factored
+// ring terms (o v^3 complex elements at its precision) when it takes at most
+// this much.
+constexpr double kRingFactorMaxBytes = 24.0 * double(size_t(1) << 30);
+
+bool ring_factored_for(const lrcc_config& cfg, int o, int v, int prec) {
+  if (cfg.ring_factored >= 0) return cfg.ring_factored == 1;
+  return (double)o * v * v * v * (prec == 64 ? 16.0 : 8.0) <= kRingFactorMaxBytes;
+}
+
+bool Context::factored(int prec) const { return ring_factored_for(cfg, (int)o, (int)v, prec); }
+
 void Context::require_sizes() const { LRCC_REQUIRE(n > 0, LRCC_E_STATE, "lrcc_load_df has not been called"); }
 
 void Context::reset_solutions() {
   have_t = have_lam = have_alpha = false;
   primal64 = primal32 = 0;
+  ring64 = ring32 = 0;
   gradL_ready = 0;
   omegas.clear();
   alpha.clear();
@@ -353,10 +366,19 @@ void Context::load_dipoles(int nc, const void* m, int where) {
 // run) is released.  The FP32 and FP64 products of a mixed solve alternate,
 // so they need not hold their transients at the same time.
 template <typename A, typename B>
-static void make_room(A* run, const OpList& ops, int nb, const std::vector<int>& keep, B* other) {
+static void make_room(A* run, const OpList& ops, int nb, const std::vector<int>& keep, B* other,
+                      double extra_bytes = 0.0) {
   if (!other || other->batched_bytes() == 0) return;
-  const double need = (double)run->transient_bytes(ops, nb, keep) - (double)run->batched_bytes();
+  const double need = (double)run->transient_bytes(ops, nb, keep) - (double)run->batched_bytes() + extra_bytes;
   if (need > 0.9 * (double)dev_available()) other->release_batched();
+}
+
+// Bytes of the tensors the ring setup writes and keeps (Z1, Z2), for make_room.
+template <typename X>
+static double ring_bytes(X& x, double elem) {
+  double b = 0;
+  for (const char* nm : {"Z1", "Z2"}) b += elem * (double)x.elems(x.module().find(nm), 1);
+  return b;
 }
 
 void Context::residual64(const void* tvec, void* R, cplx* E) {
@@ -370,6 +392,7 @@ void Context::residual64(const void* tvec, void* R, cplx* E) {
   x64->unbind(P.O1);
   x64->unbind(P.O2p);
   primal64 = (tvec == t.p) ? 1 : 0;
+  ring64 = 0;
   gradL_ready = 0;
   if (E) {
     double e[2];
@@ -386,6 +409,11 @@ void Context::ensure_primal(int prec) {
       work.ensure(n * 16);
       residual64(t.p, work.p, nullptr);
     }
+    if (factored(64) && !ring64) {
+      make_room(x64.get(), P.ring_setup, 1, {}, x32.get(), ring_bytes(*x64, 16.0));
+      x64->run(P.ring_setup, 1);
+      ring64 = 1;
+    }
     return;
   }
   ensure_x32(*this);
@@ -396,7 +424,13 @@ void Context::ensure_primal(int prec) {
     x32->bind(P.t2p, (char*)t32.p + n1 * 8);
     x32->run(P.residual, 1);
     primal32 = 1;
+    ring32 = 0;
     gradL32_ready = 0;
+  }
+  if (factored(32) && !ring32) {
+    make_room(x32.get(), P.ring_setup, 1, {}, x64.get(), ring_bytes(*x32, 8.0));
+    x32->run(P.ring_setup, 1);
+    ring32 = 1;
   }
 }
 
@@ -404,13 +438,13 @@ void Context::sigma64(Side side, int nb, const void* in, void* out) {
   ensure_primal(64);
   x64->set_max_batch(nb);
   const bool r = side == Side::Right;
-  make_room(x64.get(), r ? P.right : P.left, nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
+  make_room(x64.get(), r ? right_prog(64) : left_prog(64), nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
             std::vector<int>{P.l_gt1, P.l_gt2p}, x32.get());
   int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, double>(nb, n1, in, n, x64->ptr(a1), n1, st);
   launch_copy_rows<double, double>(nb, n2, (const char*)in + n1 * 16, n, x64->ptr(a2), n2, st);
-  x64->run(r ? P.right : P.left, nb, {o1, o2});
+  x64->run(r ? right_prog(64) : left_prog(64), nb, {o1, o2});
   launch_copy_rows<double, double>(nb, n1, x64->ptr(o1), n1, out, n, st);
   launch_copy_rows<double, double>(nb, n2, x64->ptr(o2), n2, (char*)out + n1 * 16, n, st);
   sigma_count += nb;
@@ -420,13 +454,13 @@ void Context::sigma32(Side side, int nb, const void* in64, void* out32) {
   ensure_primal(32);
   x32->set_max_batch(nb);
   const bool r = side == Side::Right;
-  make_room(x32.get(), r ? P.right : P.left, nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
+  make_room(x32.get(), r ? right_prog(32) : left_prog(32), nb, r ? std::vector<int>{P.r_dO1, P.r_dO2p} :
             std::vector<int>{P.l_gt1, P.l_gt2p}, x64.get());
   int a1 = r ? P.r_dt1 : P.l_gO1, a2 = r ? P.r_dt2p : P.l_gO2p;
   int o1 = r ? P.r_dO1 : P.l_gt1, o2 = r ? P.r_dO2p : P.l_gt2p;
   launch_copy_rows<double, float>(nb, n1, in64, n, x32->ptr(a1), n1, st);
   launch_copy_rows<double, float>(nb, n2, (const char*)in64 + n1 * 16, n, x32->ptr(a2), n2, st);
-  x32->run(r ? P.right : P.left, nb, {o1, o2});
+  x32->run(r ? right_prog(32) : left_prog(32), nb, {o1, o2});
   launch_copy_rows<float, float>(nb, n1, x32->ptr(o1), n1, out32, n, st);
   launch_copy_rows<float, float>(nb, n2, x32->ptr(o2), n2, (char*)out32 + n1 * 8, n, st);
   sigma_count += nb;
@@ -506,6 +540,7 @@ void Context::residual32(const void* tvec, void* R) {
   x32->unbind(P.O1);
   x32->unbind(P.O2p);
   primal32 = 0;
+  ring32 = 0;
   gradL32_ready = 0;
   launch_residual<float>(1, n, work.p, nullptr, tvec, nullptr, 0, R, st, D.as<double>());
 }
@@ -778,6 +813,7 @@ void Context::solve_ground(double ecorr_out[2], SolveStats& so) {
   launch_fill_zero<double>(t.p, n, st);
   have_t = have_lam = have_alpha = false;
   primal64 = primal32 = gradL_ready = 0;
+  ring64 = ring32 = 0;
   std::vector<SolveStats> ss;
   if (cfg.precision == LRCC_MIXED) {
     // FP32 coupling terms with the FP64 diagonal until the iteration stalls
@@ -803,6 +839,7 @@ void Context::solve_ground(double ecorr_out[2], SolveStats& so) {
   }
   so = ss[0];
   primal32 = 0;
+  ring32 = 0;
   gradL32_ready = 0;
   // evaluate once more at the solution: every stored intermediate then belongs to it
   have_t = true;
@@ -1052,11 +1089,18 @@ size_t workspace_estimate(const lrcc_config& cfg, int o, int v, int naux, int nr
   // the two executors' batch storage is not held at once when memory is
   // short (the products alternate; see make_room)
   double batch64 = 0, batch32 = 0;
-  bytes += executor(16.0, mode64, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.xi, 1}, {&P.eta0, 1},
-                                   {&P.gradL, 1}, {&P.hvp, nb}}, &batch64);
-  if (mixed)
-    bytes += executor(8.0, mode32, {{&P.residual, 1}, {&P.right, nb}, {&P.left, nb}, {&P.gradL, 1}, {&P.hvpt, nb}},
-                      &batch32);
+  const bool f64 = ring_factored_for(cfg, o, v, 64), f32 = ring_factored_for(cfg, o, v, 32);
+  std::vector<std::pair<const OpList*, int>> runs64{{&P.residual, 1}, {f64 ? &P.right_f : &P.right, nb},
+                                                    {f64 ? &P.left_f : &P.left, nb}, {&P.xi, 1}, {&P.eta0, 1},
+                                                    {&P.gradL, 1}, {&P.hvp, nb}};
+  if (f64) runs64.push_back({&P.ring_setup, 1});
+  bytes += executor(16.0, mode64, runs64, &batch64);
+  if (mixed) {
+    std::vector<std::pair<const OpList*, int>> runs32{{&P.residual, 1}, {f32 ? &P.right_f : &P.right, nb},
+                                                      {f32 ? &P.left_f : &P.left, nb}, {&P.gradL, 1}, {&P.hvpt, nb}};
+    if (f32) runs32.push_back({&P.ring_setup, 1});
+    bytes += executor(8.0, mode32, runs32, &batch32);
+  }
   // solver buffers per right-hand side (iterates, residuals, driving terms,
   // DIIS history, products, certification)
   const double solver = (double)nb * (2.0 * std::max(cfg.diis_size, 0) + 12.0) * 16.0 * n;
@@ -1072,12 +1116,12 @@ int Context::rhs_chunk_for(int nrhs, int prec) {
   if (cfg.rhs_chunk > 0) return std::min(cfg.rhs_chunk, nrhs);
   if (prec == 32) ensure_x32(*this);
   int64_t per = 0;
-  per += std::max(x64->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
-                  x64->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
+  per += std::max(x64->transient_bytes(right_prog(64), 1, {P.r_dO1, P.r_dO2p}),
+                  x64->transient_bytes(left_prog(64), 1, {P.l_gt1, P.l_gt2p}));
   per = std::max(per, x64->transient_bytes(P.hvp, 1, {P.h_out1, P.h_out2p}));
   if (prec == 32)
-    per += std::max(x32->transient_bytes(P.right, 1, {P.r_dO1, P.r_dO2p}),
-                    x32->transient_bytes(P.left, 1, {P.l_gt1, P.l_gt2p}));
+    per += std::max(x32->transient_bytes(right_prog(32), 1, {P.r_dO1, P.r_dO2p}),
+                    x32->transient_bytes(left_prog(32), 1, {P.l_gt1, P.l_gt2p}));
   per += (int64_t)(2 * std::max(cfg.diis_size, 0) + 12) * n * 16;
   // both executors run within one solve: their batch storage all counts
   return fit_chunk(nrhs, per, x64.get(), x32.get(), true, prec == 32);
@@ -1088,11 +1132,11 @@ int Context::sigma_chunk(Side side, int nvec, int prec) {
   const bool r = side == Side::Right;
   const std::vector<int> keep = r ? std::vector<int>{P.r_dO1, P.r_dO2p} : std::vector<int>{P.l_gt1, P.l_gt2p};
   if (prec == 64) {
-    int64_t per = x64->transient_bytes(r ? P.right : P.left, 1, keep);
+    int64_t per = x64->transient_bytes(r ? right_prog(64) : left_prog(64), 1, keep);
     return fit_chunk(nvec, per, x64.get(), x32.get(), true, false);
   }
   ensure_x32(*this);
-  int64_t per = x32->transient_bytes(r ? P.right : P.left, 1, keep) + n * 8;
+  int64_t per = x32->transient_bytes(r ? right_prog(32) : left_prog(32), 1, keep) + n * 8;
   return fit_chunk(nvec, per, x64.get(), x32.get(), false, true);
 }
 

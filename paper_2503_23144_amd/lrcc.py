@@ -24,7 +24,8 @@ HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 SIDE_RESIDUAL, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 AMP_T, AMP_LAMBDA, AMP_X, AMP_Y, AMP_XMINUS = 0, 1, 2, 3, 4
-PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL, PROG_FX, PROG_FNSPP = range(9)
+(PROG_RESIDUAL, PROG_RIGHT, PROG_LEFT, PROG_XI, PROG_HVP, PROG_ETA0, PROG_GRADL, PROG_FX, PROG_FNSPP,
+ PROG_RING_SETUP, PROG_RIGHT_F, PROG_LEFT_F) = range(12)
 
 # torch ships its own libamdhip64.so.7; load it first so that torch (device
 # memory, streams) and this library share one HIP runtime in the process.
@@ -46,7 +47,7 @@ class Config(ctypes.Structure):
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("ladder_mode", ctypes.c_int), ("ladder_mode_fp64", ctypes.c_int),
-                ("memory_mode", ctypes.c_int)]
+                ("memory_mode", ctypes.c_int), ("ring_factored", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -133,7 +134,8 @@ def build_info() -> str:
 LADDER_FULL, LADDER_DIRECT, LADDER_TRIANGLE = 0, 1, 2
 
 
-def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", ladder_fp64=None, memory="auto"):
+def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", ladder_fp64=None, memory="auto",
+                    ring_factored=None):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
@@ -144,6 +146,7 @@ def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", l
     cfg.ladder_mode = modes[ladder]
     cfg.ladder_mode_fp64 = -1 if ladder_fp64 is None else modes[ladder_fp64]
     cfg.memory_mode = {"auto": 0, "resident": 1, "lean": 2}[memory]
+    cfg.ring_factored = -1 if ring_factored is None else int(bool(ring_factored))
     return int(lib.lrcc_workspace_bytes(ctypes.byref(cfg), o, v, naux, nrhs))
 
 
@@ -190,7 +193,8 @@ class Context:
     T, Lambda, X, Y solves of LR-CCSD."""
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
-                 verbose=0, autotune=True, graphs=None, ladder="full", ladder_fp64=None, memory="auto"):
+                 verbose=0, autotune=True, graphs=None, ladder="full", ladder_fp64=None, memory="auto",
+                 ring_factored=None):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
@@ -215,6 +219,8 @@ class Context:
         cfg.ladder_mode_fp64 = -1 if ladder_fp64 is None else modes[ladder_fp64]
         # "auto", "resident" (dense integral blocks) or "lean" (packed / formed on use)
         cfg.memory_mode = {"auto": 0, "resident": 1, "lean": 2}[memory]
+        # the dt1 part of the ring term through Z1, Z2 (None: automatic)
+        cfg.ring_factored = -1 if ring_factored is None else int(bool(ring_factored))
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:

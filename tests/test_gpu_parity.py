@@ -168,13 +168,17 @@ CASES = [("c1", 4, 16, 32, 8.0, 0), ("ragged", 3, 17, 11, 8.0, 5)]
 
 
 # ------------------------------------------------------------------ sigma parity
+@pytest.mark.parametrize("ring", [None, False])
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
-def test_residual_and_sigmas_match_oracle(name, o, v, naux, scale, seed):
-    """Omega(t), A X and lambda A at random (non-converged) complex t."""
+def test_residual_and_sigmas_match_oracle(name, o, v, naux, scale, seed, ring):
+    """Omega(t), A X and lambda A at random (non-converged) complex t, with
+    the ring's dt1 terms factored through Z1, Z2 (the default at these sizes)
+    and contracted directly; then at a second t (Z1, Z2 formed again)."""
     from oracle.response import left_sigma, right_sigma
+    print(f"sigmas {name} ring_factored={ring}", flush=True)
     inp = make_inputs(o, v, naux, seed=seed)
     inp.B = inp.B * scale
-    c = _ctx(inp)
+    c = _ctx(inp, ring_factored=ring)
     P = _oracle_problem(inp)
     rng = np.random.default_rng(seed + 100)
     n = P.lay.n
@@ -195,6 +199,15 @@ def test_residual_and_sigmas_match_oracle(name, o, v, naux, scale, seed):
     got32 = c.sigma("right", X, precision="mixed")
     ref64 = c.sigma("right", X)
     assert _relerr(got32, ref64) < 1e-5
+    # new amplitudes: every product follows them
+    t2 = _rand(rng, n, scale=0.05)
+    c.set_amplitudes(_lrcc().AMP_T, t2)
+    for side, fn in (("right", right_sigma), ("left", left_sigma)):
+        got, got32 = c.sigma(side, X[:2]), c.sigma(side, X[:2], precision="mixed")
+        for r in range(2):
+            ref = fn(P, torch.as_tensor(t2), torch.as_tensor(X[r])).resolve_conj().numpy()
+            assert _relerr(got[r], ref) < 1e-12, (side, r, "second t")
+            assert _relerr(got32[r], ref) < 1e-5, (side, r, "second t, FP32")
 
 
 # ------------------------------------------------------------------ full pipeline
@@ -551,16 +564,19 @@ def test_c2_matches_stored_oracle():
 
 
 # ------------------------------------------------------------------ stored oracle values, o=20 v=150
-def test_c3_matches_stored_oracle():
+@pytest.mark.parametrize("ring", [None, False])
+def test_c3_matches_stored_oracle(ring):
     """The benchmark workload (o=20, v=150, naux=300): Omega, A X and X A at
     the seeded probe vectors against stored oracle entries, with the probe in
     a batch of 48 right-hand sides (the benchmark's product shape), in FP64
-    and in mixed precision; and E_corr."""
+    and in mixed precision, with the ring's dt1 terms factored (the default)
+    and direct; and E_corr."""
     import os
     from paper_2503_23144_amd.synth import config_inputs, probe_vectors
+    print(f"c3 stored oracle ring_factored={ring}", flush=True)
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_c3.npz"))
     inp = config_inputs("c3")
-    c = _ctx(inp, tol=1e-11)
+    c = _ctx(inp, tol=1e-11, ring_factored=ring)
     t, X, idx = probe_vectors(c.n, int(ref["sig_seed"]))
     assert np.array_equal(idx, ref["sig_idx"])
     R = c.sigma("residual", t)
@@ -830,12 +846,23 @@ def test_workspace_pipeline_matches_default_allocation(precision):
     assert 0 < peak <= est
     assert _relerr(a, a_ref) < 1e-12
     print(f"workspace estimate {est} bytes, peak use {peak} ({peak / est:.2f})")
-    # too small: a clean LRCC_E_NOMEM, nothing taken from the device
+    # too small: a clean LRCC_E_NOMEM, nothing taken from the device (load_df
+    # stores B, which fits; the integral blocks are formed by the first solve)
     small = torch.empty(2 << 20, dtype=torch.uint8, device="cuda:0")
     c = lrcc.Context(precision=precision)
     c.set_workspace(small)
+    c.load_df(inp.o, inp.v, inp.B)
+    c.load_fock(inp.fock)
+    c.load_dipoles(inp.mu)
     with pytest.raises(lrcc.LrccError) as e:
-        c.load_df(inp.o, inp.v, inp.B)
+        c.solve_ground()
+    assert e.value.code == lrcc.E_NOMEM
+    c.close()
+    tiny = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    c = lrcc.Context(precision=precision)
+    c.set_workspace(tiny)
+    with pytest.raises(lrcc.LrccError) as e:
+        c.load_df(10, 60, np.zeros((120, 70, 70), dtype=np.complex128))  # B alone is 9.4 MB
     assert e.value.code == lrcc.E_NOMEM
     c.close()
     # order: the workspace comes before load_df

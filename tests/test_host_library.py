@@ -86,12 +86,13 @@ def test_argument_checks_come_before_any_device_work():
 
 def test_program_text_is_well_formed():
     lrcc = _lrcc()
-    for which in range(9):
+    for which in range(12):
         tensors, ops = parse(lrcc.program_text(which))
         assert ops, which
         for op in ops:
             assert op["out"] in tensors
     assert lrcc.lib.lrcc_program_text(99, None, 0) == -1
+    assert lrcc.lib.lrcc_program_text(12, None, 0) == -1
 
 
 def _batch(lay, vecs):
@@ -141,6 +142,29 @@ def test_derived_operation_lists_match_oracle(o, v, naux, seed):
     for r, g in enumerate(_cat(env, I, "L(t1)", "L(t2p)", nb)):
         ref = left_sigma(P, t, X[r]).resolve_conj().numpy()
         assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
+
+    # the factored ring terms: Z1, Z2 formed once from t, then the variants
+    _, setup = parse(lrcc.program_text(lrcc.PROG_RING_SETUP))
+    I.run(setup, env)
+    _, right_f = parse(lrcc.program_text(lrcc.PROG_RIGHT_F))
+    env[I.id("R(t1)")], env[I.id("R(t2p)")] = _batch(P.lay, X)
+    I.run(right_f, env)
+    for r, g in enumerate(_cat(env, I, "R(O1)", "R(O2p)", nb)):
+        ref = right_sigma(P, t, X[r]).resolve_conj().numpy()
+        assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
+    _, left_f = parse(lrcc.program_text(lrcc.PROG_LEFT_F))
+    env[I.id("L(O1)")], env[I.id("L(O2p)")] = _batch(P.lay, X)
+    I.run(left_f, env)
+    for r, g in enumerate(_cat(env, I, "L(t1)", "L(t2p)", nb)):
+        ref = left_sigma(P, t, X[r]).resolve_conj().numpy()
+        assert np.abs(g - ref).max() < 1e-12 * np.abs(ref).max()
+    # neither variant forms the tangent / adjoint of W_mbej (the o^3 v^3 ring
+    # contraction with it is what the via terms replace); the plain ones do
+    tens_all, _ = parse(lrcc.program_text(lrcc.PROG_LEFT_F))
+    nm = lambda k: tens_all[k]["name"] if k >= 0 else ""
+    for ops_f, ops_p, wname in ((right_f, right, "R(Wmbej)"), (left_f, left, "L(Wmbej)")):
+        assert not any(wname in (nm(op["a"]), nm(op["b"]), nm(op["out"])) for op in ops_f), wname
+        assert any(wname in (nm(op["a"]), nm(op["b"]), nm(op["out"])) for op in ops_p), wname
 
     _, e0 = parse(lrcc.program_text(lrcc.PROG_ETA0))
     I.run(e0, env)
@@ -264,12 +288,17 @@ def test_fnspp_projection_list_matches_oracle():
 def test_workspace_estimate_fits_largest_config_in_lean_layout():
     """The footprint estimate of the o=40, v=400 mixed pipeline with one
     right-hand side per batch in the lean layout (FP32 W as its triangle,
-    FP64 ladder rebuilt from the factors) fits one MI355X (288 GB); the
-    resident layout with both full W does not."""
+    FP64 ladder rebuilt from the factors) fits one MI355X (288 GB), with
+    and without the FP32 Z1 of the factored ring terms (20.5 GB, taken by
+    default at this size); the resident layout with both full W does not."""
     from paper_2503_23144_amd import lrcc
-    lean = lrcc.workspace_bytes(40, 400, 800, 1, precision="mixed", ladder="triangle", ladder_fp64="direct",
-                                memory="lean")
+    kw = dict(precision="mixed", ladder="triangle", ladder_fp64="direct", memory="lean")
+    lean = lrcc.workspace_bytes(40, 400, 800, 1, **kw)
+    plain = lrcc.workspace_bytes(40, 400, 800, 1, ring_factored=False, **kw)
+    both = lrcc.workspace_bytes(40, 400, 800, 1, ring_factored=True, **kw)
+    assert 20e9 < lean - plain < 25e9  # FP32 Z1 only: 1.1 x 40 * 400^3 * 8 bytes
+    assert 40e9 < both - lean < 50e9  # forced, the FP64 executor's Z1 as well (twice that)
     resident = lrcc.workspace_bytes(40, 400, 800, 1, precision="mixed", memory="resident")
-    assert 0 < lean < 250e9 < 288e9 < resident
+    assert 0 < plain < 250e9 and lean < 265e9 < 288e9 < resident
     # the plain FP64 solver with the rebuilt ladder fits as well
     assert lrcc.workspace_bytes(40, 400, 800, 1, precision="fp64", ladder="direct", memory="lean") < 250e9
