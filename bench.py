@@ -61,20 +61,25 @@ def gemm_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+TILE_NAMES = {0: "64x64", 1: "128x64", 2: "128x128", 3: "128x128x8w", 4: "128x32"}
+
+
+def measured_traffic(workload, tile=None):
     """HBM bytes per ladder launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, if it was taken for this workload and the GEMM source
-    has not changed since (else None)."""
-    import hashlib
+    WRITE_SIZE summary, if it was taken for this workload, for the tile the
+    ladder ran with (`tile`, 0..4, as lrcc_gemm_tuned_tile reports it) and the
+    GEMM source has not changed since (else None)."""
     import re
     name = {"c3": "ladder_o20_v150_hbm_traffic.md", "c5": "ladder_o40_v400_hbm_traffic.md"}.get(workload)
     path = os.path.join(ROOT, "profiles", name or "-")
     if name is None or not os.path.exists(path):
         return None
-    m = re.search(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_src_sha256_16=([0-9a-f]{16})", open(path).read())
-    if not m or gemm_source_hash() != m.group(3):
-        return None
-    return {"bytes_per_launch": int(m.group(1)), "tile": m.group(2), "source": os.path.relpath(path, ROOT)}
+    for m in re.finditer(r"traffic_bytes_per_launch=(\d+) tile=(\S+) gemm_src_sha256_16=([0-9a-f]{16})",
+                         open(path).read()):
+        if gemm_source_hash() != m.group(3) or (tile is not None and TILE_NAMES.get(tile) != m.group(2)):
+            continue
+        return {"bytes_per_launch": int(m.group(1)), "tile": m.group(2), "source": os.path.relpath(path, ROOT)}
+    return None
 
 
 def resident(inp):
@@ -779,7 +784,9 @@ def main_c5(args):
     gemm_ms, gemm_n, gemm_fl = sig["gemm"]
     ladder_avg_s = ladder_ms / 1e3 / max(ladder_n, 1)
     ladder_tf = ladder_fl / max(ladder_ms / 1e3, 1e-30) / 1e12
-    traffic = measured_traffic("c5")
+    po_, pv_ = inp.o * (inp.o - 1) // 2, inp.v * (inp.v - 1) // 2
+    ladder_tile = lrcc.gemm_tuned_tile("mixed", False, True, nb * po_, pv_, pv_, ladder=True)
+    traffic = measured_traffic("c5", ladder_tile)
     po, pv = inp.o * (inp.o - 1) // 2, inp.v * (inp.v - 1) // 2
     out = {
         "metric": METRIC, "value": value, "unit": "sigma evals/s", "n_gpus": 1, "steps": args.steps,
@@ -803,7 +810,7 @@ def main_c5(args):
                      "traffic_source": traffic,
                      "algorithmic_flops_per_launch": 6.0 * nb * po * pv * pv,
                      "kernel": "zgemm_kernel<float, false, true, 1, ...> (packed vvvv ladder, 3M)",
-                     "avg_launch_ms": 1e3 * ladder_avg_s, "launches": ladder_n},
+                     "tile": TILE_NAMES.get(ladder_tile), "avg_launch_ms": 1e3 * ladder_avg_s, "launches": ladder_n},
         "setup_s": sig["setup_s"],
     }
     if not args.no_fp64:
@@ -933,7 +940,9 @@ def main_full_pass(args):
     dt = time.perf_counter() - t0
     value = sig / dt
 
-    traffic = measured_traffic(args.workload)
+    po_, pv_ = cfg["o"] * (cfg["o"] - 1) // 2, cfg["v"] * (cfg["v"] - 1) // 2
+    ladder_tile = lrcc.gemm_tuned_tile("mixed", False, True, 3 * len(cfg["omegas"]) * po_, pv_, pv_, ladder=True)
+    traffic = measured_traffic(args.workload, ladder_tile)
     ladder_ms, ladder_n, ladder_fl = last["ladder"]
     gemm_ms, gemm_n, gemm_fl = last["gemm"]
     ladder_avg_s = ladder_ms / 1e3 / max(ladder_n, 1)

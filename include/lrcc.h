@@ -277,6 +277,13 @@ int lrcc_gemm_noalloc(int precision, int transa, int transb, int64_t m, int64_t 
    Products split over K ignore it.  Returns LRCC_E_INVALID outside -1..4.
    The environment variable LRCC_GEMM_TILE gives the initial value. */
 int lrcc_gemm_set_tile(int tile);
+/* Tile (0..4 as above) the autotuner chose in this process for the product
+   shape (precision LRCC_FP64 or LRCC_MIXED, op(A) m x k, op(B) k x n; ladder
+   = 1 for the packed-vvvv ladder contraction of the Jacobian products, which
+   runs its own kernel variant), or -1 if that shape has not been timed.  For
+   profiles: it names the kernel a trace's or a counter's figures belong to.
+   Near-ties (within 2 %) keep the size heuristic's tile. */
+int lrcc_gemm_tuned_tile(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k, int ladder);
 
 /* Text of the derived operation lists (host-only, no GPU needed):
    which = 0 residual, 1 right sigma, 2 left sigma, 3 xi, 4 tangent of grad L

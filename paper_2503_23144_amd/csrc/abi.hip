@@ -408,6 +408,11 @@ int lrcc_gemm_set_tile(int tile) {
   return LRCC_OK;
 }
 
+int lrcc_gemm_tuned_tile(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k, int ladder) {
+  if ((precision != LRCC_FP64 && precision != LRCC_MIXED) || m < 1 || n < 1 || k < 1) return -1;
+  return lrcc::gemm_tuned_tile(precision == LRCC_FP64 ? 64 : 32, transa != 0, transb != 0, ladder ? 1 : 0, m, n, k);
+}
+
 int64_t lrcc_program_text(int which, char* buf, int64_t cap) {
   try {
     static lrcc::CcPrograms P = [] {

@@ -130,6 +130,8 @@ size_t gemm_workspace_bytes(int64_t m, int64_t n, int64_t k);
 void set_gemm_autotune(bool on);
 void set_gemm_tile(int tile);  // -1: automatic (autotuner or size heuristic)
 int gemm_tuned_shapes();
+// Tile the autotuner chose for a shape (kind 1: the ladder kernel), or -1.
+int gemm_tuned_tile(int prec, bool ta, bool tb, int kind, int64_t m, int64_t n, int64_t k);
 
 // Solver kernels (FP64 vectors, nvec right-hand sides of length n).
 // R = sig + (D + s_r) X + b_r  (sig in Ts; D, shift, X, b may be null = 0).

@@ -82,6 +82,7 @@ _sig = {
     "lrcc_gemm": (_i, [_i, _i, _i, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp]),
     "lrcc_gemm_noalloc": (_i, [_i, _i, _i, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp]),
     "lrcc_gemm_set_tile": (_i, [_i]),
+    "lrcc_gemm_tuned_tile": (_i, [_i, _i, _i, _i64, _i64, _i64, _i]),
     "lrcc_program_text": (_i64, [_i, ctypes.c_char_p, _i64]),
     "lrcc_kernel_time": (_i, [_vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "lrcc_set_timing": (_i, [_vp, _i]),
@@ -178,6 +179,13 @@ def gemm(A, B, C, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None, 
     if rc != OK:
         raise LrccError(rc, lib.lrcc_last_error(None).decode())
     return C
+
+
+def gemm_tuned_tile(precision, ta, tb, m, n, k, ladder=False):
+    """Tile the autotuner chose for a product shape in this process (-1: not
+    timed); see lrcc_gemm_tuned_tile."""
+    return int(lib.lrcc_gemm_tuned_tile({"fp64": FP64, "mixed": MIXED}[precision], int(ta), int(tb), m, n, k,
+                                        int(ladder)))
 
 
 def gemm_set_tile(tile):
