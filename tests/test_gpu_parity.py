@@ -211,14 +211,18 @@ def test_residual_and_sigmas_match_oracle(name, o, v, naux, scale, seed, ring):
 
 
 # ------------------------------------------------------------------ full pipeline
+@pytest.mark.parametrize("ring", [None, False])
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
-def test_polarizability_fp64_matches_oracle(name, o, v, naux, scale, seed):
+def test_polarizability_fp64_matches_oracle(name, o, v, naux, scale, seed, ring):
+    """T, Lambda, X, Y and alpha against the oracle, with the ring's dt1
+    terms factored (the default at these sizes) and direct."""
     from oracle.response import lr_ccsd
+    print(f"alpha {name} ring_factored={ring}", flush=True)
     inp = make_inputs(o, v, naux, seed=seed)
     inp.B = inp.B * scale
     omegas = [0.0, 0.11]
     ref = lr_ccsd(inp.B, inp.fock, inp.mu, o, omegas, tol=1e-13)
-    c = _ctx(inp, tol=1e-11)
+    c = _ctx(inp, tol=1e-11, ring_factored=ring)
     e, st = c.solve_ground()
     assert st["converged"] == 1
     assert abs(e - ref.ecorr) < 1e-10 * abs(ref.ecorr)
