@@ -79,7 +79,8 @@ typedef struct lrcc_config {
   int diis_size;         /* DIIS subspace per right-hand side (default 8, 0 = plain Jacobi) */
   int rhs_chunk;         /* right-hand sides per batched Jacobian product (0 = all) */
   int autotune;          /* 1: time the candidate GEMM tiles of each new shape once and keep the
-                            fastest (process-wide; cache file from LRCC_AUTOTUNE_CACHE); default 1 */
+                            fastest (process-wide, per bucket of nearby shapes; cache file from
+                            LRCC_AUTOTUNE_CACHE); default 1 */
   int verbose;           /* 0 silent, 1 per-solve summary, 2 per-iteration lines on stderr */
   int graphs;            /* 1: replay the Jacobian-product programs as HIP graphs (captured on the
                             second identical call, replayed from the third); default 1, or 0 when
@@ -282,7 +283,9 @@ int lrcc_gemm_set_tile(int tile);
    = 1 for the packed-vvvv ladder contraction of the Jacobian products, which
    runs its own kernel variant), or -1 if that shape has not been timed.  For
    profiles: it names the kernel a trace's or a counter's figures belong to.
-   Near-ties (within 2 %) keep the size heuristic's tile. */
+   Shapes are timed per bucket (m, n, k above 64 rounded down to their top
+   three bits, about 25 % wide), so the answer covers every shape of the
+   bucket.  Near-ties (within 2 %) keep the size heuristic's tile. */
 int lrcc_gemm_tuned_tile(int precision, int transa, int transb, int64_t m, int64_t n, int64_t k, int ladder);
 
 /* Text of the derived operation lists (host-only, no GPU needed):

@@ -448,7 +448,8 @@ static void go(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, do
 // The autotuner times every candidate once per GEMM shape (into a scratch
 // output, so accumulating calls are not disturbed) and keeps the fastest;
 // without it a size heuristic decides.  Results can persist in a text cache
-// named by LRCC_AUTOTUNE_CACHE ("gfx950 prec ta tb kind m n k tile" lines).
+// named by LRCC_AUTOTUNE_CACHE ("gfx950 prec ta tb kind m n k tile" lines,
+// m n k bucketed as below).
 
 template <typename T, int KIND>
 static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, double aim,
@@ -472,6 +473,17 @@ static void dispatch(int cfgid, bool ta, bool tb, int64_t m, int64_t n, int64_t 
 }
 
 namespace {
+// Shapes are tuned per bucket: each of m, n, k above 64 is rounded down to
+// its top three bits (four buckets per octave), so products within about
+// 25 % of each other in every dimension share one choice.  Chunked
+// contractions (the DF-direct ladder's row chunks, split virtual operands)
+// produce hundreds of nearby shapes that would otherwise each be timed.
+int64_t tune_bucket(int64_t x) {
+  if (x <= 64) return x;
+  int e = 63 - __builtin_clzll((unsigned long long)x);
+  return (x >> (e - 2)) << (e - 2);
+}
+
 struct TuneKey {
   int prec, ta, tb, kind;
   int64_t m, n, k;
@@ -518,7 +530,7 @@ void set_gemm_autotune(bool on) {
 
 int gemm_tuned_tile(int prec, bool ta, bool tb, int kind, int64_t m, int64_t n, int64_t k) {
   std::lock_guard<std::mutex> g(g_tune_mu);
-  auto it = g_tune.find(TuneKey{prec, ta, tb, kind, m, n, k});
+  auto it = g_tune.find(TuneKey{prec, ta, tb, kind, tune_bucket(m), tune_bucket(n), tune_bucket(k)});
   return it == g_tune.end() ? -1 : it->second;
 }
 
@@ -651,7 +663,7 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (st && hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
   const bool capturing = cap != hipStreamCaptureStatusNone;
-  TuneKey key{sizeof(T) == 8 ? 64 : 32, ta, tb, kind, m, n, k};
+  TuneKey key{sizeof(T) == 8 ? 64 : 32, ta, tb, kind, tune_bucket(m), tune_bucket(n), tune_bucket(k)};
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     if (g_autotune) {
@@ -678,12 +690,13 @@ void launch_gemm(bool ta, bool tb, int64_t m, int64_t n, int64_t k, double are, 
     for (int ci = 0; ci < ncand; ++ci) {
       const int c = cand[ci];
       float ms = 0;
-      for (int rep = 0; rep < 2; ++rep) {
+      for (int rep = 0; rep < 2; ++rep) {  // a second, warm timing unless the first took long
         HIP_CHECK(hipEventRecord(e0, st));
         run(c, scratch, 0.0, 0.0, true);
         HIP_CHECK(hipEventRecord(e1, st));
         HIP_CHECK(hipEventSynchronize(e1));
         HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms > 50.0f) break;
       }
       if (c == heur) heur_ms = ms;
       if (ms < best) {
