@@ -149,6 +149,39 @@ def test_gemm_tile_choice_rejects_bad_values():
     lrcc.gemm_set_tile(-1)
 
 
+def test_autotuned_tile_is_shared_by_a_shape_bucket():
+    """The autotuner (on once a context enables it) times a new product
+    shape and keeps one tile for its bucket (m, n, k rounded down to their
+    top three bits): a nearby shape reports the same tile and computes the
+    same product; a shape in another bucket has not been timed."""
+    lrcc = _lrcc()
+    c = lrcc.Context(precision="mixed", autotune=True)  # enables the process-wide autotuner
+    rng = np.random.default_rng(3)
+    dev = torch.device("cuda:0")
+
+    def product(m, n, k):
+        A = torch.tensor(rng.standard_normal((m, k)) + 1j * rng.standard_normal((m, k)), dtype=torch.complex64,
+                         device=dev)
+        B = torch.tensor(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)), dtype=torch.complex64,
+                         device=dev)
+        C = torch.empty((m, n), dtype=torch.complex64, device=dev)
+        lrcc.gemm(A, B, C, transb=True)
+        torch.cuda.synchronize()
+        rows = [0, m // 2, m - 1]  # sampled rows against a host product
+        ref = A[rows].cpu().to(torch.complex128) @ B.cpu().to(torch.complex128).T
+        assert _relerr(C[rows].cpu().numpy(), ref.numpy()) < 1e-5
+
+    product(1233, 5000, 700)  # 4.3e9 MNK: timed
+    t = lrcc.gemm_tuned_tile("mixed", 0, 1, 1233, 5000, 700)
+    assert 0 <= t <= 4
+    assert lrcc.gemm_tuned_tile("mixed", 0, 1, 1100, 4500, 650) == t  # same buckets (1024, 4096, 640)
+    product(1100, 4500, 650)
+    assert lrcc.gemm_tuned_tile("mixed", 0, 1, 1700, 4500, 650) == -1  # m in the next bucket (1536)
+    assert lrcc.gemm_tuned_tile("fp64", 0, 1, 1233, 5000, 700) == -1  # per precision
+    assert lrcc.gemm_tuned_tile("mixed", 0, 1, 1233, 5000, 700, ladder=True) == -1  # the ladder's own kernel
+    c.close()
+
+
 # ------------------------------------------------------------------ helpers
 def _ctx(inp, precision="fp64", tol=1e-11, **kw):
     lrcc = _lrcc()

@@ -95,6 +95,15 @@ def test_program_text_is_well_formed():
     assert lrcc.lib.lrcc_program_text(12, None, 0) == -1
 
 
+def test_tuned_tile_query_without_a_gpu():
+    """lrcc_gemm_tuned_tile is a host lookup: -1 for shapes never timed and
+    for invalid arguments."""
+    lrcc = _lrcc()
+    assert lrcc.gemm_tuned_tile("mixed", 0, 1, 3120, 79800, 79800, ladder=True) == -1
+    assert lrcc.lib.lrcc_gemm_tuned_tile(7, 0, 1, 10, 10, 10, 0) == -1
+    assert lrcc.lib.lrcc_gemm_tuned_tile(lrcc.FP64, 0, 1, 0, 10, 10, 0) == -1
+
+
 def _batch(lay, vecs):
     return (np.stack([lay.split(x)[0].numpy() for x in vecs]), np.stack([lay.split(x)[1].numpy() for x in vecs]))
 
