@@ -311,3 +311,20 @@ def test_workspace_estimate_fits_largest_config_in_lean_layout():
     assert 0 < plain < 250e9 and lean < 265e9 < 288e9 < resident
     # the plain FP64 solver with the rebuilt ladder fits as well
     assert lrcc.workspace_bytes(40, 400, 800, 1, precision="fp64", ladder="direct", memory="lean") < 250e9
+
+
+def test_bench_uncoupled_alpha_matches_oracle():
+    """The bench's independent-particle alpha (the reference of its
+    correlated-part error figures) is the oracle's, at two frequencies."""
+    import importlib.util
+    import os
+
+    from oracle.response import alpha_uncoupled
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    inp = make_inputs(3, 7, 5, seed=2)
+    got = bench.alpha_uncoupled_ref(inp.fock, inp.mu, inp.o, [0.0, 0.13])
+    for k, w in enumerate((0.0, 0.13)):
+        ref = alpha_uncoupled(inp.fock, inp.mu, inp.o, w)
+        assert np.abs(got[k] - ref).max() < 1e-14 * np.abs(ref).max()
