@@ -114,6 +114,12 @@ typedef struct lrcc_config {
                             contraction of t2 with dW per right-hand side; -1 (default) 1 for each
                             executor whose Z1 takes at most 24 GiB at its precision, else 0.
                             Results agree to rounding. */
+  int keep_response;     /* 1 (default): the X and Y (or X(w), X(-w)) of every right-hand side stay on
+                            the device for lrcc_get_amplitudes; 0: the frequencies are solved in
+                            groups (as many as one batched product holds, at least one), alpha of
+                            a group is formed before the next group reuses the storage, and only
+                            the last group's amplitudes can be read: memory then does not grow
+                            with the number of frequencies.  alpha is the same either way. */
 } lrcc_config;
 
 #define LRCC_LADDER_FULL 0

@@ -85,6 +85,7 @@ void lrcc_default_config(lrcc_config* cfg) {
   cfg->ladder_mode_fp64 = -1;
   cfg->memory_mode = LRCC_MEMORY_AUTO;
   cfg->ring_factored = -1;
+  cfg->keep_response = 1;
 }
 
 int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
@@ -102,6 +103,7 @@ int lrcc_create(lrcc_ctx** out, const lrcc_config* cfg) {
     LRCC_REQUIRE(c.memory_mode >= LRCC_MEMORY_AUTO && c.memory_mode <= LRCC_MEMORY_LEAN, LRCC_E_INVALID,
                  "bad memory_mode");
     LRCC_REQUIRE(c.ring_factored >= -1 && c.ring_factored <= 1, LRCC_E_INVALID, "bad ring_factored");
+    LRCC_REQUIRE(c.keep_response == 0 || c.keep_response == 1, LRCC_E_INVALID, "bad keep_response");
     LRCC_REQUIRE(c.tol_residual > 0 && c.maxit > 0 && c.diis_size >= 0 && c.diis_size <= 32 && c.rhs_chunk >= 0,
                  LRCC_E_INVALID, "bad tolerance, iteration limit, DIIS size or chunk");
     int ndev = 0;
@@ -332,7 +334,10 @@ int lrcc_get_amplitudes(lrcc_ctx* ctx, int which, int idx, void* out, int where)
                    "no X(-w) amplitudes (the last response solve took the Eq. 35 route)");
       int nr = (int)c.omegas.size() * c.ncomp;
       LRCC_REQUIRE(idx >= 0 && idx < nr, LRCC_E_INVALID, "bad right-hand-side index");
-      src = (const char*)(which == LRCC_AMP_X ? c.X.p : c.Y.p) + idx * vb;
+      LRCC_REQUIRE(idx >= c.resp_first && idx < c.resp_first + c.resp_count, LRCC_E_STATE,
+                   "amplitudes of right-hand side " + std::to_string(idx) +
+                       " were not kept (lrcc_config.keep_response = 0 keeps the last frequency group only)");
+      src = (const char*)(which == LRCC_AMP_X ? c.X.p : c.Y.p) + (size_t)(idx - c.resp_first) * vb;
     }
     copy_out(out, src, vb, where, c.st);
   });

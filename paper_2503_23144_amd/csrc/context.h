@@ -131,6 +131,10 @@ struct Context {
   void mp2_response(int nw, const double* om, cplx& emp2, std::vector<cplx>& al);
   void hbar_diagonals(std::vector<double>& Hii, std::vector<double>& Haa);
   int response_route = 0;  // 35: X and Y (Eq. 35); 36: X(w) and X(-w) (Eq. 36, X(-w) in Y)
+  // X and Y hold the right-hand sides [resp_first, resp_first + resp_count)
+  // of the last response solve (all of them unless cfg.keep_response = 0)
+  int resp_first = 0, resp_count = 0;
+  void response_alpha(int nw, int chunk, bool quadratic, int prec, std::vector<cplx>& out);
 
   // ---- Jacobian products on device FP64 vectors [nb][n] (in/out may alias no)
   void residual64(const void* tvec, void* R, cplx* E);

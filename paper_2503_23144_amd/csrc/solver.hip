@@ -1174,80 +1174,64 @@ void Context::solve_response(int nw, const double* om, std::vector<SolveStats>& 
     x64->release_results(P.gradL);
     gradL_ready = 0;
   }
-  X.ensure(nrhs * vb);
-  Y.ensure(nrhs * vb);
   have_alpha = false;
   response_route = quadratic ? 36 : 35;
   per.assign(2 * nrhs, SolveStats());
   const int chunk = rhs_chunk_for(nrhs, prec);
-  if (cfg.verbose >= 1) fprintf(stderr, "[lrcc] response: %d right-hand sides in chunks of %d\n", nrhs, chunk);
+  // Frequency groups: all frequencies at once, or (lrcc_config.keep_response
+  // = 0) as many as one batched product holds, each group's alpha formed
+  // before the next group's amplitudes overwrite X and Y
+  const int gw = cfg.keep_response ? nw : std::max(1, chunk / ncomp);
+  const int gmax = std::min(gw, nw) * ncomp;
+  X.ensure(gmax * vb);
+  Y.ensure(gmax * vb);
+  if (cfg.verbose >= 1)
+    fprintf(stderr, "[lrcc] response: %d right-hand sides in chunks of %d, frequencies in groups of %d\n", nrhs, chunk,
+            std::min(gw, nw));
   DevBuf bc, shd;
-  bc.ensure(chunk * vb);
   shd.ensure(chunk * 8);
-  for (int side = 0; side < 2; ++side) {
-    for (int c0 = 0; c0 < nrhs; c0 += chunk) {
-      int nc = std::min(chunk, nrhs - c0);
-      std::vector<double> sh(nc);
-      std::vector<int> cp(nc);
-      for (int q = 0; q < nc; ++q) {
-        int r = c0 + q;
-        cp[q] = r % ncomp;
-        sh[q] = side == 0 ? -omegas[r / ncomp] : omegas[r / ncomp];
-      }
-      void* xc = (char*)(side == 0 ? X.p : Y.p) + c0 * vb;
-      if (side == 0 || quadratic) {
-        for (int q = 0; q < nc; ++q)
-          HIP_CHECK(hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
-      } else {
-        eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, bc.p, prec, eta.p);
-      }
-      HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
-      launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);
-      std::vector<SolveStats> ss;
-      const Side sd = (side == 0 || quadratic) ? Side::Right : Side::Left;
-      solve_linear(sd, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
-      for (int q = 0; q < nc; ++q) per[side * nrhs + c0 + q] = ss[q];
-      if (cfg.verbose >= 1) {
-        int itmax = 0;
-        for (auto& t : ss) itmax = std::max(itmax, t.iterations);
-        fprintf(stderr, "[lrcc] %s right-hand sides %d..%d of %d: up to %d iterations\n", side == 0 ? "X" : "Y", c0,
-                c0 + nc - 1, nrhs, itmax);
-      }
-    }
-  }
-  // alpha_AB(w) = -1/2 [f_AB + conj f_BA],  f_AB = Y^B . xi^A + eta^A . X^B
-  if (quadratic) {
-    bc.release();
-    alpha_quadratic(nw, chunk, X.p, Y.p, eta.p, prec, alpha);
-  } else {
-    DevBuf d1, d2, w;
-    d1.ensure(nrhs * 16);
-    d2.ensure(nrhs * 16);
-    w.ensure((size_t)nrhs * 1024 * 16);
-    std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
-    for (int a = 0; a < ncomp; ++a) {
-      launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
-      std::vector<cplx> h(nrhs);
-      HIP_CHECK(hipMemcpyAsync(h.data(), d1.p, nrhs * 16, hipMemcpyDeviceToHost, st));
-      sync();
-      for (int r = 0; r < nrhs; ++r) fy[r * ncomp + a] = h[r];
-      launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, d2.p, w.p, st);
-      HIP_CHECK(hipMemcpyAsync(h.data(), d2.p, nrhs * 16, hipMemcpyDeviceToHost, st));
-      sync();
-      for (int r = 0; r < nrhs; ++r) fx[r * ncomp + a] = h[r];
-    }
-    alpha.assign(nw * ncomp * ncomp, 0.0);
-    for (int k = 0; k < nw; ++k) {
-      std::vector<cplx> f(ncomp * ncomp);
-      for (int a = 0; a < ncomp; ++a)
-        for (int bb = 0; bb < ncomp; ++bb) {
-          int r = k * ncomp + bb;
-          f[a * ncomp + bb] = fy[r * ncomp + a] + fx[r * ncomp + a];
+  alpha.assign(nw * ncomp * ncomp, 0.0);
+  for (int k0 = 0; k0 < nw; k0 += gw) {
+    const int k1 = std::min(nw, k0 + gw), ng = (k1 - k0) * ncomp, r0 = k0 * ncomp;
+    bc.ensure(std::min(chunk, gmax) * vb);
+    for (int side = 0; side < 2; ++side) {
+      for (int c0 = 0; c0 < ng; c0 += chunk) {
+        int nc = std::min(chunk, ng - c0);
+        std::vector<double> sh(nc);
+        std::vector<int> cp(nc);
+        for (int q = 0; q < nc; ++q) {
+          int r = r0 + c0 + q;
+          cp[q] = r % ncomp;
+          sh[q] = side == 0 ? -omegas[r / ncomp] : omegas[r / ncomp];
         }
-      for (int a = 0; a < ncomp; ++a)
-        for (int bb = 0; bb < ncomp; ++bb)
-          alpha[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
+        void* xc = (char*)(side == 0 ? X.p : Y.p) + c0 * vb;
+        if (side == 0 || quadratic) {
+          for (int q = 0; q < nc; ++q)
+            HIP_CHECK(
+                hipMemcpyAsync((char*)bc.p + q * vb, (char*)xi.p + cp[q] * vb, vb, hipMemcpyDeviceToDevice, st));
+        } else {
+          eta_plus_fx(nc, cp.data(), (char*)X.p + c0 * vb, bc.p, prec, eta.p);
+        }
+        HIP_CHECK(hipMemcpyAsync(shd.p, sh.data(), nc * 8, hipMemcpyHostToDevice, st));
+        launch_jacobi(nc, n, D.as<double>(), shd.as<double>(), nullptr, bc.p, xc, nullptr, st);
+        std::vector<SolveStats> ss;
+        const Side sd = (side == 0 || quadratic) ? Side::Right : Side::Left;
+        solve_linear(sd, nc, sh.data(), bc.p, xc, prec, cfg.tol_residual, ss);
+        for (int q = 0; q < nc; ++q) per[side * nrhs + r0 + c0 + q] = ss[q];
+        if (cfg.verbose >= 1) {
+          int itmax = 0;
+          for (auto& t : ss) itmax = std::max(itmax, t.iterations);
+          fprintf(stderr, "[lrcc] %s right-hand sides %d..%d of %d: up to %d iterations\n", side == 0 ? "X" : "Y",
+                  r0 + c0, r0 + c0 + nc - 1, nrhs, itmax);
+        }
+      }
     }
+    std::vector<cplx> ag;
+    if (quadratic) bc.release();  // room for the F X^B(w) of Eq. 36
+    response_alpha(k1 - k0, chunk, quadratic, prec, ag);
+    std::copy(ag.begin(), ag.end(), alpha.begin() + (size_t)k0 * ncomp * ncomp);
+    resp_first = r0;
+    resp_count = ng;
   }
   have_alpha = true;
   bool all = true;
@@ -1277,6 +1261,46 @@ void Context::eta_plus_fx(int nb, const int* comp, const void* Xs, void* out, in
 //   f_AB(-w) = eta^B.X^A(w) + X^B(-w).H^A.
 // H is built in chunks of right-hand sides; the bilinear dots run on the
 // device.
+// alpha of the nw frequencies whose amplitudes X and Y hold (from their
+// start): Eq. 35, alpha_AB(w) = -1/2 [f_AB + conj f_BA] with f_AB = Y^B . xi^A
+// + eta^A . X^B, or Eq. 36 (quadratic: Y holds X(-w)).
+void Context::response_alpha(int nw, int chunk, bool quadratic, int prec, std::vector<cplx>& out) {
+  if (quadratic) {
+    alpha_quadratic(nw, chunk, X.p, Y.p, eta.p, prec, out);
+    return;
+  }
+  const size_t vb = n * 16;
+  const int nrhs = nw * ncomp;
+  DevBuf d1, d2, w;
+  d1.ensure(nrhs * 16);
+  d2.ensure(nrhs * 16);
+  w.ensure((size_t)nrhs * 1024 * 16);
+  std::vector<cplx> fy(nrhs * ncomp), fx(nrhs * ncomp);
+  for (int a = 0; a < ncomp; ++a) {
+    launch_batched_dot<double>(nrhs, n, Y.p, n, (char*)xi.p + a * vb, 0, false, d1.p, w.p, st);
+    std::vector<cplx> h(nrhs);
+    HIP_CHECK(hipMemcpyAsync(h.data(), d1.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int r = 0; r < nrhs; ++r) fy[r * ncomp + a] = h[r];
+    launch_batched_dot<double>(nrhs, n, X.p, n, (char*)eta.p + a * vb, 0, false, d2.p, w.p, st);
+    HIP_CHECK(hipMemcpyAsync(h.data(), d2.p, nrhs * 16, hipMemcpyDeviceToHost, st));
+    sync();
+    for (int r = 0; r < nrhs; ++r) fx[r * ncomp + a] = h[r];
+  }
+  out.assign(nw * ncomp * ncomp, 0.0);
+  for (int k = 0; k < nw; ++k) {
+    std::vector<cplx> f(ncomp * ncomp);
+    for (int a = 0; a < ncomp; ++a)
+      for (int bb = 0; bb < ncomp; ++bb) {
+        int r = k * ncomp + bb;
+        f[a * ncomp + bb] = fy[r * ncomp + a] + fx[r * ncomp + a];
+      }
+    for (int a = 0; a < ncomp; ++a)
+      for (int bb = 0; bb < ncomp; ++bb)
+        out[(k * ncomp + a) * ncomp + bb] = -0.5 * (f[a * ncomp + bb] + std::conj(f[bb * ncomp + a]));
+  }
+}
+
 void Context::alpha_quadratic(int nw, int chunk, const void* Xp, const void* Xm, const void* etaB, int prec,
                               std::vector<cplx>& out) {
   const size_t vb = n * 16;

@@ -47,7 +47,7 @@ class Config(ctypes.Structure):
                 ("tol_residual", ctypes.c_double), ("maxit", ctypes.c_int), ("diis_size", ctypes.c_int),
                 ("rhs_chunk", ctypes.c_int), ("autotune", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("ladder_mode", ctypes.c_int), ("ladder_mode_fp64", ctypes.c_int),
-                ("memory_mode", ctypes.c_int), ("ring_factored", ctypes.c_int)]
+                ("memory_mode", ctypes.c_int), ("ring_factored", ctypes.c_int), ("keep_response", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -136,7 +136,7 @@ LADDER_FULL, LADDER_DIRECT, LADDER_TRIANGLE = 0, 1, 2
 
 
 def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", ladder_fp64=None, memory="auto",
-                    ring_factored=None):
+                    ring_factored=None, keep_response=True):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
@@ -229,6 +229,8 @@ class Context:
         cfg.memory_mode = {"auto": 0, "resident": 1, "lean": 2}[memory]
         # the dt1 part of the ring term through Z1, Z2 (None: automatic)
         cfg.ring_factored = -1 if ring_factored is None else int(bool(ring_factored))
+        # False: alpha per frequency group, only the last group's X and Y kept
+        cfg.keep_response = int(bool(keep_response))
         h = _vp()
         rc = lib.lrcc_create(ctypes.byref(h), ctypes.byref(cfg))
         if rc != OK:

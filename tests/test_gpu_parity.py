@@ -350,6 +350,43 @@ def test_uneven_convergence_in_chunks_matches_single_solves(precision):
     assert _relerr(a2, a1) < 1e-9
 
 
+# ------------------------------------------------------------------ frequency groups
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("quadratic", [False, True])
+def test_frequency_groups_give_the_same_alpha(precision, quadratic):
+    """keep_response=False solves the frequencies in groups (here one
+    frequency, three right-hand sides, per group) and forms alpha group by
+    group: alpha equals the all-at-once solve with the same chunks and the
+    oracle; the last group's amplitudes are readable, earlier ones are not."""
+    from oracle.response import lr_ccsd
+    lrcc = _lrcc()
+    print(f"frequency groups {precision} quadratic={quadratic}", flush=True)
+    inp = make_inputs(3, 17, 11, seed=5)
+    inp.B = inp.B * 8.0
+    omegas = [0.0, 0.07, 0.13]
+    tol = 1e-11 if precision == "fp64" else 1e-9
+    res = []
+    for keep in (True, False):
+        c = _ctx(inp, precision=precision, tol=tol, rhs_chunk=3, keep_response=keep)
+        c.solve_ground()
+        c.solve_lambda()
+        per = c.solve_response(omegas, quadratic=quadratic)
+        assert len(per) == 18 and all(s["converged"] for s in per)
+        last = [c.get_amplitudes(lrcc.AMP_X, r) for r in (6, 8)]
+        if not keep:
+            with pytest.raises(lrcc.LrccError) as e:
+                c.get_amplitudes(lrcc.AMP_X, 2)
+            assert e.value.code == lrcc.E_STATE
+        res.append((c.alpha(len(omegas)), last, [s["iterations"] for s in per]))
+        c.close()
+    assert _relerr(res[1][0], res[0][0]) < 1e-13
+    for a, b in zip(res[1][1], res[0][1]):
+        assert _relerr(a, b) < 1e-13
+    assert res[1][2] == res[0][2]
+    ref = lr_ccsd(inp.B, inp.fock, inp.mu, inp.o, omegas, tol=1e-13)
+    assert _relerr(res[1][0], ref.alpha) < (1e-8 if precision == "fp64" else 1e-6)
+
+
 # ------------------------------------------------------------------ Eq. 36 route
 @pytest.mark.parametrize("name,o,v,naux,scale,seed", CASES)
 def test_quadratic_route_matches_oracle_eq36(name, o, v, naux, scale, seed):
