@@ -424,9 +424,9 @@ def cpu_baseline(inp, budget_s=25.0):
                       f"integral build excluded ({dt:.1f} s)"}
 
 
-def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0, ring=None):
+def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0, ring=None, keep=True):
     c = lrcc.Context(precision=precision, tol=tol, ladder=ladder, ladder_fp64=ladder_fp64, memory="lean",
-                     rhs_chunk=chunk, ring_factored=ring)
+                     rhs_chunk=chunk, ring_factored=ring, keep_response=keep, verbose=1 if not keep else 0)
     c.load_df(inp.o, inp.v, dev_in["B"])
     c.load_fock(dev_in["fock"])
     c.load_dipoles(dev_in["mu"])
@@ -533,7 +533,7 @@ def fp64_plain_leg(lrcc, inp, dev_in, t, X0, reps=3):
             ladder[0] / max(ladder[1], 1), "adjoint_identity_rel": abs(lhs - rhs) / abs(lhs), "row0_fp64": r64}
 
 
-def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6):
+def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6, keep_response=True, eq36=True):
     """A full T -> Lambda -> X, Y -> alpha solve at full size in mixed
     precision on a subset of the frequencies (one right-hand side per
     product: the FP32 W as its Hermitian triangle, the FP64 ladder rebuilt,
@@ -543,7 +543,8 @@ def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6):
     out = {"omegas": list(omegas), "tol_residual": tol, "ladder": "FP32 triangle, FP64 rebuilt from the factors",
            "rhs_per_product": 1}
     t0 = time.perf_counter()
-    c = _c5_context(lrcc, inp, dev_in, "mixed", "triangle", "direct", tol=tol, chunk=1)
+    c = _c5_context(lrcc, inp, dev_in, "mixed", "triangle", "direct", tol=tol, chunk=1, keep=keep_response)
+    out["keep_response"] = keep_response
     out["integrals_s"] = time.perf_counter() - t0
     t = time.perf_counter()
     e, st0 = c.solve_ground()
@@ -559,20 +560,25 @@ def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6):
                        "converged": bool(all(p["converged"] for p in per))}
     a35 = c.alpha(len(omegas))
     print(f"[bench] c5 solve: response {out['response']}", file=sys.stderr, flush=True)
-    t = time.perf_counter()
-    per = c.solve_response(omegas, quadratic=True)
-    out["eq36"] = {"seconds": time.perf_counter() - t, "converged": bool(all(p["converged"] for p in per))}
-    a36 = c.alpha(len(omegas))
+    a36 = None
+    if eq36:
+        t = time.perf_counter()
+        per = c.solve_response(omegas, quadratic=True)
+        out["eq36"] = {"seconds": time.perf_counter() - t, "converged": bool(all(p["converged"] for p in per))}
+        a36 = c.alpha(len(omegas))
     c.close()
     lrcc.trim_memory()
     torch.cuda.empty_cache()
     out["alpha_iso"] = [float(x) for x in np.real(np.trace(a35, axis1=-2, axis2=-1)) / 3.0]
     out["alpha"] = [[[complex(z).real, complex(z).imag] for z in row] for row in np.asarray(a35[0])]
-    out["alpha_rel_diff_eq36_vs_eq35"] = float(np.abs(a36 - a35).max() / np.abs(a35).max())
-    out["alpha_rel_diff_eq36_vs_eq35_correlated_part"] = correlated_rel_diff(
-        a36, a35, alpha_uncoupled_ref(inp.fock, inp.mu, inp.o, omegas))
+    out["alpha_max_asymmetry_static"] = (float(np.abs(a35[0] - a35[0].T).max() / np.abs(a35[0]).max())
+                                         if omegas[0] == 0.0 else None)
+    if a36 is not None:
+        out["alpha_rel_diff_eq36_vs_eq35"] = float(np.abs(a36 - a35).max() / np.abs(a35).max())
+        out["alpha_rel_diff_eq36_vs_eq35_correlated_part"] = correlated_rel_diff(
+            a36, a35, alpha_uncoupled_ref(inp.fock, inp.mu, inp.o, omegas))
     out["seconds"] = time.perf_counter() - t0
-    print(f"[bench] c5 solve: {out['seconds']:.1f} s, eq36 vs eq35 {out['alpha_rel_diff_eq36_vs_eq35']:.1e}",
+    print(f"[bench] c5 solve: {out['seconds']:.1f} s, eq36 vs eq35 {out.get('alpha_rel_diff_eq36_vs_eq35')}",
           file=sys.stderr, flush=True)
     return out, a35
 
@@ -612,6 +618,9 @@ def main():
     ap.add_argument("--c4-check", action="store_true",
                     help="only the o=30, v=300 check: mixed solves of all 3 x 32 right-hand sides by Eq. 35 and "
                          "Eq. 36, and plain FP64 solves on 4 of the 32 frequencies for comparison")
+    ap.add_argument("--solve-omegas", type=int, default=1,
+                    help="c5 solve on this many frequencies of the grid (more than 1: alpha per frequency, "
+                         "only the last frequency's X and Y kept)")
     ap.add_argument("--fnspp-scale", action="store_true",
                     help="FNS++ from 1300 virtuals to 400 at o=40, then the static solve in the kept space")
     ap.add_argument("--solve-fp64", action="store_true",
@@ -857,7 +866,13 @@ def main_c5(args):
         print(f"[bench] c5 checks: mixed vs FP64 {mvf:.2e}, adjoint identity {fp['adjoint_identity_rel']:.2e}",
               file=sys.stderr, flush=True)
         assert mvf < 2e-5 and fp["adjoint_identity_rel"] < 1e-10, "products at full size fail their checks"
-    if not args.no_solve:
+    if args.solve_omegas > 1:  # a grid of frequencies, alpha per frequency group
+        idx = np.linspace(0, len(cfg["omegas"]) - 1, args.solve_omegas).round().astype(int)
+        grid = [float(cfg["omegas"][k]) for k in idx]
+        out["c5_solve_grid"], _ = solve_leg(lrcc, inp, dev_in, grid, tol=args.tol, keep_response=False, eq36=False)
+        out["c5_solve_grid"]["subset"] = (f"3 dipole directions x {len(grid)} of the 64 frequencies {grid}; T, "
+                                          "Lambda, then X, Y and alpha (Eq. 35) one frequency at a time")
+    elif not args.no_solve:
         out["c5_solve"], a35 = solve_leg(lrcc, inp, dev_in, [args.solve_omega], tol=args.tol)
         sv = out["c5_solve"]
         if args.solve_fp64:

@@ -74,7 +74,8 @@ def test_argument_checks_come_before_any_device_work():
     assert lib.lrcc_gemm(lrcc.FP64, 0, 0, 4, 4, 4, one, None, 4, dummy, 4, one, dummy, 4, None) == lrcc.E_INVALID
     assert lib.lrcc_gemm_set_tile(5) == lrcc.E_INVALID and lib.lrcc_gemm_set_tile(-2) == lrcc.E_INVALID
     for field, bad in (("precision", 5), ("ladder_mode", 3), ("tol_residual", 0.0), ("maxit", 0),
-                       ("diis_size", 33), ("rhs_chunk", -1)):
+                       ("diis_size", 33), ("rhs_chunk", -1), ("ladder_mode_fp64", 3), ("memory_mode", 3),
+                       ("ring_factored", 2), ("keep_response", 2)):
         c = lrcc.Config()
         lib.lrcc_default_config(ctypes.byref(c))
         setattr(c, field, bad)
