@@ -136,7 +136,7 @@ LADDER_FULL, LADDER_DIRECT, LADDER_TRIANGLE = 0, 1, 2
 
 
 def workspace_bytes(o, v, naux, nrhs, precision="fp64", diis=8, ladder="full", ladder_fp64=None, memory="auto",
-                    ring_factored=None, keep_response=True):
+                    ring_factored=None):
     """Device bytes of the whole pipeline with batches of up to nrhs
     right-hand sides (lrcc_workspace_bytes)."""
     cfg = Config()
@@ -202,7 +202,7 @@ class Context:
 
     def __init__(self, device=0, stream=None, precision="fp64", tol=1e-10, maxit=100, diis=8, rhs_chunk=0,
                  verbose=0, autotune=True, graphs=None, ladder="full", ladder_fp64=None, memory="auto",
-                 ring_factored=None):
+                 ring_factored=None, keep_response=True):
         cfg = Config()
         lib.lrcc_default_config(ctypes.byref(cfg))
         cfg.device = device
