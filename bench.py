@@ -832,7 +832,8 @@ def main_c5(args):
     out = {
         "metric": METRIC, "value": value, "unit": "sigma evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * sig["seconds"] / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 products (3M on FP32 MFMA) + c128 diagonal",
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "dtype_detail": "complex FP32 products (3M on FP32 MFMA, FP32 accumulation) + complex FP64 diagonal",
         "data": "synthetic",
         "config": {"workload": f"c5: o={cfg['o']} v={cfg['v']} naux={cfg['naux']} (O={po}, V={pv} packed pairs; "
                                f"W {pv * pv * 8 / 1e9:.1f} GB FP32 in HBM), batched mixed-precision right Jacobian "
@@ -1002,7 +1003,8 @@ def main_full_pass(args):
     out = {
         "metric": METRIC, "value": value, "unit": "sigma evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 products (3M, FP32 MFMA) + c128 residuals", "data": "synthetic",
+        "vs_baseline": None, "dtype": "c64",
+        "dtype_detail": "complex FP32 products (3M, FP32 MFMA) + complex FP64 residuals", "data": "synthetic",
         "config": {"workload": f"{args.workload}: o={cfg['o']} v={cfg['v']} naux={cfg['naux']}, 3 dipole directions "
                                f"x {len(cfg['omegas'])} omegas in [{min(cfg['omegas']):.2f},{max(cfg['omegas']):.2f}] Ha, "
                                "full pass (integrals, T, Lambda, X, Y, alpha)",
