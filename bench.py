@@ -571,6 +571,8 @@ def solve_leg(lrcc, inp, dev_in, omegas, tol=1e-6, keep_response=True, eq36=True
     torch.cuda.empty_cache()
     out["alpha_iso"] = [float(x) for x in np.real(np.trace(a35, axis1=-2, axis2=-1)) / 3.0]
     out["alpha"] = [[[complex(z).real, complex(z).imag] for z in row] for row in np.asarray(a35[0])]
+    if len(omegas) > 1:
+        out["alpha_all"] = [[[[complex(z).real, complex(z).imag] for z in row] for row in ak] for ak in np.asarray(a35)]
     out["alpha_max_asymmetry_static"] = (float(np.abs(a35[0] - a35[0].T).max() / np.abs(a35[0]).max())
                                          if omegas[0] == 0.0 else None)
     if a36 is not None:
@@ -621,6 +623,8 @@ def main():
     ap.add_argument("--solve-omegas", type=int, default=1,
                     help="c5 solve on this many frequencies of the grid (more than 1: alpha per frequency, "
                          "only the last frequency's X and Y kept)")
+    ap.add_argument("--solve-range", default="",
+                    help="c5 solve on the frequencies lo:hi of the 64-point grid (alpha per frequency)")
     ap.add_argument("--fnspp-scale", action="store_true",
                     help="FNS++ from 1300 virtuals to 400 at o=40, then the static solve in the kept space")
     ap.add_argument("--solve-fp64", action="store_true",
@@ -867,8 +871,12 @@ def main_c5(args):
         print(f"[bench] c5 checks: mixed vs FP64 {mvf:.2e}, adjoint identity {fp['adjoint_identity_rel']:.2e}",
               file=sys.stderr, flush=True)
         assert mvf < 2e-5 and fp["adjoint_identity_rel"] < 1e-10, "products at full size fail their checks"
-    if args.solve_omegas > 1:  # a grid of frequencies, alpha per frequency group
-        idx = np.linspace(0, len(cfg["omegas"]) - 1, args.solve_omegas).round().astype(int)
+    if args.solve_omegas > 1 or args.solve_range:  # a grid of frequencies, alpha per frequency group
+        if args.solve_range:
+            lo, hi = (int(x) for x in args.solve_range.split(":"))
+            idx = np.arange(lo, hi)
+        else:
+            idx = np.linspace(0, len(cfg["omegas"]) - 1, args.solve_omegas).round().astype(int)
         grid = [float(cfg["omegas"][k]) for k in idx]
         out["c5_solve_grid"], _ = solve_leg(lrcc, inp, dev_in, grid, tol=args.tol, keep_response=False, eq36=False)
         out["c5_solve_grid"]["subset"] = (f"3 dipole directions x {len(grid)} of the 64 frequencies {grid}; T, "
