@@ -65,7 +65,10 @@ static void arena_checks() {
 static void program_checks() {
   CcPrograms P;
   build_programs(P);
-  const OpList* lists[] = {&P.residual, &P.right, &P.left, &P.eta0, &P.xi, &P.gradL, &P.hvp, &P.hvpt, &P.fnspp};
+  const OpList* lists[] = {&P.residual, &P.right, &P.left, &P.eta0,       &P.xi,      &P.gradL,
+                           &P.hvp,      &P.hvpt,  &P.fnspp, &P.ring_setup, &P.right_f, &P.left_f};
+  CHECK(P.m.forward.empty());
+  CHECK(P.right_f.size() < P.right.size() && P.left_f.size() < P.left.size());
   for (const OpList* l : lists) {
     CHECK(!l->empty());
     CHECK(!serialize(P.m, *l).empty() && !dump(P.m, *l).empty());
@@ -90,6 +93,48 @@ static void program_checks() {
   OpList vp = vjp(m, prog, adj, {m.find("x")}, true);
   CHECK(vp.size() == 2);
   CHECK(prune(m, vp, {adj.at(m.find("x"))}).size() == 2);
+  // via terms: y = a . w(u) with w = u . g; the first derivatives through w
+  // take du . Z (Z formed by a later program) instead of forming dw
+  {
+    Module mv;
+    OpList pv = parse_program(mv, "input a[ik] u[kl]\nconst g[lj]\nw[kj] = u[kl] * g[lj]\n"
+                                  "y[ij] = a[ik] * w[kj] | u[kl] * Z[iklj]\n");
+    CHECK(mv.forward.size() == 1);
+    OpList setup = parse_program(mv, "Z[iklj] = a[ik] * g[lj]\n");
+    CHECK(setup.size() == 1 && mv.forward.empty());
+    const int u = mv.find("u"), y = mv.find("y"), z = mv.find("Z");
+    for (bool via : {false, true}) {
+      std::map<int, int> tn{{u, mv.add(via ? "du1" : "du0", "oo", Role::Tangent, true)}};
+      OpList d = prune(mv, jvp(mv, pv, tn, {y}, via ? "T1" : "T0", via), {tn.at(y)});
+      CHECK(d.size() == (via ? 1u : 2u));
+      if (via) CHECK(d[0].b == z && d[0].a == tn.at(u) && d[0].via.empty());
+      std::map<int, int> an{{y, mv.add(via ? "gy1" : "gy0", "oo", Role::Adjoint, true)}};
+      OpList g = prune(mv, vjp(mv, pv, an, {u}, true, via ? "A1" : "A0", via), {an.at(u)});
+      CHECK(g.size() == (via ? 1u : 2u));
+      if (via) CHECK(g[0].a == z && g[0].b == an.at(y));
+    }
+    const char* badv[] = {"input x[ia]\ny[ia] = 2 * x[ia] | x[ia] * Z[ia]\n",
+                          "input a[ik] u[kl]\nconst g[kj]\ny[ij] = a[ik] * g[kj] | u[kl] * Z[kl]\n"};
+    for (const char* t : badv) {
+      Module mb;
+      bool threw = false;
+      try {
+        parse_program(mb, t);
+      } catch (const Error&) {
+        threw = true;
+      }
+      CHECK(threw);
+    }
+    Module mf;
+    parse_program(mf, "input a[ik] u[kl]\nconst g[kj]\ny[ij] = a[ik] * g[kj] | u[kl] * Z[iklj]\n");
+    bool threw = false;
+    try {
+      parse_program(mf, "Z[iklj] += a[ik] * u[kl]\n");  // a forward-declared tensor's first write is '='
+    } catch (const Error&) {
+      threw = true;
+    }
+    CHECK(threw);
+  }
   // malformed programs fail with an error, not a crash
   const char* bad[] = {"y[ia] = q[ia]\n", "input x[ia]\ny[ia] += x[ia]\n", "input x[ia]\ny[ab] = x[ia]\n",
                        "input x[ia]\ny[ia] = x[ia] *\n", "input x[ia]\ny[ia] = unpack(x[ia], 7)\n",
