@@ -424,9 +424,12 @@ def cpu_baseline(inp, budget_s=25.0):
                       f"integral build excluded ({dt:.1f} s)"}
 
 
-def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0, ring=None, keep=True):
+def _c5_context(lrcc, inp, dev_in, precision, ladder, ladder_fp64=None, tol=1e-6, chunk=0, ring=None, keep=True,
+                verbose=None):
+    if verbose is None:  # long solves print their progress
+        verbose = 1 if not keep else 0
     c = lrcc.Context(precision=precision, tol=tol, ladder=ladder, ladder_fp64=ladder_fp64, memory="lean",
-                     rhs_chunk=chunk, ring_factored=ring, keep_response=keep, verbose=1 if not keep else 0)
+                     rhs_chunk=chunk, ring_factored=ring, keep_response=keep, verbose=verbose)
     c.load_df(inp.o, inp.v, dev_in["B"])
     c.load_fock(dev_in["fock"])
     c.load_dipoles(dev_in["mu"])
@@ -886,7 +889,7 @@ def main_c5(args):
         sv = out["c5_solve"]
         if args.solve_fp64:
             t = time.perf_counter()
-            c = _c5_context(lrcc, inp, dev_in, "fp64", "full", tol=args.tol64, chunk=1)
+            c = _c5_context(lrcc, inp, dev_in, "fp64", "full", tol=args.tol64, chunk=1, verbose=2)
             c.solve_ground()
             c.solve_lambda()
             c.solve_response([args.solve_omega])
