@@ -329,3 +329,26 @@ def test_bench_uncoupled_alpha_matches_oracle():
     for k, w in enumerate((0.0, 0.13)):
         ref = alpha_uncoupled(inp.fock, inp.mu, inp.o, w)
         assert np.abs(got[k] - ref).max() < 1e-14 * np.abs(ref).max()
+
+
+def test_bench_refuses_more_than_one_gpu_and_reads_traffic_by_tile():
+    """bench.py runs on one GPU only: --gpus 2 exits with a message and
+    status 2 before touching a device.  The traffic figure is read from the
+    committed counter summary only for the tile it was measured on."""
+    import importlib.util
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.join(os.path.dirname(__file__), "..")
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t = bench.measured_traffic("c5", 3)
+    assert t is not None and t["tile"] == "128x128x8w" and t["bytes_per_launch"] > 5e11
+    assert bench.measured_traffic("c5", 0) is None  # not measured on the 64 x 64 tile
+    assert bench.measured_traffic("c1", 3) is None
