@@ -240,7 +240,9 @@ int lrcc_sigma(lrcc_ctx *ctx, int side, int nvec, const double *shifts, const vo
 
 /* Length n = nocc*nvir + O*V of one amplitude vector (0 before load_df). */
 int64_t lrcc_amplitude_length(const lrcc_ctx *ctx);
-/* Checkpoint / resume of T, Lambda, X or Y (idx = k*ncomp + B for X, Y). */
+/* Checkpoint / resume of T, Lambda, X or Y (idx = k*ncomp + B for X, Y).
+   With lrcc_config.keep_response = 0 only the last frequency group's X and Y
+   are kept; other idx give LRCC_E_STATE. */
 int lrcc_get_amplitudes(lrcc_ctx *ctx, int which, int idx, void *out, int where);
 int lrcc_set_amplitudes(lrcc_ctx *ctx, int which, int idx, const void *in, int where);
 
